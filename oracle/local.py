@@ -1,0 +1,141 @@
+"""Operators evaluated at a sample of sites (oracle; test infrastructure only).
+
+The operators are local: out(x) needs the links at x (and at the backward
+neighbours) and psi on the 3^4 hypercube around x.  These functions compute
+out(x) for a list of coordinates only, by explicit neighbour gathers, so a
+lattice whose full FP64 application would not fit the host (e.g. D_B on 32^4
+at N_v = 12) can still be checked at sampled sites.  They use the hop forms:
+
+* D_S: m psi(x) + sum_mu eta_mu(x)/2 [V_mu(x) psi(x+mu) - V_mu(x-mu)^dag psi(x-mu)]
+  (Sec. 3);
+* D_W: (4 + m0) psi(x) - 1/2 sum_mu [(1 - gamma_mu) V_mu(x) psi(x+mu)
+  + (1 + gamma_mu) V_mu(x-mu)^dag psi(x-mu)] (eq. def_wils, c_SW = 0);
+* D_B: (m0 - lambda_0/2) psi(x) + sum_{d != 0} [-lambda_k/2 + rho_k d.gamma]
+  W_d(x) psi(x+d) (eqs. def_bril, def_der, def_lap) with every W_d(x) built
+  from V by the path average of Tab. 1 at the sampled site itself.
+
+``coords`` is an integer array of shape (n, 4) holding (x, y, z, t).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+from .gamma import GAMMA, IDENTITY
+
+_RHO = (None, 64 / 432, 16 / 432, 4 / 432, 1 / 432)
+_LAMBDA = (-240 / 64, 8 / 64, 4 / 64, 2 / 64, 1 / 64)
+
+
+def sample_sites(dims, count: int, seed: int) -> np.ndarray:
+    """``count`` distinct random coordinates plus the 16 corners of the lattice
+    (which exercise every periodic wrap)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    total = int(np.prod(dims))
+    idx = g.choice(total, size=min(count, total), replace=False)
+    nx, ny, nz, _ = dims
+    c = np.stack([idx % nx, (idx // nx) % ny, (idx // (nx * ny)) % nz, idx // (nx * ny * nz)], axis=1)
+    corners = np.array([[a * (dims[0] - 1), b * (dims[1] - 1), cc * (dims[2] - 1), d * (dims[3] - 1)]
+                        for a, b, cc, d in itertools.product((0, 1), repeat=4)])
+    return np.unique(np.concatenate([c, corners]), axis=0)
+
+
+def _dims(field) -> tuple:
+    nt, nz, ny, nx = field.shape[:4]
+    return (nx, ny, nz, nt)
+
+
+def _at(field: np.ndarray, coords: np.ndarray, d=(0, 0, 0, 0)) -> np.ndarray:
+    """field(x + d) for every x in coords."""
+    dims = _dims(field)
+    c = (coords + np.asarray(d)[None, :]) % np.asarray(dims)[None, :]
+    return field[c[:, 3], c[:, 2], c[:, 1], c[:, 0]]
+
+
+def _unit(mu: int, s: int = 1):
+    e = [0, 0, 0, 0]
+    e[mu] = s
+    return e
+
+
+def _dag(u):
+    return np.conj(np.swapaxes(u, -1, -2))
+
+
+def staggered_at(V, psi, mass, coords, adjoint=False):
+    out = mass * _at(psi, coords)
+    sgn = -1.0 if adjoint else 1.0
+    for mu in range(4):
+        eta = np.where(coords[:, :mu].sum(axis=1) % 2 == 0, 1.0, -1.0)[:, None, None]
+        fwd = _at(V, coords)[:, mu] @ _at(psi, coords, _unit(mu))
+        bwd = _dag(_at(V, coords, _unit(mu, -1))[:, mu]) @ _at(psi, coords, _unit(mu, -1))
+        out = out + sgn * 0.5 * eta * (fwd - bwd)
+    return out
+
+
+def _spin(g, f):
+    return np.einsum("st,ntcv->nscv", g, f)
+
+
+def wilson_at(V, psi, m0, coords, adjoint=False):
+    sgn = -1.0 if adjoint else 1.0
+    out = (4.0 + m0) * _at(psi, coords)
+    for mu in range(4):
+        fwd = _at(V, coords)[:, mu][:, None] @ _at(psi, coords, _unit(mu))
+        bwd = _dag(_at(V, coords, _unit(mu, -1))[:, mu])[:, None] @ _at(psi, coords, _unit(mu, -1))
+        out = out - 0.5 * _spin(IDENTITY - sgn * GAMMA[mu], fwd) - 0.5 * _spin(IDENTITY + sgn * GAMMA[mu], bwd)
+    return out
+
+
+def path_link_at(V, coords, d) -> np.ndarray:
+    """W_d(x) for x in coords: mean over the k! hop orderings of the path
+    product, V_{-mu}(y) = V_mu(y - mu)^dag (Tab. 1)."""
+    steps = [(mu, s) for mu, s in enumerate(d) if s]
+    nc = V.shape[-1]
+    acc = np.zeros((len(coords), nc, nc), dtype=np.complex128)
+    for order in itertools.permutations(steps):
+        prod = None
+        pos = np.zeros(4, dtype=int)
+        for mu, s in order:
+            if s > 0:
+                link = _at(V, coords, pos)[:, mu]
+            else:
+                link = _dag(_at(V, coords, pos + np.array(_unit(mu, -1)))[:, mu])
+            prod = link if prod is None else prod @ link
+            pos = pos + np.array(_unit(mu, s))
+        acc += prod
+    return acc / math.factorial(len(steps))
+
+
+def brillouin_at(V, psi, m0, coords, adjoint=False):
+    sgn = -1.0 if adjoint else 1.0
+    out = (m0 - 0.5 * _LAMBDA[0]) * _at(psi, coords)
+    for d in itertools.product((-1, 0, 1), repeat=4):
+        k = sum(1 for s in d if s)
+        if k == 0:
+            continue
+        spin = -0.5 * _LAMBDA[k] * IDENTITY + sgn * _RHO[k] * sum(d[mu] * GAMMA[mu] for mu in range(4))
+        w = path_link_at(V, coords, d)
+        out = out + _spin(spin, w[:, None] @ _at(psi, coords, d))
+    return out
+
+
+def link_grad_at(op: str, chi, psi, coords, mu: int) -> np.ndarray:
+    """G_mu(x) for x in coords (see ``oracle.grad`` for the formula)."""
+    e = _unit(mu)
+    if op == "staggered":
+        eta_x = np.where(coords[:, :mu].sum(axis=1) % 2 == 0, 1.0, -1.0)[:, None, None]
+        cf = (coords + np.array(e)) % np.asarray(_dims(psi))
+        eta_f = np.where(cf[:, :mu].sum(axis=1) % 2 == 0, 1.0, -1.0)[:, None, None]
+        t1 = 0.5 * eta_x * (_at(chi, coords) @ _dag(_at(psi, coords, e)))
+        t2 = -0.5 * eta_f * (_at(psi, coords) @ _dag(_at(chi, coords, e)))
+        return t1 + t2
+    if op == "wilson":
+        phi_f = _spin(-0.5 * (IDENTITY - GAMMA[mu]), _at(psi, coords, e))
+        phi_b = _spin(-0.5 * (IDENTITY + GAMMA[mu]), _at(psi, coords))
+        t1 = np.einsum("nsav,nsbv->nab", _at(chi, coords), np.conj(phi_f))
+        t2 = np.einsum("nsav,nsbv->nab", phi_b, np.conj(_at(chi, coords, e)))
+        return t1 + t2
+    raise ValueError(op)
