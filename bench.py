@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Benchmark of the Dirac matrix times a block of N_v vectors on one MI355X.
+
+Headline (one JSON line on stdout): Wilson D_W at c_SW = 0 on a 16^3 x 32
+lattice, N_v = 12 right-hand sides, m0 = 0.1, FP32, exp(0.3 i H) links --
+Gflop/s at the standard 1320 flops per site and right-hand side, and the
+kernel's share of the HBM bandwidth roofline.  A step is one application of
+D_W to the 12-vector block (site indexing, 8 hops with spin projection,
+single write of every output).  Inputs are resident in HBM before timing;
+R rotating (U, in, out) sets (default 4, about 1.4 GB) keep the working set
+well above the 256 MB Infinity Cache.
+
+Further rows (``rows`` in the JSON line), each timed the same way:
+D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
+BF16 storage, link gradients at 24^3 x 48, and the mixed-precision solve at
+32^3 x 64 (time to ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16
+inner storage).
+
+cpu_baseline: the FP64 numpy oracle applying the same operator on the host
+cores (BLAS pinned to one thread), on the full headline workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK = 78.6e12       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+FP64_VALU_PEAK = 78.6e12
+FLOPS = {"staggered": 570, "wilson": 1320, "brillouin": 28224}   # per site and right-hand side
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def site_bytes(op: str, nv: int, eb: int) -> int:
+    """Compulsory bytes per site: links read once, input read once, output written once."""
+    links = {"staggered": 36, "wilson": 36, "brillouin": 360}[op]
+    comps = 3 if op == "staggered" else 12
+    return eb * (links + 2 * comps * nv)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dslash_common.hpp", "stencils.hpp", "apply.hip"):
+        with open(os.path.join(ROOT, "paper_1808_05506_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(name)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def timed(torch, launch, steps: int, warmup: int) -> float:
+    """Mean seconds per launch over ``steps`` launches on the current stream."""
+    for i in range(warmup):
+        launch(i)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(steps):
+        launch(i)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def rotated_sets(torch, U, P, count: int):
+    """``count`` distinct input sets: lattice translations of (U, P) along t."""
+    sets = [(U, P)]
+    for k in range(1, count):
+        sets.append((torch.roll(U, shifts=k, dims=0).contiguous(), torch.roll(P, shifts=k, dims=0).contiguous()))
+    return sets
+
+
+def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label):
+    sets = rotated_sets(torch, U, P, rotate)
+    outs = [torch.empty_like(P) for _ in sets]
+    launch = lambda i: D.apply(op, sets[i % len(sets)][0], sets[i % len(sets)][1], mass, out=outs[i % len(sets)])
+    t = timed(torch, launch, steps, warmup)
+    nt, nz, ny, nx = P.shape[:4]
+    vol = nt * nz * ny * nx
+    nv = P.shape[-1] if P.dtype in (torch.complex64, torch.complex128) else P.shape[-2]
+    flops = FLOPS[op] * vol * nv
+    nbytes = site_bytes(op, nv, dtype_bytes) * vol
+    row = {"us": t * 1e6, "gflops": flops / t / 1e9, "gbs": nbytes / t / 1e9,
+           "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": flops,
+           "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
+    log(f"{label}: {t * 1e6:.1f} us  {row['gflops']:.0f} Gflop/s  {row['gbs']:.0f} GB/s")
+    return row, t
+
+
+def cpu_baseline(dims, nv, m0, min_seconds: float = 10.0):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synthetic
+    from oracle import wilson
+    u = synthetic.round_to(synthetic.gauge_links(dims, "smooth", 1), "c64")
+    p = synthetic.round_to(synthetic.wilson_spinor(dims, nv, 101), "c64")
+    vol = int(np.prod(dims))
+    reps, t_total = 0, 0.0
+    with threadpool_limits(limits=1):
+        while t_total < min_seconds and reps < 5:
+            t0 = time.perf_counter()
+            wilson.apply(u, p, m0)
+            t_total += time.perf_counter() - t0
+            reps += 1
+    gflops = FLOPS["wilson"] * vol * nv * reps / t_total / 1e9
+    return {"value": gflops, "unit": "Gflop/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full FP64 numpy applications of D_W (eq. def_wils, literal form) to the same "
+                      f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} N_v={nv} workload, {t_total:.1f} s, BLAS pinned to 1 thread",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def rows_bench(torch, D, np, synthetic, steps, warmup):
+    rows = {}
+    dev = torch.device("cuda:0")
+
+    def up(a, dt):
+        return torch.from_numpy(a.astype(dt)).to(dev)
+
+    # D_S 8^4, N_v = 4 (cache-resident, launch-bound)
+    u = synthetic.gauge_links((8, 8, 8, 8), "haar", 0)
+    p = synthetic.staggered_spinor((8, 8, 8, 8), 4, 100)
+    rows["staggered_8^4_nv4_fp32"], _ = bench_apply(torch, D, "staggered", up(u, np.complex64), up(p, np.complex64),
+                                                    0.0, steps, warmup, 1, 8, "D_S 8^4 nv4")
+    # D_S 32^4, N_v = 12
+    dims = (32, 32, 32, 32)
+    U = up(synthetic.gauge_links(dims, "haar", 0), np.complex64)
+    P = up(synthetic.staggered_spinor(dims, 12, 100), np.complex64)
+    rows["staggered_32^4_nv12_fp32"], _ = bench_apply(torch, D, "staggered", U, P, 0.0, steps, warmup, 1, 8,
+                                                      "D_S 32^4 nv12")
+    del U, P
+    # D_B 32^4, N_v = 12, FP32 and FP64 (W built on the GPU, untimed setup)
+    v = synthetic.gauge_links(dims, "haar", 2)
+    p = synthetic.wilson_spinor(dims, 12, 102)
+    for name, cdt, eb, peak in (("fp32", np.complex64, 8, FP32_VALU_PEAK), ("fp64", np.complex128, 16, FP64_VALU_PEAK)):
+        V = up(v, cdt)
+        t0 = time.perf_counter()
+        W = D.brillouin_links(V)
+        torch.cuda.synchronize()
+        tw = time.perf_counter() - t0
+        del V
+        P = up(p, cdt)
+        row, t = bench_apply(torch, D, "brillouin", W, P, 0.1, max(3, steps // 10), 2, 1, eb, f"D_B 32^4 {name}")
+        row["valu_frac"] = row["flops_per_launch"] / t / peak
+        row["valu_peak_tflops"] = peak / 1e12
+        row["w_build_ms"] = tw * 1e3
+        rows[f"brillouin_32^4_nv12_{name}"] = row
+        del W, P
+        torch.cuda.empty_cache()
+    # D_W with BF16 storage (FP32 arithmetic) on the headline workload
+    dims = (16, 16, 16, 32)
+    u = synthetic.gauge_links(dims, "smooth", 1)
+    p = synthetic.wilson_spinor(dims, 12, 101)
+    Ub = D.convert(up(u, np.complex64), "bf16")
+    Pb = D.convert(up(p, np.complex64), "bf16")
+    rows["wilson_16^3x32_nv12_bf16"], _ = bench_apply(torch, D, "wilson", Ub, Pb, 0.1, steps, warmup, 4, 4,
+                                                      "D_W bf16")
+    # link gradients at 24^3 x 48, N_v = 12
+    dims = (24, 24, 24, 48)
+    for op, kind, seed in (("staggered", "haar", 4), ("wilson", "smooth", 5)):
+        gen = synthetic.staggered_spinor if op == "staggered" else synthetic.wilson_spinor
+        U = up(synthetic.gauge_links(dims, kind, seed), np.complex64)
+        C = up(gen(dims, 12, 104), np.complex64)
+        P = up(gen(dims, 12, 105), np.complex64)
+        gU = torch.empty_like(U)
+        import ctypes
+        lib = D._lib
+        dims_c = (ctypes.c_int * 4)(*dims)
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        code = D.op_code(op)
+
+        def launch(i):
+            rc = lib.dslash_backward(code, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                     ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(gU.data_ptr()), None, dims_c, 3,
+                                     12, 0.0, 0, stream)
+            if rc:
+                raise RuntimeError(f"dslash_backward failed: {rc}")
+        t = timed(torch, launch, steps, warmup)
+        vol = int(np.prod(dims))
+        nbytes = site_bytes(op, 12, 8) * vol
+        rows[f"link_grad_{op}_24^3x48_nv12_fp32"] = {"us": t * 1e6, "gbs": nbytes / t / 1e9,
+                                                     "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+                                                     "bytes_per_launch": nbytes}
+        log(f"link grad {op}: {t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
+        del U, C, P, gU
+    torch.cuda.empty_cache()
+    # mixed-precision solve, 32^3 x 64, N_v = 12, m0 = 0.05, smooth links
+    dims = (32, 32, 32, 64)
+    U = up(synthetic.gauge_links(dims, "smooth", 3), np.complex128)
+    B = up(synthetic.wilson_spinor(dims, 12, 103), np.complex128)
+    solve = {}
+    for inner, itol in (("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = D.solve("wilson", U, B, 0.05, inner=inner, tol=1e-10, inner_tol=itol)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        solve[inner] = {"seconds": t, "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
+                        "max_relres": max(info["relres"]), "status": info["status"], "inner_tol": itol}
+        log(f"solve inner={inner}: {t:.2f} s, {info['inner_iters']} inner / {info['outer_iters']} outer, "
+            f"max relres {max(info['relres']):.2e}")
+        del x
+    base = solve["c64"]["seconds"]
+    for k in ("bf16", "f16"):
+        solve[k]["speedup_vs_fp32_inner"] = base / solve[k]["seconds"]
+    rows["solve_wilson_32^3x64_nv12"] = solve
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--rotate", type=int, default=4)
+    ap.add_argument("--rows", choices=["all", "none"], default="all")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_1808_05506_amd import dslash as D
+
+    dims, nv, m0 = (16, 16, 16, 32), 12, 0.1
+    dev = torch.device("cuda:0")
+    log(f"device: {torch.cuda.get_device_name(0)}")
+    u = synthetic.gauge_links(dims, "smooth", 1)
+    p = synthetic.wilson_spinor(dims, nv, 101)
+    U = torch.from_numpy(u.astype(np.complex64)).to(dev)
+    P = torch.from_numpy(p.astype(np.complex64)).to(dev)
+    row, t = bench_apply(torch, D, "wilson", U, P, m0, args.steps, args.warmup, args.rotate, 8, "D_W 16^3x32 nv12 fp32")
+    del U, P
+    torch.cuda.empty_cache()
+
+    traffic = measured_traffic("wilson_16^3x32_nv12_fp32")
+    roofline = {"bound": "hbm", "achieved": row["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": row["gbs"] / HBM_PEAK_GBS, "traffic": traffic}
+
+    rows = {}
+    if args.rows == "all":
+        rows = rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
+
+    cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
+
+    out = {
+        "metric": "Dslash Gflop/s + % HBM roofline (N_v=12, FP32); mixed-prec solve speedup",
+        "value": row["gflops"],
+        "unit": "Gflop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wilson_dslash_16^3x32_nv12_fp32", "op": "wilson", "dims": list(dims), "nv": nv,
+                   "m0": m0, "c_sw": 0, "links": "exp(0.3 i H), seed 1", "rhs": "CN(0,1), seed 101",
+                   "flops_per_site_rhs": 1320, "bytes_per_site": site_bytes("wilson", nv, 8),
+                   "rotating_sets": args.rotate},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * dslash.h -- C ABI of the MI355X (gfx950) Dirac-operator library.
+ *
+ * The library applies three lattice Dirac operators to a block of N_v
+ * right-hand-side vectors, following S. Duerr, "Three Dirac operators on two
+ * architectures with one piece of code and no hassle" (LATTICE 2018):
+ *
+ *   STAGGERED  D_S  (Sec. 3, the D_S equation; eta phases, precomputed links V)
+ *   WILSON     D_W  (Sec. 4, eq. def_wils at c_SW = 0)
+ *   BRILLOUIN  D_B  (Sec. 5, eqs. def_bril, def_der, def_lap at c_SW = 0, with
+ *                    the precomputed off-axis links W of Tab. 1)
+ *
+ * plus the adjoint operators, the link gradient (backward pass) of
+ * L = Re sum chi^dag D psi, the construction of W from V, and a
+ * mixed-precision solver for D x = b.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * dims      {Nx, Ny, Nz, Nt}, the paper's index order (Sec. 2).  Periodic
+ *           boundaries in all four directions.  Site index
+ *           s = x + Nx*(y + Ny*(z + Nz*t)), 0-based coordinates.
+ * Nc        number of colours; only 3 is built.
+ * Nv        number of right-hand sides, >= 1.
+ * dtype     storage of every field argument of the call:
+ *             DSLASH_C64  complex float  (re, im) interleaved, FP32 arithmetic
+ *             DSLASH_C128 complex double (re, im) interleaved, FP64 arithmetic
+ *             DSLASH_BF16 bfloat16 pairs (re, im), FP32 arithmetic
+ *             DSLASH_F16  IEEE half pairs (re, im), FP32 arithmetic
+ *           Low-precision stores round to nearest even.
+ * Layouts   (C order, site index slowest, as the paper's Fortran arrays with
+ *           the space-time index right-most, Sec. 2):
+ *             links V     [Nt][Nz][Ny][Nx][4][Nc][Nc], element [..][mu][a][b]
+ *                         = (V_mu(x))_{ab}, mu = 0..3 for x, y, z, t
+ *             off-axis W  [Nt][Nz][Ny][Nx][40][Nc][Nc] (Tab. 1 caption); the
+ *                         direction d in {-1,0,1}^4 with highest-index non-zero
+ *                         component +1 sits in slot n(d) - 41,
+ *                         n(d) = sum_mu (d_mu + 1) 3^mu; the other 40 follow
+ *                         from W_{-d}(x) = W_d(x-d)^dag
+ *             Wilson and Brillouin spinor block  [Nt][Nz][Ny][Nx][4][Nc][Nv]
+ *             staggered spinor block             [Nt][Nz][Ny][Nx][Nc][Nv]
+ *           (the paper's vec(Nv,Nc,4,...) and suv(Nv,Nc,...) options).
+ * gamma     Euclidean chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]
+ *           (k = 1,2,3), gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1,1,-1,-1).
+ * Pointers  all field pointers are DEVICE pointers owned by the caller; the
+ *           library allocates nothing in apply / adjoint / backward / links.
+ *           Outputs are overwritten, never accumulated into.
+ * stream    a hipStream_t passed as void* (NULL = the default stream).  Every
+ *           call except dslash_solve is asynchronous on it.
+ * Errors    return codes, never exceptions or aborts.  Arguments are checked
+ *           synchronously before any launch; a failed call launches nothing.
+ *           dslash_last_error() gives a thread-local detail string.
+ */
+#ifndef DSLASH_H
+#define DSLASH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSLASH_OK = 0,
+  DSLASH_E_ARG = 1,          /* null pointer, bad dims / Nv / op / dtype        */
+  DSLASH_E_UNSUPPORTED = 2,  /* Nc != 3, or an op/dtype pair that is not built  */
+  DSLASH_E_ALIAS = 3,        /* an output aliases an input                      */
+  DSLASH_E_HIP = 4,          /* a HIP runtime call or launch failed             */
+  DSLASH_E_NOCONV = 5,       /* solver hit its iteration limit                  */
+  DSLASH_E_WORKSPACE = 6     /* solver workspace null or too small              */
+} dslash_status;
+
+typedef enum { DSLASH_STAGGERED = 0, DSLASH_WILSON = 1, DSLASH_BRILLOUIN = 2 } dslash_op;
+
+typedef enum { DSLASH_C64 = 0, DSLASH_C128 = 1, DSLASH_BF16 = 2, DSLASH_F16 = 3 } dslash_dtype;
+
+/*
+ * out = D in.
+ *   STAGGERED (Sec. 3):  out(x) = m in(x) + sum_mu eta_mu(x)/2 [V_mu(x) in(x+mu)
+ *                                  - V_mu(x-mu)^dag in(x-mu)],
+ *                        eta_1 = 1, eta_2 = (-1)^x, eta_3 = (-1)^(x+y),
+ *                        eta_4 = (-1)^(x+y+z); mass = m (0 is the paper's
+ *                        operator).  Every extent must be even.
+ *   WILSON (eq. def_wils, c_SW = 0):  D_W = sum gamma_mu nabla^std_mu
+ *                        - Laplace^std / 2 + m0, V_{-mu}(x) = V_mu(x-mu)^dag;
+ *                        mass = m0.  U = V.
+ *   BRILLOUIN (eq. def_bril, c_SW = 0):  D_B = sum gamma_mu nabla^iso_mu
+ *                        - Laplace^bri / 2 + m0 with the 54-point derivative
+ *                        (eq. def_der) and 81-point Laplacian (eq. def_lap);
+ *                        mass = m0.  U = the stored W.
+ * U, in: read only.  out: written once per element.  in == out -> E_ALIAS.
+ * Every extent >= 2 (>= 3 is needed for the Brillouin stencil to be distinct
+ * sites, but 2 is accepted and sums coinciding terms).
+ */
+int dslash_apply(int op, const void* U, const void* in, void* out, const int dims[4], int Nc, int Nv,
+                 double mass, int dtype, void* stream);
+
+/*
+ * out = D^dag in.  STAGGERED: the hop term changes sign (it is
+ * anti-Hermitian; the mass is real).  WILSON, BRILLOUIN: gamma_5 D gamma_5,
+ * i.e. every gamma_mu in the hop terms changes sign.  Same arguments and
+ * errors as dslash_apply.
+ */
+int dslash_apply_adjoint(int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
+                         int Nv, double mass, int dtype, void* stream);
+
+/*
+ * Backward pass of out = D[U] in for a real loss L with grad_out = dL/dout
+ * (PyTorch convention for complex tensors: dL/dRe + i dL/dIm).
+ *   grad_in = D^dag grad_out                                   (nullable)
+ *   grad_U  = G,  G_mu(x) = sum_v sum_s [ g(x)_s (x) conj((P_+ in(x+mu))_s)
+ *                                  + (P_- in(x))_s (x) conj(g(x+mu)_s) ]  (nullable)
+ * with (x) the colour outer product, g = grad_out, and P_+, P_- the spin
+ * factors of the forward and backward hop: eta_mu(x)/2 and -eta_mu(x)/2 for
+ * STAGGERED, -(1 - gamma_mu)/2 and -(1 + gamma_mu)/2 for WILSON.  This is the
+ * link gradient of L = Re sum conj(grad_out) * (D in) with the links treated
+ * as free complex matrices.  grad_U has the layout of V.  BRILLOUIN:
+ * grad_U must be NULL (E_UNSUPPORTED otherwise).  Outputs may not alias
+ * inputs (E_ALIAS).  Only C64 and C128 are accepted.
+ */
+int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U,
+                    void* grad_in, const int dims[4], int Nc, int Nv, double mass, int dtype,
+                    void* stream);
+
+/*
+ * W = off-axis links of V (Tab. 1): for each of the 40 stored directions d
+ * with k non-zero components, W_d(x) = (1/k!) sum over the k! orderings of
+ * the hops of the ordered product of V along the path from x, with
+ * V_{-mu}(y) = V_mu(y - mu)^dag.  V [..][4][Nc][Nc] -> W [..][40][Nc][Nc].
+ * C64 or C128.  V == W -> E_ALIAS.
+ */
+int dslash_brillouin_links(const void* V, void* W, const int dims[4], int Nc, int dtype, void* stream);
+
+/*
+ * Copy n complex numbers from src (src_dtype) to dst (dst_dtype), rounding to
+ * nearest even when narrowing.  Any pair of the four dtypes.  n == 0 is a
+ * no-op.  src == dst -> E_ALIAS.
+ */
+int dslash_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t n, void* stream);
+
+/*
+ * Workspace bytes dslash_solve needs for this problem (0 on bad arguments).
+ */
+size_t dslash_solve_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype);
+
+/*
+ * Solve D x = b for all Nv right-hand sides (the paper has no solver; this is
+ * the mixed-precision scheme of FP64 defect correction around an inner CG on
+ * the normal equations D^dag D e = D^dag r).
+ *   Outer loop, FP64 on the GPU:  r = b - D x, relres_v = ||r_v|| / ||b_v||;
+ *     stop when every relres_v <= tol.
+ *   Inner loop: CG on D^dag D with links and vectors stored in inner_dtype
+ *     (C64, BF16 or F16) and FP32 arithmetic, the right-hand side r scaled
+ *     per column to unit RMS, run to inner_tol (relative, per column) or
+ *     max_inner iterations; then x += scale * e in FP64.
+ *   Inner products and norms are accumulated in FP64 in a fixed order.
+ * op: STAGGERED or WILSON.  U64, b64: C128 device arrays; x64: C128 device
+ * array holding the initial guess on entry and the solution on exit.
+ * workspace: device memory of at least dslash_solve_workspace_bytes bytes.
+ * final_relres (host, Nv doubles, nullable): true FP64 relative residuals.
+ * iters (host, 2 ints, nullable): total inner iterations, outer iterations.
+ * Synchronises the stream.  Returns E_NOCONV (x still updated) if max_outer
+ * outer iterations did not reach tol.
+ */
+int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer,
+                 int max_inner, void* workspace, size_t ws_bytes, double* final_relres, int* iters,
+                 void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* dslash_status_string(int status);
+
+/* Thread-local detail of the last failure in this thread ("" if none). */
+const char* dslash_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int dslash_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSLASH_H */

@@ -139,3 +139,46 @@ def link_grad_at(op: str, chi, psi, coords, mu: int) -> np.ndarray:
         t2 = np.einsum("nsav,nsbv->nab", phi_b, np.conj(_at(chi, coords, e)))
         return t1 + t2
     raise ValueError(op)
+
+
+def loss_at(op: str, V, chi, psi, mass, coords) -> float:
+    """Re sum over the listed sites of conj(chi(x)) * (D psi)(x)."""
+    if op == "staggered":
+        out = staggered_at(V, psi, mass, coords)
+    elif op == "wilson":
+        out = wilson_at(V, psi, mass, coords)
+    else:
+        raise ValueError(op)
+    c = coords
+    return float(np.real(np.vdot(chi[c[:, 3], c[:, 2], c[:, 1], c[:, 0]], out)))
+
+
+def fd_link_grad_local(op: str, V, chi, psi, mass, link, h: float = 1.0) -> complex:
+    """Central difference of L = Re sum_x conj(chi) (D psi) in the real and
+    imaginary part of one link entry ``link = (t, z, y, x, mu, a, b)``.
+
+    Only out(x) and out(x + mu) depend on V_mu(x), so the difference of L
+    equals that of the loss restricted to those two sites; L is affine in the
+    entry, so the difference is exact.  ``V`` is perturbed in place and
+    restored.
+    """
+    t, z, y, x, mu, _, _ = link
+    dims = _dims(V)
+    here = np.array([x, y, z, t])
+    there = here.copy()
+    there[mu] = (there[mu] + 1) % dims[mu]
+    sites = np.stack([here, there])
+    if there[mu] == here[mu]:
+        sites = sites[:1]
+    saved = V[link]
+    parts = []
+    try:
+        for step in (1.0, 1j):
+            V[link] = saved + h * step
+            lp = loss_at(op, V, chi, psi, mass, sites)
+            V[link] = saved - h * step
+            lm = loss_at(op, V, chi, psi, mass, sites)
+            parts.append((lp - lm) / (2 * h))
+    finally:
+        V[link] = saved
+    return parts[0] + 1j * parts[1]

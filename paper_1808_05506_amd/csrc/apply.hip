@@ -1,0 +1,104 @@
+// Dirac-operator application kernels: D_S, D_W, D_B and their adjoints, in
+// every storage type.  One thread per (site, right-hand side); see stencils.hpp.
+#include <stdlib.h>
+
+#include "launch.hpp"
+#include "stencils.hpp"
+
+namespace dsl {
+
+Geom make_geom(const int dims[4], int nv) {
+  Geom g;
+  for (int i = 0; i < 4; ++i) g.n[i] = dims[i];
+  g.stride[0] = 1;
+  g.stride[1] = dims[0];
+  g.stride[2] = dims[0] * dims[1];
+  g.stride[3] = dims[0] * dims[1] * dims[2];
+  g.vol = uint32_t(dims[0]) * dims[1] * dims[2] * dims[3];
+  g.nv = nv;
+  g.dx = FastDiv::make(dims[0]);
+  g.dy = FastDiv::make(dims[1]);
+  g.dz = FastDiv::make(dims[2]);
+  return g;
+}
+
+static int gcd_int(int a, int b) {
+  while (b) {
+    int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Lanes: right-hand sides fastest (blockDim.x = min(nv, 64)), sites along
+// blockDim.y.  The block holds whole waves when lcm(vc, 64) <= 256 and at
+// most 256 threads.  DSLASH_SITES_PER_BLOCK overrides the site count (tuning).
+Shape site_v_shape(uint32_t vol, int nv) {
+  const int vc = nv < 64 ? nv : 64;
+  const int l = vc / gcd_int(vc, 64) * 64;
+  int sb = l <= 256 ? l / vc : (256 / vc > 0 ? 256 / vc : 1);
+  while (vc * sb * 2 <= 256 && l <= 256) sb *= 2;
+  if (const char* e = getenv("DSLASH_SITES_PER_BLOCK")) {
+    int v = atoi(e);
+    if (v > 0 && v * vc <= 256) sb = v;  // kernels are built for at most 256 threads
+  }
+  Shape sh;
+  sh.block = dim3(vc, sb, 1);
+  sh.grid = dim3((vol + sb - 1) / sb, (nv + vc - 1) / vc, 1);
+  return sh;
+}
+
+template <int OP, bool ADJ, class S, class T>
+__global__ void __launch_bounds__(256) apply_kernel(Geom g, const typename S::word* __restrict__ U,
+                                                   const typename S::word* __restrict__ in,
+                                                   typename S::word* __restrict__ out, T mass) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t s = lb * blockDim.y + threadIdx.y;
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+  if (s >= g.vol || v >= g.nv) return;
+  if (OP == OP_STAGGERED)
+    staggered_site<ADJ, S, T>(g, U, in, out, s, v, mass);
+  else if (OP == OP_WILSON)
+    wilson_site<ADJ, S, T>(g, U, in, out, s, v, T(4) + mass);
+  else
+    brillouin_site<ADJ, S, T>(g, U, in, out, s, v, mass + T(15.0 / 8.0));
+}
+
+template <int OP, class S, class T>
+static hipError_t apply_t(bool adj, const Geom& g, const void* U, const void* in, void* out, double mass,
+                          hipStream_t st) {
+  using W = typename S::word;
+  const Shape sh = site_v_shape(g.vol, g.nv);
+  if (adj)
+    hipLaunchKernelGGL((apply_kernel<OP, true, S, T>), sh.grid, sh.block, 0, st, g, (const W*)U, (const W*)in,
+                       (W*)out, T(mass));
+  else
+    hipLaunchKernelGGL((apply_kernel<OP, false, S, T>), sh.grid, sh.block, 0, st, g, (const W*)U, (const W*)in,
+                       (W*)out, T(mass));
+  return hipGetLastError();
+}
+
+template <int OP>
+static hipError_t apply_op(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
+                           double mass, hipStream_t st) {
+  switch (dtype) {
+    case DT_C64: return apply_t<OP, C64, float>(adj, g, U, in, out, mass, st);
+    case DT_C128: return apply_t<OP, C128, double>(adj, g, U, in, out, mass, st);
+    case DT_BF16: return apply_t<OP, BF16, float>(adj, g, U, in, out, mass, st);
+    case DT_F16: return apply_t<OP, F16, float>(adj, g, U, in, out, mass, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
+                        double mass, hipStream_t st) {
+  switch (op) {
+    case OP_STAGGERED: return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, mass, st);
+    case OP_WILSON: return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, mass, st);
+    case OP_BRILLOUIN: return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, mass, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dsl

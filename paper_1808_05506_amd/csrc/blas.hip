@@ -1,0 +1,317 @@
+// Precision conversion and the BLAS-1 kernels of the mixed-precision solver.
+//
+// Fields are [site][comps][nv] complex with the column (right-hand side)
+// index fastest.  Per-column reductions accumulate in FP64: every thread sums
+// its rows in a fixed order, the block reduces through LDS in a fixed tree,
+// and a final kernel sums the kReduceBlocks block partials in index order, so
+// results are bitwise reproducible run to run.
+#include "launch.hpp"
+
+namespace dsl {
+
+template <int DT> struct StorageOf;
+template <> struct StorageOf<DT_C64> { using type = C64; };
+template <> struct StorageOf<DT_C128> { using type = C128; };
+template <> struct StorageOf<DT_BF16> { using type = BF16; };
+template <> struct StorageOf<DT_F16> { using type = F16; };
+
+// ---------------------------------------------------------------- conversion
+template <class SI, class SO, class T>
+__global__ void __launch_bounds__(256) convert_kernel(const typename SI::word* __restrict__ src,
+                                                      typename SO::word* __restrict__ dst, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    SO::template store<T>(dst + i, SI::template load<T>(src + i));
+}
+
+static dim3 stream_grid(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b == 0) b = 1;
+  return dim3(unsigned(b));
+}
+
+template <int DI, int DO>
+static void convert_t(const void* src, void* dst, size_t n, hipStream_t st) {
+  using SI = typename StorageOf<DI>::type;
+  using SO = typename StorageOf<DO>::type;
+  // FP64 arithmetic only when both ends are FP64; a narrowing store from FP64
+  // rounds once, directly from the double value.
+  if (DI == DT_C128 || DO == DT_C128)
+    hipLaunchKernelGGL((convert_kernel<SI, SO, double>), stream_grid(n), dim3(256), 0, st,
+                       (const typename SI::word*)src, (typename SO::word*)dst, n);
+  else
+    hipLaunchKernelGGL((convert_kernel<SI, SO, float>), stream_grid(n), dim3(256), 0, st,
+                       (const typename SI::word*)src, (typename SO::word*)dst, n);
+}
+
+template <int DI>
+static hipError_t convert_from(const void* src, int ddt, void* dst, size_t n, hipStream_t st) {
+  switch (ddt) {
+    case DT_C64: convert_t<DI, DT_C64>(src, dst, n, st); break;
+    case DT_C128: convert_t<DI, DT_C128>(src, dst, n, st); break;
+    case DT_BF16: convert_t<DI, DT_BF16>(src, dst, n, st); break;
+    case DT_F16: convert_t<DI, DT_F16>(src, dst, n, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  switch (sdt) {
+    case DT_C64: return convert_from<DT_C64>(src, ddt, dst, n, st);
+    case DT_C128: return convert_from<DT_C128>(src, ddt, dst, n, st);
+    case DT_BF16: return convert_from<DT_BF16>(src, ddt, dst, n, st);
+    case DT_F16: return convert_from<DT_F16>(src, ddt, dst, n, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- reductions
+// Block (vc, ry): lane x = column, y = row within the block's stride.
+struct ColShape {
+  dim3 grid, block;
+};
+static ColShape col_shape(int nv) {
+  const int vc = nv < 64 ? nv : 64;
+  int ry = 256 / vc;
+  if (ry < 1) ry = 1;
+  ColShape c;
+  c.block = dim3(vc, ry);
+  c.grid = dim3(kReduceBlocks, (nv + vc - 1) / vc);
+  return c;
+}
+
+// sum over threadIdx.y of val (per column lane), result valid in threadIdx.y == 0
+__device__ __forceinline__ double block_col_sum(double val, double* sh) {
+  const int vc = blockDim.x, ry = blockDim.y;
+  sh[threadIdx.y * vc + threadIdx.x] = val;
+  __syncthreads();
+  for (int w = 1; w < ry; w <<= 1) {
+    if ((threadIdx.y % (2 * w)) == 0 && threadIdx.y + w < ry)
+      sh[threadIdx.y * vc + threadIdx.x] += sh[(threadIdx.y + w) * vc + threadIdx.x];
+    __syncthreads();
+  }
+  return sh[threadIdx.x];
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) norm2_kernel(const typename S::word* __restrict__ x, size_t rows, int nv,
+                                                    double* __restrict__ partial) {
+  extern __shared__ double shd[];
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (v < nv)
+    for (size_t r = size_t(blockIdx.x) * blockDim.y + threadIdx.y; r < rows; r += size_t(gridDim.x) * blockDim.y) {
+      cpx<double> z = S::template load<double>(x + r * nv + v);
+      acc = fma(z.r, z.r, fma(z.i, z.i, acc));
+    }
+  double tot = block_col_sum(acc, shd);
+  if (threadIdx.y == 0 && v < nv) partial[size_t(blockIdx.x) * nv + v] = tot;
+}
+
+__global__ void finish_sum_kernel(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[size_t(b) * nv + v];
+    out[v] = s;
+  }
+}
+
+static hipError_t finish(const double* partial, int nv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_sum_kernel, dim3((nv + 255) / 256), dim3(256), 0, st, partial, kReduceBlocks, nv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(int dtype, const void* x, size_t sites, int comps, int nv, double* partial, double* out,
+                        hipStream_t st) {
+  const ColShape c = col_shape(nv);
+  const size_t rows = sites * comps;
+  const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
+  switch (dtype) {
+    case DT_C64: hipLaunchKernelGGL(norm2_kernel<C64>, c.grid, c.block, lds, st, (const float2*)x, rows, nv, partial); break;
+    case DT_C128: hipLaunchKernelGGL(norm2_kernel<C128>, c.grid, c.block, lds, st, (const double2*)x, rows, nv, partial); break;
+    case DT_BF16: hipLaunchKernelGGL(norm2_kernel<BF16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial); break;
+    case DT_F16: hipLaunchKernelGGL(norm2_kernel<F16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(partial, nv, out, st);
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void __launch_bounds__(256) xmy_kernel(const double2* __restrict__ b, const double2* __restrict__ t,
+                                                  double2* __restrict__ r, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    double2 x = b[i], y = t[i];
+    r[i] = make_double2(x.x - y.x, x.y - y.y);
+  }
+}
+
+hipError_t launch_xmy(const void* b, const void* t, void* r, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(xmy_kernel, stream_grid(n), dim3(256), 0, st, (const double2*)b, (const double2*)t,
+                     (double2*)r, n);
+  return hipGetLastError();
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) scale_to_kernel(const double2* __restrict__ hi, typename S::word* __restrict__ lo,
+                                                       const double* __restrict__ inv, size_t n, int nv) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double s = inv[i % nv];
+    double2 x = hi[i];
+    S::template store<double>(lo + i, cpx<double>{s * x.x, s * x.y});
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) axpy_promote_kernel(double2* __restrict__ x, const typename S::word* __restrict__ e,
+                                                           const double* __restrict__ sc, size_t n, int nv) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double s = sc[i % nv];
+    cpx<double> z = S::template load<double>(e + i);
+    double2 y = x[i];
+    x[i] = make_double2(fma(s, z.r, y.x), fma(s, z.i, y.y));
+  }
+}
+
+hipError_t launch_scale_to(const void* hi, int lodt, void* lo, const double* inv, size_t sites, int comps, int nv,
+                           hipStream_t st) {
+  const size_t n = sites * comps * nv;
+  const dim3 gr = stream_grid(n), bl(256);
+  switch (lodt) {
+    case DT_C64: hipLaunchKernelGGL(scale_to_kernel<C64>, gr, bl, 0, st, (const double2*)hi, (float2*)lo, inv, n, nv); break;
+    case DT_BF16: hipLaunchKernelGGL(scale_to_kernel<BF16>, gr, bl, 0, st, (const double2*)hi, (uint32_t*)lo, inv, n, nv); break;
+    case DT_F16: hipLaunchKernelGGL(scale_to_kernel<F16>, gr, bl, 0, st, (const double2*)hi, (uint32_t*)lo, inv, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_promote(void* x, int lodt, const void* e, const double* s, size_t sites, int comps, int nv,
+                               hipStream_t st) {
+  const size_t n = sites * comps * nv;
+  const dim3 gr = stream_grid(n), bl(256);
+  switch (lodt) {
+    case DT_C64: hipLaunchKernelGGL(axpy_promote_kernel<C64>, gr, bl, 0, st, (double2*)x, (const float2*)e, s, n, nv); break;
+    case DT_BF16: hipLaunchKernelGGL(axpy_promote_kernel<BF16>, gr, bl, 0, st, (double2*)x, (const uint32_t*)e, s, n, nv); break;
+    case DT_F16: hipLaunchKernelGGL(axpy_promote_kernel<F16>, gr, bl, 0, st, (double2*)x, (const uint32_t*)e, s, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// e += alpha p; r -= alpha q; per-column |r|^2 partials (FP32 arithmetic for the
+// updates, FP64 for the norm)
+template <class S>
+__global__ void __launch_bounds__(256) cg_update_xr_kernel(typename S::word* __restrict__ e, typename S::word* __restrict__ r,
+                                                           const typename S::word* __restrict__ p,
+                                                           const typename S::word* __restrict__ q,
+                                                           const double* __restrict__ alpha, size_t rows, int nv,
+                                                           double* __restrict__ partial) {
+  extern __shared__ double shd[];
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (v < nv) {
+    const float a = float(alpha[v]);
+    for (size_t row = size_t(blockIdx.x) * blockDim.y + threadIdx.y; row < rows; row += size_t(gridDim.x) * blockDim.y) {
+      const size_t i = row * nv + v;
+      cpx<float> ev = S::template load<float>(e + i), pv = S::template load<float>(p + i);
+      cpx<float> rv = S::template load<float>(r + i), qv = S::template load<float>(q + i);
+      ev = rmadd(ev, a, pv);
+      rv = rmadd(rv, -a, qv);
+      S::template store<float>(e + i, ev);
+      S::template store<float>(r + i, rv);
+      cpx<double> rs = S::template load<double>(r + i);  // the stored (rounded) residual
+      acc = fma(rs.r, rs.r, fma(rs.i, rs.i, acc));
+    }
+  }
+  double tot = block_col_sum(acc, shd);
+  if (threadIdx.y == 0 && v < nv) partial[size_t(blockIdx.x) * nv + v] = tot;
+}
+
+hipError_t launch_cg_update_xr(int dtype, void* e, void* r, const void* p, const void* q, const double* alpha,
+                               size_t sites, int comps, int nv, double* partial, double* out, hipStream_t st) {
+  const ColShape c = col_shape(nv);
+  const size_t rows = sites * comps;
+  const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
+  switch (dtype) {
+    case DT_C64:
+      hipLaunchKernelGGL(cg_update_xr_kernel<C64>, c.grid, c.block, lds, st, (float2*)e, (float2*)r, (const float2*)p,
+                         (const float2*)q, alpha, rows, nv, partial);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL(cg_update_xr_kernel<BF16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
+                         (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
+      break;
+    case DT_F16:
+      hipLaunchKernelGGL(cg_update_xr_kernel<F16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
+                         (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return finish(partial, nv, out, st);
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) cg_update_p_kernel(typename S::word* __restrict__ p,
+                                                          const typename S::word* __restrict__ r,
+                                                          const double* __restrict__ beta, size_t n, int nv) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const float b = float(beta[i % nv]);
+    cpx<float> pv = S::template load<float>(p + i), rv = S::template load<float>(r + i);
+    S::template store<float>(p + i, rmadd(rv, b, pv));
+  }
+}
+
+hipError_t launch_cg_update_p(int dtype, void* p, const void* r, const double* beta, size_t sites, int comps, int nv,
+                              hipStream_t st) {
+  const size_t n = sites * comps * nv;
+  const dim3 gr = stream_grid(n), bl(256);
+  switch (dtype) {
+    case DT_C64: hipLaunchKernelGGL(cg_update_p_kernel<C64>, gr, bl, 0, st, (float2*)p, (const float2*)r, beta, n, nv); break;
+    case DT_BF16: hipLaunchKernelGGL(cg_update_p_kernel<BF16>, gr, bl, 0, st, (uint32_t*)p, (const uint32_t*)r, beta, n, nv); break;
+    case DT_F16: hipLaunchKernelGGL(cg_update_p_kernel<F16>, gr, bl, 0, st, (uint32_t*)p, (const uint32_t*)r, beta, n, nv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(uint32_t* __restrict__ x, size_t nwords) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nwords; i += size_t(gridDim.x) * blockDim.x)
+    x[i] = 0u;
+}
+
+hipError_t launch_zero(int dtype, void* x, size_t n, hipStream_t st) {
+  const size_t nwords = n * dtype_bytes(dtype) / 4;
+  if (nwords == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, stream_grid(nwords), dim3(256), 0, st, (uint32_t*)x, nwords);
+  return hipGetLastError();
+}
+
+__global__ void cg_scalars_kernel(int mode, int nv, double* rr, double* rr_new, double* pq, double* rr0,
+                                  double* alpha, double* beta, double* active, double tol) {
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    const bool on = active[v] != 0.0;
+    if (mode == 0) {
+      alpha[v] = (on && pq[v] > 0.0) ? rr[v] / pq[v] : 0.0;
+    } else {
+      beta[v] = (on && rr[v] > 0.0) ? rr_new[v] / rr[v] : 0.0;
+      if (on) rr[v] = rr_new[v];
+      const bool still = on && rr0[v] > 0.0 && sqrt(rr[v] / rr0[v]) > tol;
+      active[v] = still ? 1.0 : 0.0;
+    }
+  }
+}
+
+hipError_t launch_cg_scalars(int mode, int nv, double* rr, double* rr_new, double* pq, double* rr0, double* alpha,
+                             double* beta, double* active, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(cg_scalars_kernel, dim3(1), dim3(256), 0, st, mode, nv, rr, rr_new, pq, rr0, alpha, beta,
+                     active, tol);
+  return hipGetLastError();
+}
+
+}  // namespace dsl

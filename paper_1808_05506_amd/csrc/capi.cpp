@@ -1,0 +1,221 @@
+// C ABI of the Dirac-operator library (declared in include/dslash.h).
+//
+// Every entry point validates its arguments synchronously, before any HIP
+// call, and reports failures as status codes with a thread-local detail
+// string; nothing is thrown across the ABI.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/dslash.h"
+#include "launch.hpp"
+#include "solver.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(DSLASH_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool valid_dtype(int dt) { return dt >= DSLASH_C64 && dt <= DSLASH_F16; }
+
+// Common checks on lattice geometry and sizes.
+int check_geom(int op, const int dims[4], int Nc, int Nv) {
+  if (!dims) return fail(DSLASH_E_ARG, "dims is NULL");
+  if (op < DSLASH_STAGGERED || op > DSLASH_BRILLOUIN) return fail(DSLASH_E_ARG, "unknown op %d", op);
+  if (Nc != 3) return fail(DSLASH_E_UNSUPPORTED, "only Nc = 3 is built (got %d)", Nc);
+  if (Nv < 1) return fail(DSLASH_E_ARG, "Nv must be >= 1 (got %d)", Nv);
+  uint64_t vol = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 2) return fail(DSLASH_E_ARG, "dims[%d] = %d < 2", i, dims[i]);
+    if (op == DSLASH_STAGGERED && (dims[i] & 1))
+      return fail(DSLASH_E_ARG, "staggered operator needs even extents (dims[%d] = %d)", i, dims[i]);
+    vol *= uint64_t(dims[i]);
+  }
+  if (vol >= (1ull << 31)) return fail(DSLASH_E_ARG, "lattice volume %llu >= 2^31", (unsigned long long)vol);
+  return DSLASH_OK;
+}
+
+uint64_t volume(const int dims[4]) { return uint64_t(dims[0]) * dims[1] * dims[2] * dims[3]; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = uintptr_t(a), pb = uintptr_t(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+namespace dsl {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace dsl
+
+extern "C" {
+
+const char* dslash_status_string(int status) {
+  switch (status) {
+    case DSLASH_OK: return "ok";
+    case DSLASH_E_ARG: return "invalid argument";
+    case DSLASH_E_UNSUPPORTED: return "unsupported configuration";
+    case DSLASH_E_ALIAS: return "output aliases an input";
+    case DSLASH_E_HIP: return "HIP runtime error";
+    case DSLASH_E_NOCONV: return "solver did not converge";
+    case DSLASH_E_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+const char* dslash_last_error(void) { return g_err; }
+
+int dslash_version(void) { return 100; }
+
+static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
+                        int Nv, double mass, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
+  if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
+  if (!U || !in || !out) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * eb;
+  const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * eb;
+  if (overlap(in, nspin, out, nspin)) return fail(DSLASH_E_ALIAS, "in and out overlap");
+  if (overlap(U, nlink, out, nspin)) return fail(DSLASH_E_ALIAS, "U and out overlap");
+  const dsl::Geom g = dsl::make_geom(dims, Nv);
+  hipError_t e = dsl::launch_apply(op, adj, dtype, g, U, in, out, mass, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
+  return DSLASH_OK;
+}
+
+int dslash_apply(int op, const void* U, const void* in, void* out, const int dims[4], int Nc, int Nv, double mass,
+                 int dtype, void* stream) {
+  return apply_common(false, op, U, in, out, dims, Nc, Nv, mass, dtype, stream);
+}
+
+int dslash_apply_adjoint(int op, const void* U, const void* in, void* out, const int dims[4], int Nc, int Nv,
+                         double mass, int dtype, void* stream) {
+  return apply_common(true, op, U, in, out, dims, Nc, Nv, mass, dtype, stream);
+}
+
+int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U, void* grad_in,
+                    const int dims[4], int Nc, int Nv, double mass, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
+  if (dtype != DSLASH_C64 && dtype != DSLASH_C128)
+    return fail(DSLASH_E_UNSUPPORTED, "backward is built for C64 and C128 only (got dtype %d)", dtype);
+  if (!grad_out) return fail(DSLASH_E_ARG, "grad_out is NULL");
+  if (grad_in && !U) return fail(DSLASH_E_ARG, "U is NULL but grad_in requested");
+  if (grad_U && !in) return fail(DSLASH_E_ARG, "in is NULL but grad_U requested");
+  if (grad_U && op == DSLASH_BRILLOUIN)
+    return fail(DSLASH_E_UNSUPPORTED, "link gradient of the Brillouin operator is not built");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * eb;
+  const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * eb;
+  if (grad_in) {
+    if (overlap(grad_in, nspin, grad_out, nspin) || (in && overlap(grad_in, nspin, in, nspin)) ||
+        overlap(grad_in, nspin, U, nlink))
+      return fail(DSLASH_E_ALIAS, "grad_in overlaps an input");
+  }
+  if (grad_U) {
+    if (overlap(grad_U, nlink, grad_out, nspin) || overlap(grad_U, nlink, in, nspin) ||
+        (U && overlap(grad_U, nlink, U, nlink)) || (grad_in && overlap(grad_U, nlink, grad_in, nspin)))
+      return fail(DSLASH_E_ALIAS, "grad_U overlaps another argument");
+  }
+  const dsl::Geom g = dsl::make_geom(dims, Nv);
+  hipStream_t st = (hipStream_t)stream;
+  if (grad_in) {
+    hipError_t e = dsl::launch_apply(op, true, dtype, g, U, grad_out, grad_in, mass, st);
+    if (e != hipSuccess) return hip_fail(e, "dslash_backward grad_in launch");
+  }
+  if (grad_U) {
+    hipError_t e = dsl::launch_link_grad(op, dtype, g, grad_out, in, grad_U, st);
+    if (e != hipSuccess) return hip_fail(e, "dslash_backward grad_U launch");
+  }
+  return DSLASH_OK;
+}
+
+int dslash_brillouin_links(const void* V, void* W, const int dims[4], int Nc, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return rc;
+  if (dtype != DSLASH_C64 && dtype != DSLASH_C128)
+    return fail(DSLASH_E_UNSUPPORTED, "W construction is built for C64 and C128 only (got dtype %d)", dtype);
+  if (!V || !W) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  if (overlap(V, size_t(vol) * 36 * eb, W, size_t(vol) * 360 * eb)) return fail(DSLASH_E_ALIAS, "V and W overlap");
+  const dsl::Geom g = dsl::make_geom(dims, 1);
+  hipError_t e = dsl::launch_brillouin_links(dtype, g, V, W, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_brillouin_links launch");
+  return DSLASH_OK;
+}
+
+int dslash_convert(const void* src, int src_dtype, void* dst, int dst_dtype, size_t n, void* stream) {
+  g_err[0] = 0;
+  if (!valid_dtype(src_dtype) || !valid_dtype(dst_dtype)) return fail(DSLASH_E_ARG, "unknown dtype");
+  if (n == 0) return DSLASH_OK;
+  if (!src || !dst) return fail(DSLASH_E_ARG, "NULL pointer");
+  if (overlap(src, n * dsl::dtype_bytes(src_dtype), dst, n * dsl::dtype_bytes(dst_dtype)))
+    return fail(DSLASH_E_ALIAS, "src and dst overlap");
+  hipError_t e = dsl::launch_convert(src, src_dtype, dst, dst_dtype, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_convert launch");
+  return DSLASH_OK;
+}
+
+size_t dslash_solve_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype) {
+  if (check_geom(op, dims, Nc, Nv)) return 0;
+  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16) return 0;
+  return dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
+}
+
+int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                 void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
+  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16)
+    return fail(DSLASH_E_ARG, "inner dtype must be C64, BF16 or F16 (got %d)", inner_dtype);
+  if (!U64 || !b64 || !x64) return fail(DSLASH_E_ARG, "NULL field pointer");
+  if (!(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1)) return fail(DSLASH_E_ARG, "need tol > 0, 0 < inner_tol < 1");
+  if (max_outer < 1 || max_inner < 1) return fail(DSLASH_E_ARG, "iteration limits must be >= 1");
+  const size_t need = dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
+  if (!workspace || ws_bytes < need)
+    return fail(DSLASH_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, workspace ? ws_bytes : size_t(0));
+  const uint64_t vol = volume(dims);
+  const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * 16;
+  const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * 16;
+  if (overlap(x64, nspin, b64, nspin) || overlap(x64, nspin, U64, nlink) || overlap(x64, nspin, workspace, need) ||
+      overlap(workspace, need, U64, nlink) || overlap(workspace, need, b64, nspin))
+    return fail(DSLASH_E_ALIAS, "x, b, U and workspace must not overlap");
+  dsl::SolveArgs a;
+  a.op = op;
+  a.U64 = U64;
+  a.b64 = b64;
+  a.x64 = x64;
+  for (int i = 0; i < 4; ++i) a.dims[i] = dims[i];
+  a.nv = Nv;
+  a.mass = mass;
+  a.inner_dtype = inner_dtype;
+  a.tol = tol;
+  a.inner_tol = inner_tol;
+  a.max_outer = max_outer;
+  a.max_inner = max_inner;
+  a.workspace = workspace;
+  a.final_relres = final_relres;
+  a.iters = iters;
+  a.stream = (hipStream_t)stream;
+  return dsl::solve(a);
+}
+
+}  // extern "C"

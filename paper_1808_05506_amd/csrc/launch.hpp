@@ -1,0 +1,63 @@
+// Internal launcher interface between the C ABI / solver (host C++) and the
+// HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "dslash_common.hpp"
+
+namespace dsl {
+
+enum Op { OP_STAGGERED = 0, OP_WILSON = 1, OP_BRILLOUIN = 2 };
+enum Dtype { DT_C64 = 0, DT_C128 = 1, DT_BF16 = 2, DT_F16 = 3 };
+
+inline size_t dtype_bytes(int dt) { return dt == DT_C128 ? 16 : dt == DT_C64 ? 8 : 4; }
+inline int spinor_comps(int op) { return op == OP_STAGGERED ? 3 : 12; }
+inline int links_per_site(int op) { return op == OP_BRILLOUIN ? 40 : 4; }
+
+Geom make_geom(const int dims[4], int nv);
+
+// Thread shape of the (site, right-hand side) kernels.
+struct Shape {
+  dim3 grid, block;
+};
+Shape site_v_shape(uint32_t vol, int nv);
+
+hipError_t launch_apply(int op, bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
+                        double mass, hipStream_t st);
+hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
+hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
+                            hipStream_t st);
+hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t st);
+
+// ---- solver BLAS-1 (fields of `comps` complex numbers per site times nv columns,
+//      column index fastest; per-column scalars are device arrays of nv doubles)
+constexpr int kReduceBlocks = 512;
+// partial[b][v] = sum over the block's sites of |x|^2 (FP64), then out[v] = sum_b partial[b][v]
+hipError_t launch_norm2(int dtype, const void* x, size_t sites, int comps, int nv, double* partial, double* out,
+                        hipStream_t st);
+// r = b - t (all C128)
+hipError_t launch_xmy(const void* b, const void* t, void* r, size_t n, hipStream_t st);
+// lo = hi * inv[v] (hi C128 -> lo dtype)
+hipError_t launch_scale_to(const void* hi, int lodt, void* lo, const double* inv, size_t sites, int comps, int nv,
+                           hipStream_t st);
+// x += s[v] * e  (x C128, e lo dtype)
+hipError_t launch_axpy_promote(void* x, int lodt, const void* e, const double* s, size_t sites, int comps, int nv,
+                               hipStream_t st);
+// e += alpha[v] p;  r -= alpha[v] q;  partial |r|^2 -> out
+hipError_t launch_cg_update_xr(int dtype, void* e, void* r, const void* p, const void* q, const double* alpha,
+                               size_t sites, int comps, int nv, double* partial, double* out, hipStream_t st);
+// p = r + beta[v] p
+hipError_t launch_cg_update_p(int dtype, void* p, const void* r, const double* beta, size_t sites, int comps,
+                              int nv, hipStream_t st);
+// zero n complex numbers of dtype
+hipError_t launch_zero(int dtype, void* x, size_t n, hipStream_t st);
+// per-column CG scalars on the device (see solver.cpp):
+//   mode 0: alpha = active ? rr / pq : 0
+//   mode 1: beta = active ? rr_new / rr : 0; rr = active ? rr_new : rr;
+//           active &= sqrt(rr / rr0) > tol
+hipError_t launch_cg_scalars(int mode, int nv, double* rr, double* rr_new, double* pq, double* rr0, double* alpha,
+                             double* beta, double* active, double tol, hipStream_t st);
+
+}  // namespace dsl

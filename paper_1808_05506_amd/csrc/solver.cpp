@@ -1,0 +1,175 @@
+// Mixed-precision solve of D x = b (the paper has no solver; this is the
+// defect-correction scheme of the library's C ABI).
+//
+//   outer (FP64):  r = b - D x;  relres_v = ||r_v|| / ||b_v||;  stop when all <= tol
+//                  rhat = r / rms(r)  (per column, so 16-bit storage sees O(1) values)
+//   inner (storage inner_dtype, FP32 arithmetic): CG on D^dag D e = D^dag rhat,
+//                  e0 = 0, per-column alpha/beta, each column frozen once
+//                  ||r_inner|| / ||r_inner,0|| <= inner_tol
+//   update (FP64): x += rms(r) * e
+//
+// Every vector operation runs in a HIP kernel; the host only sequences the
+// launches and reads the per-column norms (Nv doubles) to decide convergence.
+#include "solver.hpp"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <vector>
+
+#include "../../include/dslash.h"
+#include "launch.hpp"
+
+namespace dsl {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t u_lo, e, r, p, q, s, t64, r64, partial, scal, total;
+  size_t field_lo, field64, links_lo;
+};
+
+Layout layout(int op, const int dims[4], int nv, int lodt) {
+  const size_t vol = size_t(dims[0]) * dims[1] * dims[2] * dims[3];
+  const size_t comps = size_t(spinor_comps(op));
+  Layout L;
+  L.links_lo = vol * links_per_site(op) * 9;
+  L.field_lo = vol * comps * nv;
+  L.field64 = L.field_lo;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t eb = dtype_bytes(lodt);
+  L.u_lo = take(L.links_lo * eb);
+  L.e = take(L.field_lo * eb);
+  L.r = take(L.field_lo * eb);
+  L.p = take(L.field_lo * eb);
+  L.q = take(L.field_lo * eb);
+  L.s = take(L.field_lo * eb);
+  L.t64 = take(L.field64 * 16);
+  L.r64 = take(L.field64 * 16);
+  L.partial = take(size_t(kReduceBlocks) * nv * sizeof(double));
+  L.scal = take(size_t(12) * nv * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int hipfail(hipError_t e, const char* where) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  return set_error(DSLASH_E_HIP, buf);
+}
+
+#define DSL_TRY(expr, where)                         \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hipfail(_e, where); \
+  } while (0)
+
+}  // namespace
+
+size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype) {
+  return layout(op, dims, nv, inner_dtype).total;
+}
+
+int solve(const SolveArgs& a) {
+  const int nv = a.nv;
+  const int lodt = a.inner_dtype;
+  const Layout L = layout(a.op, a.dims, nv, lodt);
+  unsigned char* ws = static_cast<unsigned char*>(a.workspace);
+  void* u_lo = ws + L.u_lo;
+  void* e = ws + L.e;
+  void* r = ws + L.r;
+  void* p = ws + L.p;
+  void* q = ws + L.q;
+  void* s = ws + L.s;
+  void* t64 = ws + L.t64;
+  void* r64 = ws + L.r64;
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* sc = reinterpret_cast<double*>(ws + L.scal);
+  double *rr = sc, *rr_new = sc + nv, *pq = sc + 2 * nv, *rr0 = sc + 3 * nv, *alpha = sc + 4 * nv,
+         *beta = sc + 5 * nv, *active = sc + 6 * nv, *nb2 = sc + 7 * nv, *nr2 = sc + 8 * nv,
+         *scale = sc + 9 * nv, *inv = sc + 10 * nv;
+  hipStream_t st = a.stream;
+  const Geom g = make_geom(a.dims, nv);
+  const size_t vol = g.vol;
+  const int comps = spinor_comps(a.op);
+  const double nelem = double(vol) * comps;
+
+  DSL_TRY(launch_convert(a.U64, DT_C128, u_lo, lodt, L.links_lo, st), "link conversion");
+  DSL_TRY(launch_norm2(DT_C128, a.b64, vol, comps, nv, partial, nb2, st), "norm of b");
+  std::vector<double> hb(nv), hr(nv), hact(nv), hsc(2 * nv);
+  DSL_TRY(hipMemcpyAsync(hb.data(), nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
+  DSL_TRY(hipStreamSynchronize(st), "sync");
+
+  int total_inner = 0, outer = 0, status = DSLASH_OK;
+  std::vector<double> relres(nv, 0.0);
+  for (;;) {
+    // r = b - D x in FP64
+    DSL_TRY(launch_apply(a.op, false, DT_C128, g, a.U64, a.x64, t64, a.mass, st), "outer apply");
+    DSL_TRY(launch_xmy(a.b64, t64, r64, L.field64, st), "outer residual");
+    DSL_TRY(launch_norm2(DT_C128, r64, vol, comps, nv, partial, nr2, st), "outer norm");
+    DSL_TRY(hipMemcpyAsync(hr.data(), nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
+    DSL_TRY(hipStreamSynchronize(st), "sync");
+    bool done = true;
+    for (int v = 0; v < nv; ++v) {
+      relres[v] = hb[v] > 0 ? sqrt(hr[v] / hb[v]) : sqrt(hr[v]);
+      if (relres[v] > a.tol) done = false;
+    }
+    if (done) break;
+    if (outer == a.max_outer) {
+      status = set_error(DSLASH_E_NOCONV, "outer iteration limit reached");
+      break;
+    }
+    ++outer;
+    // per-column RMS scaling of the residual; converged columns get rhs 0 and stay frozen
+    for (int v = 0; v < nv; ++v) {
+      const bool work = relres[v] > a.tol && hr[v] > 0;
+      const double rms = sqrt(hr[v] / nelem);
+      hsc[v] = work ? rms : 0.0;
+      hsc[nv + v] = work ? 1.0 / rms : 0.0;
+    }
+    DSL_TRY(hipMemcpyAsync(scale, hsc.data(), 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
+    DSL_TRY(launch_scale_to(r64, lodt, q, inv, vol, comps, nv, st), "scale residual");
+    // inner CG on D^dag D e = D^dag rhat
+    DSL_TRY(launch_apply(a.op, true, lodt, g, u_lo, q, r, a.mass, st), "inner rhs");
+    DSL_TRY(launch_zero(lodt, e, L.field_lo, st), "zero e");
+    DSL_TRY(launch_convert(r, lodt, p, lodt, L.field_lo, st), "p = r");
+    DSL_TRY(launch_norm2(lodt, r, vol, comps, nv, partial, rr, st), "inner norm");
+    DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
+    for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
+    DSL_TRY(hipMemcpyAsync(active, hact.data(), nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    for (int k = 0; k < a.max_inner; ++k) {
+      DSL_TRY(launch_apply(a.op, false, lodt, g, u_lo, p, q, a.mass, st), "inner D p");
+      DSL_TRY(launch_norm2(lodt, q, vol, comps, nv, partial, pq, st), "|Dp|^2");
+      DSL_TRY(launch_cg_scalars(0, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "alpha");
+      DSL_TRY(launch_apply(a.op, true, lodt, g, u_lo, q, s, a.mass, st), "inner D^dag q");
+      DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, vol, comps, nv, partial, rr_new, st), "x/r update");
+      DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
+      DSL_TRY(launch_cg_update_p(lodt, p, r, beta, vol, comps, nv, st), "p update");
+      ++total_inner;
+      DSL_TRY(hipMemcpyAsync(hact.data(), active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
+      DSL_TRY(hipStreamSynchronize(st), "sync");
+      bool any = false;
+      for (int v = 0; v < nv; ++v) any = any || hact[v] != 0.0;
+      if (!any) break;
+    }
+    DSL_TRY(launch_axpy_promote(a.x64, lodt, e, scale, vol, comps, nv, st), "x update");
+  }
+  if (a.final_relres)
+    for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];
+  if (a.iters) {
+    a.iters[0] = total_inner;
+    a.iters[1] = outer;
+  }
+  return status;
+}
+
+}  // namespace dsl

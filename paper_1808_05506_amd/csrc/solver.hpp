@@ -1,0 +1,30 @@
+// Mixed-precision solver driver (host side of dslash_solve).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace dsl {
+
+struct SolveArgs {
+  int op;
+  const void* U64;
+  const void* b64;
+  void* x64;
+  int dims[4];
+  int nv;
+  double mass;
+  int inner_dtype;
+  double tol, inner_tol;
+  int max_outer, max_inner;
+  void* workspace;
+  double* final_relres;
+  int* iters;
+  hipStream_t stream;
+};
+
+size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype);
+int solve(const SolveArgs& a);
+int set_error(int code, const char* msg);
+
+}  // namespace dsl

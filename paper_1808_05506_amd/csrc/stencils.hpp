@@ -1,0 +1,435 @@
+// Per-thread bodies of the three Dirac stencils.
+//
+// One thread owns one (site, right-hand side) pair and accumulates every
+// contribution to that output in registers, then writes it once -- the
+// thread-private "site" accumulator of Sec. 2, here one per GPU lane.  The
+// right-hand-side index is the fastest lane index, so for a fixed spin and
+// colour the lanes of one site read N_v consecutive complex numbers and every
+// lane of a site reads the same link (one cache line serves them all).
+//
+// Spin structure uses the chiral basis gamma_mu = [[0, A_mu], [A_mu^dag, 0]]
+// with A_k = -i sigma_k and A_4 = 1.  For c = +-1,
+//   (1 + c gamma_mu) psi = [h ; c A_mu^dag h],  h = psi_up + c A_mu psi_low,
+// so a hop needs only the 2-spinor h (rank-2 projector of eq. def_wils).
+#pragma once
+
+#include "dslash_common.hpp"
+
+namespace dsl {
+
+template <int C, class T> DSL_HD cpx<T> cs(cpx<T> a) { return C > 0 ? a : -a; }            // c * a
+template <int C, class T> DSL_HD cpx<T> ci(cpx<T> a) { return C > 0 ? times_i(a) : times_mi(a); }  // c i a
+
+template <class S, class T>
+DSL_HD void load_link(const typename S::word* __restrict__ U, size_t base, cpx<T> (&u)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(U + base + a * 3 + b);
+}
+
+template <class S, class T>
+DSL_HD void load_wspinor(const typename S::word* __restrict__ in, size_t base, int nv, cpx<T> (&p)[4][3]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[sp][c] = S::template load<T>(in + base + size_t(sp * 3 + c) * nv);
+}
+
+// h = psi_up + c A_mu psi_low
+template <int MU, int C, class T>
+DSL_HD void project(const cpx<T> (&p)[4][3], cpx<T> (&h)[2][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (MU == 0) {        // A_1 = [[0,-i],[-i,0]]
+      h[0][c] = p[0][c] - ci<C>(p[3][c]);
+      h[1][c] = p[1][c] - ci<C>(p[2][c]);
+    } else if (MU == 1) { // A_2 = [[0,-1],[1,0]]
+      h[0][c] = p[0][c] - cs<C>(p[3][c]);
+      h[1][c] = p[1][c] + cs<C>(p[2][c]);
+    } else if (MU == 2) { // A_3 = [[-i,0],[0,i]]
+      h[0][c] = p[0][c] - ci<C>(p[2][c]);
+      h[1][c] = p[1][c] + ci<C>(p[3][c]);
+    } else {              // A_4 = 1
+      h[0][c] = p[0][c] + cs<C>(p[2][c]);
+      h[1][c] = p[1][c] + cs<C>(p[3][c]);
+    }
+  }
+}
+
+// acc += [t ; c A_mu^dag t]
+template <int MU, int C, class T>
+DSL_HD void reconstruct_add(cpx<T> (&acc)[4][3], const cpx<T> (&t)[2][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[0][c] += t[0][c];
+    acc[1][c] += t[1][c];
+    if (MU == 0) {        // A_1^dag = [[0,i],[i,0]]
+      acc[2][c] += ci<C>(t[1][c]);
+      acc[3][c] += ci<C>(t[0][c]);
+    } else if (MU == 1) { // A_2^dag = [[0,1],[-1,0]]
+      acc[2][c] += cs<C>(t[1][c]);
+      acc[3][c] -= cs<C>(t[0][c]);
+    } else if (MU == 2) { // A_3^dag = [[i,0],[0,-i]]
+      acc[2][c] += ci<C>(t[0][c]);
+      acc[3][c] -= ci<C>(t[1][c]);
+    } else {              // A_4^dag = 1
+      acc[2][c] += cs<C>(t[0][c]);
+      acc[3][c] += cs<C>(t[1][c]);
+    }
+  }
+}
+
+// t[s] = u h[s]  (DAG = false)  or  u^dag h[s]  (DAG = true), s = 0, 1
+template <bool DAG, class T>
+DSL_HD void su3_mul2(const cpx<T> (&u)[3][3], const cpx<T> (&h)[2][3], cpx<T> (&t)[2][3]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<T> r = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) r = DAG ? cjmadd(r, u[b][a], h[s][b]) : cmadd(r, u[a][b], h[s][b]);
+      t[s][a] = r;
+    }
+}
+
+// One Wilson hop: acc += (1 + c gamma_mu) U' psi(n), U' = U or U^dag.
+template <int MU, int C, bool DAG, class S, class T>
+DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S::word* __restrict__ in,
+                       size_t link_base, size_t spin_base, int nv, cpx<T> (&acc)[4][3]) {
+  cpx<T> p[4][3];
+  load_wspinor<S, T>(in, spin_base, nv, p);
+  cpx<T> h[2][3];
+  project<MU, C, T>(p, h);
+  cpx<T> u[3][3];
+  load_link<S, T>(U, link_base, u);
+  cpx<T> t[2][3];
+  su3_mul2<DAG, T>(u, h, t);
+  reconstruct_add<MU, C, T>(acc, t);
+}
+
+// D_W at c_SW = 0 (eq. def_wils) in hop form:
+//   out(x) = (4 + m0) in(x) - 1/2 sum_mu [(1 - gamma_mu) V_mu(x) in(x+mu)
+//                                       + (1 + gamma_mu) V_mu(x-mu)^dag in(x-mu)]
+// ADJ: gamma_5 D_W gamma_5, i.e. gamma_mu -> -gamma_mu.
+template <bool ADJ, class S, class T>
+DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
+                        const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                        uint32_t s, int v, T diag) {
+  constexpr int CF = ADJ ? +1 : -1;  // forward projector 1 + CF gamma
+  constexpr int CB = -CF;            // backward projector 1 + CB gamma
+  const SiteNbr nb = site_nbr(g, s);
+  const int nv = g.nv;
+  const size_t sps = size_t(12) * nv;  // complex numbers per site of a spinor block
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[a][c] = zero<T>();
+
+  const uint32_t sf0 = s + nb.fwd[0], sb0 = s + nb.bwd[0];
+  const uint32_t sf1 = s + nb.fwd[1], sb1 = s + nb.bwd[1];
+  const uint32_t sf2 = s + nb.fwd[2], sb2 = s + nb.bwd[2];
+  const uint32_t sf3 = s + nb.fwd[3], sb3 = s + nb.bwd[3];
+  wilson_hop<0, CF, false, S, T>(U, in, (size_t(s) * 4 + 0) * 9, sf0 * sps + v, nv, acc);
+  wilson_hop<0, CB, true, S, T>(U, in, (size_t(sb0) * 4 + 0) * 9, sb0 * sps + v, nv, acc);
+  wilson_hop<1, CF, false, S, T>(U, in, (size_t(s) * 4 + 1) * 9, sf1 * sps + v, nv, acc);
+  wilson_hop<1, CB, true, S, T>(U, in, (size_t(sb1) * 4 + 1) * 9, sb1 * sps + v, nv, acc);
+  wilson_hop<2, CF, false, S, T>(U, in, (size_t(s) * 4 + 2) * 9, sf2 * sps + v, nv, acc);
+  wilson_hop<2, CB, true, S, T>(U, in, (size_t(sb2) * 4 + 2) * 9, sb2 * sps + v, nv, acc);
+  wilson_hop<3, CF, false, S, T>(U, in, (size_t(s) * 4 + 3) * 9, sf3 * sps + v, nv, acc);
+  wilson_hop<3, CB, true, S, T>(U, in, (size_t(sb3) * 4 + 3) * 9, sb3 * sps + v, nv, acc);
+
+  const size_t base = size_t(s) * sps + v;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t e = base + size_t(sp * 3 + c) * nv;
+      cpx<T> p = S::template load<T>(in + e);
+      cpx<T> o;
+      o.r = fma(diag, p.r, T(-0.5) * acc[sp][c].r);
+      o.i = fma(diag, p.i, T(-0.5) * acc[sp][c].i);
+      S::template store<T>(out + e, o);
+    }
+}
+
+// D_S (Sec. 3): out(x) = m in(x) + sum_mu eta_mu(x)/2 [V_mu(x) in(x+mu) - V_mu(x-mu)^dag in(x-mu)],
+// eta_1 = 1, eta_2 = (-1)^x, eta_3 = (-1)^(x+y), eta_4 = (-1)^(x+y+z).  ADJ negates the hop term.
+template <bool ADJ, class S, class T>
+DSL_HD void staggered_site(const Geom& g, const typename S::word* __restrict__ U,
+                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                           uint32_t s, int v, T mass) {
+  const SiteNbr nb = site_nbr(g, s);
+  const int nv = g.nv;
+  const size_t sps = size_t(3) * nv;
+  cpx<T> acc[3] = {zero<T>(), zero<T>(), zero<T>()};
+  int par = 0;  // x_1 + ... + x_{mu-1}
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const T eta = (par & 1) ? T(-1) : T(1);
+    par += nb.c[mu];
+    const uint32_t sf = s + nb.fwd[mu], sb = s + nb.bwd[mu];
+    cpx<T> u[3][3], ub[3][3], pf[3], pb[3];
+    load_link<S, T>(U, (size_t(s) * 4 + mu) * 9, u);
+    load_link<S, T>(U, (size_t(sb) * 4 + mu) * 9, ub);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pf[c] = S::template load<T>(in + size_t(sf) * sps + size_t(c) * nv + v);
+      pb[c] = S::template load<T>(in + size_t(sb) * sps + size_t(c) * nv + v);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<T> t = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t = cmadd(t, u[a][b], pf[b]);
+      cpx<T> tb = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) tb = cjmadd(tb, ub[b][a], pb[b]);
+      acc[a] = rmadd(acc[a], eta, t - tb);
+    }
+  }
+  const T half = ADJ ? T(-0.5) : T(0.5);
+  const size_t base = size_t(s) * sps + v;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const size_t e = base + size_t(c) * nv;
+    cpx<T> p = S::template load<T>(in + e);
+    cpx<T> o;
+    o.r = fma(mass, p.r, half * acc[c].r);
+    o.i = fma(mass, p.i, half * acc[c].i);
+    S::template store<T>(out + e, o);
+  }
+}
+
+// ---------------------------------------------------------------- Brillouin
+// Direction of stored slot j (Tab. 1 caption): n = j + 41 = sum_mu (d_mu + 1) 3^mu.
+DSL_HD void stored_direction(int j, int (&d)[4]) {
+  int n = j + 41;
+  d[0] = n % 3 - 1;
+  d[1] = (n / 3) % 3 - 1;
+  d[2] = (n / 9) % 3 - 1;
+  d[3] = n / 27 - 1;
+}
+
+// Coefficients printed after eq. def_lap: rho_k = (64,16,4,1)/432, lambda_k = (-240,8,4,2,1)/64.
+template <class T> DSL_HD T bri_rho(int k) {
+  return k == 1 ? T(64.0 / 432.0) : k == 2 ? T(16.0 / 432.0) : k == 3 ? T(4.0 / 432.0) : T(1.0 / 432.0);
+}
+template <class T> DSL_HD T bri_lambda(int k) {
+  return k == 0 ? T(-240.0 / 64.0) : k == 1 ? T(8.0 / 64.0) : k == 2 ? T(4.0 / 64.0) : k == 3 ? T(2.0 / 64.0) : T(1.0 / 64.0);
+}
+
+// t[s] = w p[s] (DAG false) or w^dag p[s] (DAG true), all four spins
+template <bool DAG, class T>
+DSL_HD void su3_mul4(const cpx<T> (&w)[3][3], const cpx<T> (&p)[4][3], cpx<T> (&t)[4][3]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<T> r = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) r = DAG ? cjmadd(r, w[b][a], p[s][b]) : cmadd(r, w[a][b], p[s][b]);
+      t[s][a] = r;
+    }
+}
+
+// (alpha + i beta) * y added to acc
+template <class T> DSL_HD cpx<T> cmadd_ab(cpx<T> acc, T alpha, T beta, cpx<T> y) {
+  acc.r = fma(alpha, y.r, acc.r);
+  acc.r = fma(-beta, y.i, acc.r);
+  acc.i = fma(alpha, y.i, acc.i);
+  acc.i = fma(beta, y.r, acc.i);
+  return acc;
+}
+
+// D_B at c_SW = 0 (eqs. def_bril, def_der, def_lap), hop form:
+//   out(x) = (m0 - lambda_0/2) in(x) + sum_{d != 0} [-lambda_k/2 + rho_k d.gamma] W_d(x) in(x+d)
+// taken over pairs (d, -d) of one stored slot j:  W_d(x) is stored at x,
+// W_{-d}(x) = W_d(x-d)^dag is read at x-d.  With chi_+- the two products,
+//   a (chi_+ + chi_-) + b (d.gamma)(chi_+ - chi_-),  a = -lambda_k/2, b = rho_k,
+// and d.gamma = [[0, S], [S^dag, 0]], S = sum_mu d_mu A_mu
+//   = [[d4 - i d3, -d2 - i d1], [d2 - i d1, d4 + i d3]].
+// ADJ: gamma_5 D_B gamma_5, i.e. b -> -b.
+template <bool ADJ, class S, class T>
+DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W,
+                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                           uint32_t s, int v, T diag) {
+  const SiteNbr nb = site_nbr(g, s);
+  const int nv = g.nv;
+  const size_t sps = size_t(12) * nv;
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[a][c] = zero<T>();
+
+#pragma unroll 1
+  for (int j = 0; j < 40; ++j) {
+    int d[4];
+    stored_direction(j, d);
+    int offp = 0, offm = 0, k = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      offp += d[mu] > 0 ? nb.fwd[mu] : (d[mu] < 0 ? nb.bwd[mu] : 0);
+      offm += d[mu] > 0 ? nb.bwd[mu] : (d[mu] < 0 ? nb.fwd[mu] : 0);
+      k += d[mu] != 0;
+    }
+    const uint32_t sp = s + offp, sm = s + offm;
+    const T a = T(-0.5) * bri_lambda<T>(k);
+    const T b = (ADJ ? T(-1) : T(1)) * bri_rho<T>(k);
+    const T B1 = b * T(d[0]), B2 = b * T(d[1]), B3 = b * T(d[2]), B4 = b * T(d[3]);
+
+    cpx<T> chi_p[4][3], chi_m[4][3];
+    {
+      cpx<T> w[3][3], p[4][3];
+      load_link<S, T>(W, (size_t(s) * 40 + j) * 9, w);
+      load_wspinor<S, T>(in, size_t(sp) * sps + v, nv, p);
+      su3_mul4<false, T>(w, p, chi_p);
+    }
+    {
+      cpx<T> w[3][3], p[4][3];
+      load_link<S, T>(W, (size_t(sm) * 40 + j) * 9, w);
+      load_wspinor<S, T>(in, size_t(sm) * sps + v, nv, p);
+      su3_mul4<true, T>(w, p, chi_m);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cpx<T> y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[q][c] = rmadd(acc[q][c], a, chi_p[q][c] + chi_m[q][c]);
+        y[q] = chi_p[q][c] - chi_m[q][c];
+      }
+      // upper += S y_low, lower += S^dag y_up
+      acc[0][c] = cmadd_ab(acc[0][c], B4, -B3, y[2]);
+      acc[0][c] = cmadd_ab(acc[0][c], -B2, -B1, y[3]);
+      acc[1][c] = cmadd_ab(acc[1][c], B2, -B1, y[2]);
+      acc[1][c] = cmadd_ab(acc[1][c], B4, B3, y[3]);
+      acc[2][c] = cmadd_ab(acc[2][c], B4, B3, y[0]);
+      acc[2][c] = cmadd_ab(acc[2][c], B2, B1, y[1]);
+      acc[3][c] = cmadd_ab(acc[3][c], -B2, B1, y[0]);
+      acc[3][c] = cmadd_ab(acc[3][c], B4, -B3, y[1]);
+    }
+  }
+  const size_t base = size_t(s) * sps + v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t e = base + size_t(q * 3 + c) * nv;
+      cpx<T> p = S::template load<T>(in + e);
+      cpx<T> o;
+      o.r = fma(diag, p.r, acc[q][c].r);
+      o.i = fma(diag, p.i, acc[q][c].i);
+      S::template store<T>(out + e, o);
+    }
+}
+
+// ---------------------------------------------------------------- W build
+// W_d(x) for stored slot j (Tab. 1): mean over the k! orderings of the hops of
+// d of the ordered product V_{e1}(x) V_{e2}(x+e1) ..., V_{-mu}(y) = V_mu(y-mu)^dag.
+template <class S, class T>
+DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restrict__ V,
+                                typename S::word* __restrict__ Wout, uint32_t s, int j) {
+  int d[4];
+  stored_direction(j, d);
+  int mus[4], sgn[4], k = 0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu)
+    if (d[mu] != 0) {
+      mus[k] = mu;
+      sgn[k] = d[mu];
+      ++k;
+    }
+  const SiteNbr nb = site_nbr(g, s);
+  cpx<T> acc[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
+
+  int nperm = 0;
+  // all permutations of {0..3}; keep those that fix k..3, i.e. the k! orderings of the first k hops
+#pragma unroll 1
+  for (int code = 0; code < 24; ++code) {
+    int perm[4];
+    {
+      // decode the Lehmer code (factorial number system) into a permutation
+      int avail[4] = {0, 1, 2, 3};
+      int rem = code;
+      const int fact[4] = {6, 2, 1, 1};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int q = rem / fact[i];
+        rem -= q * fact[i];
+        perm[i] = avail[q];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+          if (t >= q) avail[t] = avail[t + 1];
+      }
+    }
+    bool keep = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i >= k && perm[i] != i) keep = false;
+    if (!keep) continue;
+    ++nperm;
+    int pos[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+    cpx<T> m[3][3];
+#pragma unroll 1
+    for (int i = 0; i < k; ++i) {
+      const int mu = mus[perm[i]], sg = sgn[perm[i]];
+      int q[4] = {pos[0], pos[1], pos[2], pos[3]};
+      if (sg < 0) q[mu] = (q[mu] == 0) ? g.n[mu] - 1 : q[mu] - 1;  // link V_mu(y - mu)^dag
+      const uint32_t ls = uint32_t(q[0] + g.stride[1] * q[1] + g.stride[2] * q[2] + g.stride[3] * q[3]);
+      cpx<T> l[3][3];
+      load_link<S, T>(V, (size_t(ls) * 4 + mu) * 9, l);
+      if (sg < 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = a; b < 3; ++b) {
+            cpx<T> x = l[a][b], y = l[b][a];
+            l[a][b] = conj(y);
+            l[b][a] = conj(x);
+          }
+      }
+      if (i == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) m[a][b] = l[a][b];
+      } else {
+        cpx<T> r[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            cpx<T> z = zero<T>();
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z = cmadd(z, m[a][c], l[c][b]);
+            r[a][b] = z;
+          }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) m[a][b] = r[a][b];
+      }
+      pos[mu] = sg > 0 ? (pos[mu] + 1 == g.n[mu] ? 0 : pos[mu] + 1) : q[mu];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[a][b] += m[a][b];
+  }
+  const T inv = T(1) / T(nperm);
+  const size_t base = (size_t(s) * 40 + j) * 9;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) S::template store<T>(Wout + base + a * 3 + b, inv * acc[a][b]);
+}
+
+}  // namespace dsl

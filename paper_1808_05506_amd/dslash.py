@@ -1,0 +1,278 @@
+"""Python binding of ``libdslash.so`` (ctypes).
+
+Argument marshalling only: shape, dtype, device and contiguity checks, then
+one call into the C ABI (``include/dslash.h``) on the caller's current HIP
+stream.  Every arithmetic step runs in the library's HIP kernels; there is no
+host fallback, and a missing library raises at import of this module.
+
+Tensor conventions (lattice dims = (Nx, Ny, Nz, Nt), site index slowest):
+
+* links ``U``:  ``[Nt, Nz, Ny, Nx, 4, 3, 3]`` (Brillouin: ``[..., 40, 3, 3]``)
+* Wilson / Brillouin spinors: ``[Nt, Nz, Ny, Nx, 4, 3, Nv]``
+* staggered spinors: ``[Nt, Nz, Ny, Nx, 3, Nv]``
+* complex64 / complex128 tensors, or for 16-bit storage real ``bfloat16`` /
+  ``float16`` tensors with a trailing dimension 2 holding (re, im).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
+    "backward", "brillouin_links", "convert", "solve", "dslash", "op_code",
+]
+
+STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
+C64, C128, BF16, F16 = 0, 1, 2, 3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libdslash.so")
+
+
+def _load():
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    vp, ip, i, d, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.dslash_apply.argtypes = [i, vp, vp, vp, ip, i, i, d, i, vp]
+    lib.dslash_apply_adjoint.argtypes = [i, vp, vp, vp, ip, i, i, d, i, vp]
+    lib.dslash_backward.argtypes = [i, vp, vp, vp, vp, vp, ip, i, i, d, i, vp]
+    lib.dslash_brillouin_links.argtypes = [vp, vp, ip, i, i, vp]
+    lib.dslash_convert.argtypes = [vp, i, vp, i, sz, vp]
+    lib.dslash_solve_workspace_bytes.argtypes = [i, ip, i, i, i]
+    lib.dslash_solve_workspace_bytes.restype = sz
+    lib.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                                 ctypes.POINTER(ctypes.c_double), ip, vp]
+    lib.dslash_status_string.restype = ctypes.c_char_p
+    lib.dslash_last_error.restype = ctypes.c_char_p
+    for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
+                 "dslash_convert", "dslash_solve", "dslash_version"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+class DslashError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.dslash_status_string(code).decode()
+        detail = _lib.dslash_last_error().decode()
+        super().__init__(f"{where}: {msg} ({detail})")
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise DslashError(rc, where)
+
+
+def op_code(op) -> int:
+    names = {"staggered": STAGGERED, "wilson": WILSON, "brillouin": BRILLOUIN}
+    if isinstance(op, str):
+        if op not in names:
+            raise ValueError(f"unknown operator {op!r}")
+        return names[op]
+    if op in (STAGGERED, WILSON, BRILLOUIN):
+        return int(op)
+    raise ValueError(f"unknown operator {op!r}")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.bfloat16 and t.shape[-1] == 2:
+        return BF16
+    if t.dtype == torch.float16 and t.shape[-1] == 2:
+        return F16
+    raise ValueError(f"unsupported tensor dtype {t.dtype} (shape {tuple(t.shape)})")
+
+
+def _core_shape(t: torch.Tensor) -> tuple:
+    """Shape without the trailing (re, im) axis of 16-bit storage."""
+    return tuple(t.shape[:-1]) if _dtype_code(t) in (BF16, F16) else tuple(t.shape)
+
+
+def _dims_c(shape) -> ctypes.Array:
+    nt, nz, ny, nx = shape[:4]
+    return (ctypes.c_int * 4)(nx, ny, nz, nt)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _require(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _spinor_shape(op: int, lat, nv: int) -> tuple:
+    return tuple(lat) + ((3, nv) if op == STAGGERED else (4, 3, nv))
+
+
+def _validate(op: int, U: torch.Tensor, psi: torch.Tensor):
+    _require(U, "U")
+    _require(psi, "psi")
+    if _dtype_code(U) != _dtype_code(psi):
+        raise ValueError(f"U and psi must have the same storage dtype ({U.dtype} vs {psi.dtype})")
+    if U.device != psi.device:
+        raise ValueError("U and psi must be on the same device")
+    us, ps = _core_shape(U), _core_shape(psi)
+    nl = 40 if op == BRILLOUIN else 4
+    if len(us) != 7 or us[4:] != (nl, 3, 3):
+        raise ValueError(f"U must have shape [Nt,Nz,Ny,Nx,{nl},3,3], got {us}")
+    nv = ps[-1]
+    if ps != _spinor_shape(op, us[:4], nv):
+        raise ValueError(f"psi shape {ps} does not match U {us} for this operator")
+    return us[:4], nv
+
+
+def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """out = D psi (or D^dag psi); no autograd (see ``dslash``)."""
+    op = op_code(op)
+    lat, nv = _validate(op, U, psi)
+    if out is None:
+        out = torch.empty_like(psi)
+    else:
+        _require(out, "out")
+        if out.shape != psi.shape or out.dtype != psi.dtype:
+            raise ValueError("out must match psi in shape and dtype")
+    fn = _lib.dslash_apply_adjoint if adjoint else _lib.dslash_apply
+    _check(fn(op, _ptr(U), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass), _dtype_code(psi),
+              _stream(psi)), "dslash_apply")
+    return out
+
+
+def apply_adjoint(op, U, psi, mass: float = 0.0, out=None):
+    return apply(op, U, psi, mass, adjoint=True, out=out)
+
+
+def backward(op, U: torch.Tensor, grad_out: torch.Tensor, psi: torch.Tensor, mass: float = 0.0,
+             need_grad_U: bool = True, need_grad_in: bool = True):
+    """(grad_U, grad_in) of out = D[U] psi for upstream gradient grad_out."""
+    op = op_code(op)
+    lat, nv = _validate(op, U, psi)
+    _require(grad_out, "grad_out")
+    if grad_out.shape != psi.shape or grad_out.dtype != psi.dtype:
+        raise ValueError("grad_out must match psi in shape and dtype")
+    gU = torch.empty_like(U) if need_grad_U else None
+    gi = torch.empty_like(psi) if need_grad_in else None
+    _check(_lib.dslash_backward(op, _ptr(U), _ptr(grad_out), _ptr(psi),
+                                _ptr(gU) if gU is not None else None, _ptr(gi) if gi is not None else None,
+                                _dims_c(lat), 3, nv, float(mass), _dtype_code(psi), _stream(psi)), "dslash_backward")
+    return gU, gi
+
+
+def brillouin_links(V: torch.Tensor) -> torch.Tensor:
+    """Stored off-axis links W [Nt,Nz,Ny,Nx,40,3,3] of V (Tab. 1)."""
+    _require(V, "V")
+    vs = _core_shape(V)
+    if len(vs) != 7 or vs[4:] != (4, 3, 3):
+        raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
+    W = torch.empty(vs[:4] + (40, 3, 3), dtype=V.dtype, device=V.device)
+    _check(_lib.dslash_brillouin_links(_ptr(V), _ptr(W), _dims_c(vs), 3, _dtype_code(V), _stream(V)),
+           "dslash_brillouin_links")
+    return W
+
+
+_TORCH_OF = {C64: (torch.complex64, False), C128: (torch.complex128, False),
+             BF16: (torch.bfloat16, True), F16: (torch.float16, True)}
+_NAMES = {"c64": C64, "c128": C128, "bf16": BF16, "f16": F16}
+
+
+def convert(x: torch.Tensor, dtype: str) -> torch.Tensor:
+    """Copy x into storage ``dtype`` ('c64', 'c128', 'bf16', 'f16'), rounding to nearest even."""
+    _require(x, "x")
+    dst_code = _NAMES[dtype]
+    src_code = _dtype_code(x)
+    core = _core_shape(x)
+    tdt, pair = _TORCH_OF[dst_code]
+    out = torch.empty(core + ((2,) if pair else ()), dtype=tdt, device=x.device)
+    n = 1
+    for s in core:
+        n *= s
+    _check(_lib.dslash_convert(_ptr(x), src_code, _ptr(out), dst_code, n, _stream(x)), "dslash_convert")
+    return out
+
+
+def solve(op, U: torch.Tensor, b: torch.Tensor, mass: float, inner: str = "bf16", tol: float = 1e-10,
+          inner_tol: float = 0.05, max_outer: int = 100, max_inner: int = 20000, x0: torch.Tensor | None = None):
+    """Solve D x = b by FP64 defect correction around a low-precision CG on D^dag D.
+
+    U, b: complex128.  Returns (x, info) with info = {relres: per-column FP64
+    ||b - D x||/||b||, inner_iters, outer_iters, status}.  Raises on argument
+    errors; non-convergence is reported in info['status'] (5).
+    """
+    op = op_code(op)
+    lat, nv = _validate(op, U, b)
+    if U.dtype != torch.complex128:
+        raise ValueError("solve takes complex128 links and right-hand sides")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    code = _NAMES[inner]
+    dims = _dims_c(lat)
+    nbytes = _lib.dslash_solve_workspace_bytes(op, dims, 3, nv, code)
+    if nbytes == 0:
+        raise ValueError(f"unsupported solver configuration (inner={inner})")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    relres = (ctypes.c_double * nv)()
+    iters = (ctypes.c_int * 2)()
+    rc = _lib.dslash_solve(op, _ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
+                           float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
+                           _stream(b))
+    if rc not in (0, 5):
+        raise DslashError(rc, "dslash_solve")
+    return x, {"relres": list(relres), "inner_iters": iters[0], "outer_iters": iters[1], "status": rc}
+
+
+class _DslashFn(torch.autograd.Function):
+    """out = D[U] psi (or D^dag psi) with the hand-written backward of the library.
+
+    Forward op:  grad_psi = D^dag g,  grad_U = link gradient of Re<g, D psi>.
+    Adjoint op:  Re<g, D^dag psi> = Re<psi, D g>, so grad_psi = D g and
+                 grad_U = link gradient with the roles of g and psi swapped.
+    """
+
+    @staticmethod
+    def forward(ctx, op, U, psi, mass, adjoint):
+        ctx.op, ctx.mass, ctx.adjoint = op, mass, adjoint
+        ctx.save_for_backward(U, psi)
+        return apply(op, U, psi, mass, adjoint)
+
+    @staticmethod
+    def backward(ctx, g):
+        U, psi = ctx.saved_tensors
+        g = g.contiguous()
+        need_u, need_psi = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        gU = gpsi = None
+        if not ctx.adjoint:
+            gU, gpsi = backward(ctx.op, U, g, psi, ctx.mass, need_u, need_psi)
+        else:
+            if need_u:
+                gU, _ = backward(ctx.op, U, psi, g, ctx.mass, True, False)
+            if need_psi:
+                gpsi = apply(ctx.op, U, g, ctx.mass, adjoint=False)
+        return None, gU, gpsi, None, None
+
+
+def dslash(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False) -> torch.Tensor:
+    """Autograd-aware D psi (complex64 / complex128; links: staggered and Wilson)."""
+    return _DslashFn.apply(op_code(op), U, psi, float(mass), bool(adjoint))

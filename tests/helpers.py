@@ -40,3 +40,25 @@ def read_golden(name):
             if line and not line.startswith("#"):
                 rows.append(line.split())
     return rows
+
+
+def bf16_bits(a):
+    """Round complex a to bfloat16 (RNE) on the host; returns uint16 [..., 2]."""
+    f = np.stack([a.real, a.imag], -1).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return u
+
+
+def from_bf16_bits(u):
+    f = (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return f[..., 0] + 1j * f[..., 1]
+
+
+def f16_pairs(a):
+    return np.stack([a.real, a.imag], -1).astype(np.float32).astype(np.float16)
+
+
+def from_f16_pairs(h):
+    h = h.astype(np.float64)
+    return h[..., 0] + 1j * h[..., 1]

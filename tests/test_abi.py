@@ -1,0 +1,118 @@
+"""C ABI: exported symbols and synchronous argument validation (no GPU needed:
+every call here fails validation before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dslash.h")
+LIB = os.path.join(ROOT, "paper_1808_05506_amd", "libdslash.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdslash.so not built")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    l = ctypes.CDLL(LIB)
+    l.dslash_last_error.restype = ctypes.c_char_p
+    l.dslash_status_string.restype = ctypes.c_char_p
+    vp, ip, i, d, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    l.dslash_apply.argtypes = [i, vp, vp, vp, ip, i, i, d, i, vp]
+    l.dslash_apply_adjoint.argtypes = [i, vp, vp, vp, ip, i, i, d, i, vp]
+    l.dslash_backward.argtypes = [i, vp, vp, vp, vp, vp, ip, i, i, d, i, vp]
+    l.dslash_brillouin_links.argtypes = [vp, vp, ip, i, i, vp]
+    l.dslash_convert.argtypes = [vp, i, vp, i, sz, vp]
+    l.dslash_solve_workspace_bytes.argtypes = [i, ip, i, i, i]
+    l.dslash_solve_workspace_bytes.restype = sz
+    l.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                               ctypes.POINTER(ctypes.c_double), ip, vp]
+    return l
+
+
+def _dims(*d):
+    return (ctypes.c_int * 4)(*d)
+
+
+def test_exports_every_declared_symbol(lib):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
+    assert len(declared) == 10
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.dslash_version() == 100
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.dslash_status_string(code)
+    assert lib.dslash_status_string(99) == b"unknown status"
+
+
+A, B, C = 0x10000, 0x4000000, 0x8000000   # fake device addresses, never dereferenced
+
+
+@pytest.mark.parametrize("fn", ["dslash_apply", "dslash_apply_adjoint"])
+def test_apply_validation(lib, fn):
+    f = getattr(lib, fn)
+    d = _dims(4, 4, 4, 4)
+    assert f(1, None, B, C, d, 3, 12, 0.1, 0, None) == 1            # NULL U
+    assert f(1, A, B, C, None, 3, 12, 0.1, 0, None) == 1            # NULL dims
+    assert f(7, A, B, C, d, 3, 12, 0.1, 0, None) == 1               # bad op
+    assert f(1, A, B, C, d, 3, 12, 0.1, 9, None) == 1               # bad dtype
+    assert f(1, A, B, C, d, 3, 0, 0.1, 0, None) == 1                # Nv < 1
+    assert f(1, A, B, C, _dims(4, 1, 4, 4), 3, 2, 0.1, 0, None) == 1  # extent < 2
+    assert f(1, A, B, C, d, 2, 12, 0.1, 0, None) == 2               # Nc != 3
+    assert f(0, A, B, C, _dims(4, 3, 4, 4), 3, 2, 0.0, 0, None) == 1  # odd extent, staggered
+    assert b"even" in lib.dslash_last_error()
+    assert f(1, A, B, B, d, 3, 12, 0.1, 0, None) == 3               # in == out
+    assert f(1, A, B, B + 64, d, 3, 12, 0.1, 0, None) == 3          # overlapping out
+    assert f(1, B + 8, A, B, d, 3, 12, 0.1, 0, None) == 3           # out overlaps U
+    assert f(1, A, B, C, _dims(2048, 2048, 1024, 2), 3, 1, 0.1, 0, None) == 1  # volume >= 2^31
+
+
+def test_backward_validation(lib):
+    d = _dims(4, 4, 4, 4)
+    assert lib.dslash_backward(1, A, None, B, C, 0, d, 3, 2, 0.1, 0, None) == 1       # NULL grad_out
+    assert lib.dslash_backward(1, A, B, C, 0x9000000, 0, d, 3, 2, 0.1, 2, None) == 2  # bf16 backward
+    assert lib.dslash_backward(2, A, B, C, 0x9000000, 0, d, 3, 2, 0.1, 0, None) == 2  # Brillouin grad_U
+    assert lib.dslash_backward(1, A, B, C, None, B, d, 3, 2, 0.1, 0, None) == 3       # grad_in == grad_out
+    assert lib.dslash_backward(1, A, B, C, C, None, d, 3, 2, 0.1, 0, None) == 3       # grad_U == in
+
+
+def test_links_convert_validation(lib):
+    d = _dims(4, 4, 4, 4)
+    assert lib.dslash_brillouin_links(None, B, d, 3, 0, None) == 1
+    assert lib.dslash_brillouin_links(A, B, d, 3, 2, None) == 2
+    assert lib.dslash_brillouin_links(A, A, d, 3, 0, None) == 3
+    assert lib.dslash_convert(A, 0, B, 7, 10, None) == 1
+    assert lib.dslash_convert(A, 0, A, 1, 10, None) == 3
+    assert lib.dslash_convert(None, 0, None, 1, 0, None) == 0    # n == 0 is a no-op
+
+
+def test_solve_validation(lib):
+    d = _dims(4, 4, 4, 4)
+    assert lib.dslash_solve_workspace_bytes(1, d, 3, 2, 2) > 0
+    assert lib.dslash_solve_workspace_bytes(1, d, 3, 2, 1) == 0   # C128 inner not allowed
+    assert lib.dslash_solve_workspace_bytes(1, d, 4, 2, 2) == 0
+    rel = (ctypes.c_double * 2)()
+    it = (ctypes.c_int * 2)()
+    ws_need = lib.dslash_solve_workspace_bytes(1, d, 3, 2, 2)
+    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, None, 0, rel, it, None) == 6
+    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, 0x20000000, ws_need - 1, rel, it, None) == 6
+    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, -1.0, 0.1, 10, 100, 0x20000000, ws_need, rel, it, None) == 1
+    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 1.5, 10, 100, 0x20000000, ws_need, rel, it, None) == 1
+    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 0, 1e-10, 0.1, 0, 100, 0x20000000, ws_need, rel, it, None) == 1
+    assert lib.dslash_solve(1, A, B, B, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, 0x20000000, ws_need, rel, it, None) == 3
+
+
+def test_binding_rejects_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    from paper_1808_05506_amd import dslash as D
+    u = torch.zeros(2, 2, 2, 2, 4, 3, 3, dtype=torch.complex64)
+    p = torch.zeros(2, 2, 2, 2, 4, 3, 1, dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        D.apply("wilson", u, p, 0.1)
+    with pytest.raises(ValueError):
+        D.op_code("clover")

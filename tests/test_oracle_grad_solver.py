@@ -94,3 +94,12 @@ def test_local_link_grad(op):
     G = grad.link_grad(op, chi, psi)
     for mu in range(4):
         assert np.abs(local.link_grad_at(op, chi, psi, sites, mu) - G[idx][:, mu]).max() < 1e-13
+
+
+@pytest.mark.parametrize("op", ["staggered", "wilson"])
+def test_local_fd_matches_full_fd(op):
+    u, chi, psi = _fields(op, 40)
+    links = [(1, 0, 1, 3, 0, 2, 1), (3, 1, 0, 0, 3, 0, 0), (0, 1, 1, 2, 1, 1, 2), (2, 0, 0, 1, 2, 2, 2)]
+    full = grad.fd_link_grad(op, u, chi, psi, links, mass=0.2)
+    for n, l in enumerate(links):
+        assert abs(local.fd_link_grad_local(op, u, chi, psi, 0.2, l) - full[n]) < 1e-12 * abs(full[n]) + 1e-14
