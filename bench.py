@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--rotate", type=int, default=4)
     ap.add_argument("--rows", choices=["all", "none"], default="all")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain FP32 complex copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -256,6 +258,22 @@ def main():
     dims, nv, m0 = (16, 16, 16, 32), 12, 0.1
     dev = torch.device("cuda:0")
     log(f"device: {torch.cuda.get_device_name(0)}")
+    copy_row = None
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.zeros(n, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        import ctypes
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def copy(i):
+            rc = D._lib.dslash_convert(ctypes.c_void_p(src.data_ptr()), 0, ctypes.c_void_p(dst.data_ptr()), 0, n, stream)
+            if rc:
+                raise RuntimeError(f"dslash_convert failed: {rc}")
+        tc = timed(torch, copy, 10, 2)
+        copy_row = {"bytes_read": n * 8, "bytes_written": n * 8, "us": tc * 1e6, "gbs": 16 * n / tc / 1e9}
+        log(f"copy {args.calibrate_copy} MiB: {tc * 1e6:.1f} us, {16 * n / tc / 1e9:.0f} GB/s (read + write)")
+        del src, dst
     u = synthetic.gauge_links(dims, "smooth", 1)
     p = synthetic.wilson_spinor(dims, nv, 101)
     U = torch.from_numpy(u.astype(np.complex64)).to(dev)
@@ -295,6 +313,8 @@ def main():
         "cpu_baseline": cpu,
         "rows": rows,
     }
+    if copy_row:
+        out["copy_calibration"] = copy_row
     print(json.dumps(out), flush=True)
 
 
