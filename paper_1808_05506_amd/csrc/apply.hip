@@ -49,33 +49,73 @@ Shape site_v_shape(uint32_t vol, int nv) {
   return sh;
 }
 
+// Launch configuration of the (site, right-hand side) kernels: thread shape,
+// row-chunk traversal (used when one x-row chunk fills at least two waves),
+// and whether workgroups are regrouped per XCD.  DSLASH_TBAND (t-band width,
+// default 8) and DSLASH_XCD (0/1, default 1) are tuning overrides.
+struct Launch {
+  Shape sh;
+  bool rows;
+  bool xcd;
+  RowTraversal tr;
+};
+
+static Launch make_launch(const Geom& g) {
+  Launch L;
+  L.sh = site_v_shape(g.vol, g.nv);
+  const uint32_t vc = L.sh.block.x;
+  uint32_t sb = L.sh.block.y;
+  if (sb > uint32_t(g.n[0])) sb = g.n[0];
+  L.rows = sb * vc >= 128;
+  int bt = 8;
+  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  L.xcd = true;
+  if (const char* e = getenv("DSLASH_XCD")) L.xcd = atoi(e) != 0;
+  if (L.rows) {
+    L.tr = make_row_traversal(g, sb, uint32_t(bt > 0 ? bt : 1));
+    L.sh.block.y = sb;
+    L.sh.grid.x = L.tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]);
+  }
+  return L;
+}
+
 template <int OP, bool ADJ, class S, class T>
-__global__ void __launch_bounds__(256) apply_kernel(Geom g, const typename S::word* __restrict__ U,
+__global__ void __launch_bounds__(256) apply_kernel(Geom g, RowTraversal tr, int rows, int xcd,
+                                                   const typename S::word* __restrict__ U,
                                                    const typename S::word* __restrict__ in,
                                                    typename S::word* __restrict__ out, T mass) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t s = lb * blockDim.y + threadIdx.y;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const int v = blockIdx.y * blockDim.x + threadIdx.x;
-  if (s >= g.vol || v >= g.nv) return;
+  uint32_t s;
+  bool live;
+  SiteNbr nb;
+  if (rows) {
+    nb = row_site(g, tr, lb, threadIdx.y, s, live);
+  } else {
+    s = lb * blockDim.y + threadIdx.y;
+    live = s < g.vol;
+    if (live) nb = site_nbr(g, s);
+  }
+  if (!live || v >= g.nv) return;
   if (OP == OP_STAGGERED)
-    staggered_site<ADJ, S, T>(g, U, in, out, s, v, mass);
+    staggered_site<ADJ, S, T>(g, U, in, out, s, nb, v, mass);
   else if (OP == OP_WILSON)
-    wilson_site<ADJ, S, T>(g, U, in, out, s, v, T(4) + mass);
+    wilson_site<ADJ, S, T>(g, U, in, out, s, nb, v, T(4) + mass);
   else
-    brillouin_site<ADJ, S, T>(g, U, in, out, s, v, mass + T(15.0 / 8.0));
+    brillouin_site<ADJ, S, T>(g, U, in, out, s, nb, v, mass + T(15.0 / 8.0));
 }
 
 template <int OP, class S, class T>
 static hipError_t apply_t(bool adj, const Geom& g, const void* U, const void* in, void* out, double mass,
                           hipStream_t st) {
   using W = typename S::word;
-  const Shape sh = site_v_shape(g.vol, g.nv);
+  const Launch L = make_launch(g);
   if (adj)
-    hipLaunchKernelGGL((apply_kernel<OP, true, S, T>), sh.grid, sh.block, 0, st, g, (const W*)U, (const W*)in,
-                       (W*)out, T(mass));
+    hipLaunchKernelGGL((apply_kernel<OP, true, S, T>), L.sh.grid, L.sh.block, 0, st, g, L.tr, int(L.rows),
+                       int(L.xcd), (const W*)U, (const W*)in, (W*)out, T(mass));
   else
-    hipLaunchKernelGGL((apply_kernel<OP, false, S, T>), sh.grid, sh.block, 0, st, g, (const W*)U, (const W*)in,
-                       (W*)out, T(mass));
+    hipLaunchKernelGGL((apply_kernel<OP, false, S, T>), L.sh.grid, L.sh.block, 0, st, g, L.tr, int(L.rows),
+                       int(L.xcd), (const W*)U, (const W*)in, (W*)out, T(mass));
   return hipGetLastError();
 }
 
@@ -95,7 +135,11 @@ hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* 
                         double mass, hipStream_t st) {
   switch (op) {
     case OP_STAGGERED: return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, mass, st);
-    case OP_WILSON: return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, mass, st);
+    case OP_WILSON: {
+      const hipError_t e = launch_wilson_rows(adj, dtype, g, U, in, out, mass, st);
+      if (e != hipErrorNotSupported) return e;
+      return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, mass, st);
+    }
     case OP_BRILLOUIN: return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, mass, st);
   }
   return hipErrorInvalidValue;

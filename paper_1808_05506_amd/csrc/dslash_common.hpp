@@ -183,9 +183,78 @@ DSL_HD SiteNbr site_nbr(const Geom& g, uint32_t s) {
   return r;
 }
 
+// Row traversal.  A workgroup owns one chunk of `sb` consecutive sites of an
+// x-row, so y, z, t and the y/z/t neighbour offsets are uniform across it.
+// Rows are visited plane by plane (all chunks and y of one (z, t)), and the
+// (z, t) planes in bands of `bt` time slices: t fastest inside a band, then z,
+// then the next band.  A site's z- and t-neighbour rows are then at most
+// bt planes away in visiting order, which keeps them inside the L2 of the XCD
+// that needs them (a plain lexicographic walk puts the t-neighbours a whole
+// time slice away).
+struct RowTraversal {
+  uint32_t sb, chunks;       // sites per chunk, chunks per x-row
+  uint32_t rows_plane;       // Ny * chunks
+  uint32_t bt, band_planes;  // band width in t, planes per full band (bt * Nz)
+  uint32_t nbands, btlast;   // number of bands, width of the last band
+  FastDiv d_plane, d_chunks, d_band, d_bt, d_btlast;
+};
+
+inline RowTraversal make_row_traversal(const Geom& g, uint32_t sb, uint32_t bt) {
+  RowTraversal r;
+  r.sb = sb;
+  r.chunks = (uint32_t(g.n[0]) + sb - 1) / sb;
+  r.rows_plane = uint32_t(g.n[1]) * r.chunks;
+  if (bt < 1) bt = 1;
+  if (bt > uint32_t(g.n[3])) bt = g.n[3];
+  r.bt = bt;
+  r.band_planes = bt * uint32_t(g.n[2]);
+  r.nbands = (uint32_t(g.n[3]) + bt - 1) / bt;
+  r.btlast = uint32_t(g.n[3]) - bt * (r.nbands - 1);
+  r.d_plane = FastDiv::make(r.rows_plane);
+  r.d_chunks = FastDiv::make(r.chunks);
+  r.d_band = FastDiv::make(r.band_planes);
+  r.d_bt = FastDiv::make(bt);
+  r.d_btlast = FastDiv::make(r.btlast);
+  return r;
+}
+
+DSL_HD SiteNbr nbr_from_coords(const Geom& g, int x, int y, int z, int t) {
+  SiteNbr r;
+  r.c[0] = x;
+  r.c[1] = y;
+  r.c[2] = z;
+  r.c[3] = t;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int wrap = (g.n[mu] - 1) * g.stride[mu];
+    r.fwd[mu] = (r.c[mu] == g.n[mu] - 1) ? -wrap : g.stride[mu];
+    r.bwd[mu] = (r.c[mu] == 0) ? wrap : -g.stride[mu];
+  }
+  return r;
+}
+
+// Site of lane `xi` of logical row-chunk block L; live = false past the row end.
+DSL_HD SiteNbr row_site(const Geom& g, const RowTraversal& tr, uint32_t L, uint32_t xi, uint32_t& s, bool& live) {
+  const uint32_t p = tr.d_plane.div(L);
+  const uint32_t rin = L - p * tr.rows_plane;
+  const uint32_t y = tr.d_chunks.div(rin);
+  const uint32_t chunk = rin - y * tr.chunks;
+  const uint32_t band = tr.d_band.div(p);
+  const uint32_t q = p - band * tr.band_planes;
+  const bool last = band + 1 == tr.nbands;
+  const uint32_t z = last ? tr.d_btlast.div(q) : tr.d_bt.div(q);
+  const uint32_t tt = q - z * (last ? tr.btlast : tr.bt);
+  const uint32_t t = band * tr.bt + tt;
+  const uint32_t x = chunk * tr.sb + xi;
+  live = x < uint32_t(g.n[0]);
+  s = x + uint32_t(g.n[0]) * (y + uint32_t(g.n[1]) * (z + uint32_t(g.n[2]) * t));
+  return nbr_from_coords(g, int(x), int(y), int(z), int(t));
+}
+
 // Hardware dispatches workgroup b to XCD b % 8.  Map the first 8*floor(nb/8)
 // workgroups so that XCD k receives a contiguous range of logical blocks.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, bool on = true) {
+  if (!on) return b;
   const uint32_t per = nb >> 3;
   if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
   return b;

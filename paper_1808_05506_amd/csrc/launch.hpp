@@ -26,6 +26,8 @@ Shape site_v_shape(uint32_t vol, int nv);
 
 hipError_t launch_apply(int op, bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
                         double mass, hipStream_t st);
+hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
+                              double mass, hipStream_t st);
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st);

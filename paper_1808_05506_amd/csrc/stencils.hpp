@@ -116,10 +116,9 @@ DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S:
 template <bool ADJ, class S, class T>
 DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
-                        uint32_t s, int v, T diag) {
+                        uint32_t s, const SiteNbr& nb, int v, T diag) {
   constexpr int CF = ADJ ? +1 : -1;  // forward projector 1 + CF gamma
   constexpr int CB = -CF;            // backward projector 1 + CB gamma
-  const SiteNbr nb = site_nbr(g, s);
   const int nv = g.nv;
   const size_t sps = size_t(12) * nv;  // complex numbers per site of a spinor block
   cpx<T> acc[4][3];
@@ -160,8 +159,7 @@ DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
 template <bool ADJ, class S, class T>
 DSL_HD void staggered_site(const Geom& g, const typename S::word* __restrict__ U,
                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
-                           uint32_t s, int v, T mass) {
-  const SiteNbr nb = site_nbr(g, s);
+                           uint32_t s, const SiteNbr& nb, int v, T mass) {
   const int nv = g.nv;
   const size_t sps = size_t(3) * nv;
   cpx<T> acc[3] = {zero<T>(), zero<T>(), zero<T>()};
@@ -255,8 +253,7 @@ template <class T> DSL_HD cpx<T> cmadd_ab(cpx<T> acc, T alpha, T beta, cpx<T> y)
 template <bool ADJ, class S, class T>
 DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W,
                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
-                           uint32_t s, int v, T diag) {
-  const SiteNbr nb = site_nbr(g, s);
+                           uint32_t s, const SiteNbr& nb, int v, T diag) {
   const int nv = g.nv;
   const size_t sps = size_t(12) * nv;
   cpx<T> acc[4][3];

@@ -190,3 +190,37 @@ def test_errors_raise():
         D.apply("wilson", U, P, 0.1, out=P)       # in == out
     with pytest.raises(ValueError):
         D.apply("staggered", U, P, 0.1)           # wrong spinor shape for the op
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16", "f16"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("dims", [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (32, 2, 3, 2)])
+def test_wilson_row_staged_path(dt, adj, dims):
+    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged kernel; 20 and
+    # 32 sites split into chunks (a partial one for 20)
+    nv = 12
+    say(f"case wilson rows {dims} nv={nv} {dt} adj={adj}")
+    u, p = _wil_fields(dims, nv, 81, 82, dt, "haar")
+    out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), wilson.apply(u, p, 0.1, adj), dt, "D_W rows")
+
+
+def test_row_staged_determinism_across_chunk_sizes():
+    dims, nv = (22, 4, 4, 4), 12
+    u, p = _wil_fields(dims, nv, 91, 92, "c64")
+    U, P = up(u, "c64"), up(p, "c64")
+    outs = []
+    old = os.environ.get("DSLASH_ROW_SITES")
+    try:
+        for r in ("11", "16", "21"):
+            os.environ["DSLASH_ROW_SITES"] = r
+            say(f"case rows determinism R={r}")
+            outs.append(D.apply("wilson", U, P, 0.1).cpu())
+    finally:
+        if old is None:
+            os.environ.pop("DSLASH_ROW_SITES", None)
+        else:
+            os.environ["DSLASH_ROW_SITES"] = old
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), wilson.apply(u, p, 0.1), "c64", "D_W rows R sweep")
