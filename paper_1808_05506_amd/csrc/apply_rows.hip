@@ -38,14 +38,13 @@ __device__ __forceinline__ void copy_pieces(void* __restrict__ dst, const void* 
 }
 
 // LDS layout, in storage words (one complex number each):
-//   own  [(R + 2) * 12 NV]  sites x0 - 1 .. x0 + n of the chunk's row (index x - x0 + 1)
-//   nbr  [R * 12 NV]        the current neighbour row's x0 .. x0 + n - 1; reused for the output
+//   buf  [(R + 2) * 12 NV]  one staged row at index x - x0 + 1: a neighbour row
+//                           fills 1 .. n, the chunk's own row 0 .. n + 1 (with
+//                           the halo sites x0 - 1 and x0 + n); reused for the output
 //   lown [(R + 1) * 36]     links of sites x0 - 1 .. x0 + n - 1 (index x - x0 + 1)
 //   lnb  [R * 9]            V_mu of the backward neighbour row (current mu)
-template <int NV>
-DSL_HD size_t rows_lds_words(int R) {
-  return size_t(R + 2) * 12 * NV + size_t(R) * 12 * NV + size_t(R + 1) * 36 + size_t(R) * 9;
-}
+template <int NV, class S>
+size_t rows_lds_words(int R);
 
 template <class S, class T, int NV>
 DSL_HD void lds_spinor(const typename S::word* __restrict__ site, int v, cpx<T> (&p)[4][3]) {
@@ -83,20 +82,45 @@ struct RowPieces {
   static constexpr int CH = 12 * int(sizeof(typename S::word)) / 16;
 };
 
+// LDS stride of one site in the row buffer, in storage words.  For a fixed
+// spin-colour component the lanes of one site read a window of N_v words;
+// consecutive sites are placed so that their windows fall on consecutive LDS
+// banks (stride = window mod 64 dwords), which makes the per-component reads
+// of a wave conflict-free.  The unpadded stride (12 N_v words) is a multiple
+// of 64 dwords for FP32 N_v = 12 and would put every site on the same banks.
+// Padding is skipped when it would cost more than a quarter of the row.
+template <int NV, class S>
+struct SiteStride {
+  static constexpr int WB = int(sizeof(typename S::word));
+  static constexpr int SWD = 12 * NV * WB / 4;                // dwords per site, unpadded
+  static constexpr int WIN = NV * WB / 4;                     // dwords per component window
+  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
+  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % 16 == 0) ? SWD + PAD : SWD;
+  static constexpr int WORDS = DW * 4 / WB;                   // site stride in storage words
+  static constexpr int PIECES = DW * 4 / 16;                  // site stride in 16-byte pieces
+};
+
+template <int NV, class S>
+size_t rows_lds_words(int R) {
+  return size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R + 1) * 36 + size_t(R) * 9;
+}
+
+// Piece assignment of a staged row: lane (x, v) of the workgroup moves the
+// pieces j * N_v + v (j = 0 .. CH - 1) of site x of the run, so the N_v lanes
+// of a site read N_v consecutive 16-byte pieces per instruction and the LDS
+// position follows from the site without a division.  Lanes past a partial
+// chunk's end repeat the last site (same data to the same place).
 template <int MU, int SGN, int NV, class S>
 __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
-                                          const typename S::word* __restrict__ in, int tid, int nth,
+                                          const typename S::word* __restrict__ in, int xl, int v, int tid,
                                           u32x4 (&r)[RowPieces<S>::CH + 1]) {
   using W = typename S::word;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   const uint32_t nrow = row_base_shift(g, c, MU, SGN) + uint32_t(c.x0);
-  const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(nrow) * SW);
-  const int pieces = c.n * SW * int(sizeof(W)) / 16;
+  const int xc = xl < c.n ? xl : c.n - 1;
+  const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(nrow + xc) * SW);
 #pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    const int i = tid + j * nth;
-    r[j] = src[i < pieces ? i : pieces - 1];
-  }
+  for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
   if (SGN < 0) {
     const int w = tid < c.n * 9 ? tid : c.n * 9 - 1;
     const int k = w / 9, e = w - k * 9;
@@ -109,16 +133,13 @@ __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, cons
 
 template <int SGN, int NV, class S>
 __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
-                                           typename S::word* nbr, typename S::word* lnb, int tid, int nth) {
+                                           typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
   using W = typename S::word;
-  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
-  u32x4* dst = reinterpret_cast<u32x4*>(nbr);
-  const int pieces = c.n * SW * int(sizeof(W)) / 16;
+  constexpr int CH = RowPieces<S>::CH, SSP = SiteStride<NV, S>::PIECES;
+  const int xc = xl < c.n ? xl : c.n - 1;
+  u32x4* dst = reinterpret_cast<u32x4*>(row) + xc * SSP;
 #pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    const int i = tid + j * nth;
-    dst[i < pieces ? i : pieces - 1] = r[j];
-  }
+  for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
   if (SGN < 0) {
     W lk;
     const u32x4 z = r[CH];
@@ -127,28 +148,63 @@ __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[R
   }
 }
 
+// The chunk's own row in the same register shape: CH pieces of site x and,
+// in slot CH, at most one piece of the two halo sites x0 - 1, x0 + n (2 * 12 N_v
+// words, never more pieces than threads; the launcher checks this).
+template <int NV, class S>
+__device__ __forceinline__ void own_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm,
+                                          int xp, int xl, int v, int tid, u32x4 (&r)[RowPieces<S>::CH + 1]) {
+  using W = typename S::word;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(W)) / 16;
+  const int xc = xl < c.n ? xl : c.n - 1;
+  const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + c.x0 + xc) * SW);
+#pragma unroll
+  for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
+  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
+  const int hs = h < SP ? xm : xp;
+  r[CH] = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+}
+
+template <int NV, class S>
+__device__ __forceinline__ void own_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+                                           typename S::word* buf, int xl, int v, int tid) {
+  using W = typename S::word;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(W)) / 16;
+  constexpr int SSP = SiteStride<NV, S>::PIECES;
+  const int xc = xl < c.n ? xl : c.n - 1;
+  u32x4* dst = reinterpret_cast<u32x4*>(buf) + (xc + 1) * SSP;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
+  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
+  u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
+  hdst[h < SP ? h : h - SP] = r[CH];
+}
+
 template <int MU, int SGN, bool ADJ, int NV, class S, class T>
 __device__ __forceinline__ void row_compute(const typename S::word* nbr, const typename S::word* lown,
                                             const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
-  constexpr int SW = 12 * NV;
+  constexpr int SSW = SiteStride<NV, S>::WORDS;
   if (SGN > 0)
-    lds_hop<MU, (ADJ ? 1 : -1), false, NV, S, T>(nbr + xl * SW, lown + (xl + 1) * 36 + MU * 9, v, acc);
+    lds_hop<MU, (ADJ ? 1 : -1), false, NV, S, T>(nbr + xl * SSW, lown + (xl + 1) * 36 + MU * 9, v, acc);
   else
-    lds_hop<MU, (ADJ ? -1 : 1), true, NV, S, T>(nbr + xl * SW, lnb + xl * 9, v, acc);
+    lds_hop<MU, (ADJ ? -1 : 1), true, NV, S, T>(nbr + xl * SSW, lnb + xl * 9, v, acc);
 }
 
-template <bool ADJ, int NV, class S, class T>
-__global__ void __launch_bounds__(256) wilson_rows_kernel(Geom g, RowTraversal tr, int xcd,
-                                                         const typename S::word* __restrict__ U,
-                                                         const typename S::word* __restrict__ in,
-                                                         typename S::word* __restrict__ out, T diag) {
+// Occupancy hint per prefetch depth: deeper prefetch holds more rows in
+// registers (about 28 VGPRs per FP32 row) and runs fewer waves per SIMD.
+template <int DEPTH> struct RowsWaves { static constexpr int value = DEPTH <= 2 ? 4 : (DEPTH <= 4 ? 3 : 2); };
+
+template <int DEPTH, bool ADJ, int NV, class S, class T>
+__global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
+    wilson_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ U,
+                       const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
   using W = typename S::word;
-  constexpr int SW = 12 * NV;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
   extern __shared__ uint4 smem_rows[];
   const int R = int(tr.sb);
-  W* own = reinterpret_cast<W*>(smem_rows);
-  W* nbr = own + (R + 2) * SW;
-  W* lown = nbr + R * SW;
+  W* buf = reinterpret_cast<W*>(smem_rows);
+  W* lown = buf + (R + 2) * SSW;
   W* lnb = lown + (R + 1) * 36;
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
@@ -157,21 +213,31 @@ __global__ void __launch_bounds__(256) wilson_rows_kernel(Geom g, RowTraversal t
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
 
-  // Three neighbour rows in flight at a time: row k + 2 is requested while
-  // hop k is evaluated.  Order: +y, -y, +z, -z, +t, -t.
-  u32x4 ra[RowPieces<S>::CH + 1], rb[RowPieces<S>::CH + 1], rc[RowPieces<S>::CH + 1];
-  row_issue<1, +1, NV, S>(g, c, U, in, tid, nth, ra);
-  row_issue<1, -1, NV, S>(g, c, U, in, tid, nth, rb);
-
-  // own row with one halo site on each side, and its links
-  // (piece counts: a site's spinor is 12 NV words = RowPieces::CH pieces per
-  // right-hand side, so the row needs CH pieces per thread and a halo site at
-  // most one; a site's links are 36 words, at most 3 pieces per thread)
-  constexpr int CH = RowPieces<S>::CH;
-  constexpr int SITE_PIECES = SW * int(sizeof(W)) / 16, LINK_PIECES = 36 * int(sizeof(W)) / 16;
-  copy_pieces<CH>(own + SW, in + size_t(c.row_base + c.x0) * SW, c.n * SITE_PIECES, tid, nth);
-  copy_pieces<1>(own, in + size_t(c.row_base + xm) * SW, SITE_PIECES, tid, nth);
-  copy_pieces<1>(own + (c.n + 1) * SW, in + size_t(c.row_base + xp) * SW, SITE_PIECES, tid, nth);
+  // Seven rows pass through the one LDS row buffer: +y, -y, +z, -z, +t, -t,
+  // then the chunk's own row with its halo sites.  Row k is requested DEPTH
+  // steps before it is consumed (DEPTH = 7: all at once), each into its own
+  // register array.
+  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+#define DSL_ISSUE(K)                                                                   \
+  do {                                                                                 \
+    if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, U, in, xl, v, tid, r0);        \
+    if constexpr (K == 1) row_issue<1, -1, NV, S>(g, c, U, in, xl, v, tid, r1);        \
+    if constexpr (K == 2) row_issue<2, +1, NV, S>(g, c, U, in, xl, v, tid, r2);        \
+    if constexpr (K == 3) row_issue<2, -1, NV, S>(g, c, U, in, xl, v, tid, r3);        \
+    if constexpr (K == 4) row_issue<3, +1, NV, S>(g, c, U, in, xl, v, tid, r4);        \
+    if constexpr (K == 5) row_issue<3, -1, NV, S>(g, c, U, in, xl, v, tid, r5);        \
+    if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);             \
+  } while (0)
+  DSL_ISSUE(0);
+  if constexpr (DEPTH > 1) DSL_ISSUE(1);
+  if constexpr (DEPTH > 2) DSL_ISSUE(2);
+  if constexpr (DEPTH > 3) DSL_ISSUE(3);
+  if constexpr (DEPTH > 4) DSL_ISSUE(4);
+  if constexpr (DEPTH > 5) DSL_ISSUE(5);
+  if constexpr (DEPTH > 6) DSL_ISSUE(6);
+  // links of the chunk's sites and of the halo site x0 - 1 (at most 3 pieces
+  // per thread: a site's links are 36 words)
+  constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16;
   copy_pieces<3>(lown + 36, U + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
   copy_pieces<1>(lown, U + size_t(c.row_base + xm) * 36, LINK_PIECES, tid, nth);
 
@@ -181,60 +247,81 @@ __global__ void __launch_bounds__(256) wilson_rows_kernel(Geom g, RowTraversal t
 #pragma unroll
     for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
 
-#define DSL_ROW_STEP(MU, SGN, CUR, NMU, NSGN, NEXT)                            \
-  row_commit<SGN, NV, S>(c, CUR, nbr, lnb, tid, nth);                          \
-  __syncthreads();                                                             \
-  if (NMU > 0) row_issue<(NMU > 0 ? NMU : 1), NSGN, NV, S>(g, c, U, in, tid, nth, NEXT); \
-  row_compute<MU, SGN, ADJ, NV, S, T>(nbr, lown, lnb, xl, v, acc);             \
-  __syncthreads();
-  DSL_ROW_STEP(1, +1, ra, 2, +1, rc)
-  DSL_ROW_STEP(1, -1, rb, 2, -1, ra)
-  DSL_ROW_STEP(2, +1, rc, 3, +1, rb)
-  DSL_ROW_STEP(2, -1, ra, 3, -1, rc)
-  DSL_ROW_STEP(3, +1, rb, 0, +1, ra)
-  DSL_ROW_STEP(3, -1, rc, 0, +1, rb)
-#undef DSL_ROW_STEP
-
   // Lanes past a partial chunk's end (xl >= n) compute on stale but in-bounds
   // LDS data and their results are never copied out; keeping every lane on
   // the same straight-line path lets the compiler keep the prefetches in
   // flight across the hops.
+  W* const row = buf + SSW;  // neighbour rows sit at index 1 .. n
+#define DSL_ROW_STEP(K, MU, SGN, CUR)                                         \
+  row_commit<SGN, NV, S>(c, CUR, row, lnb, xl, v, tid);                       \
+  __syncthreads();                                                            \
+  if constexpr (K + DEPTH < 7) DSL_ISSUE(K + DEPTH);                          \
+  row_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);            \
+  __syncthreads();
+  DSL_ROW_STEP(0, 1, +1, r0)
+  DSL_ROW_STEP(1, 1, -1, r1)
+  DSL_ROW_STEP(2, 2, +1, r2)
+  DSL_ROW_STEP(3, 2, -1, r3)
+  DSL_ROW_STEP(4, 3, +1, r4)
+  DSL_ROW_STEP(5, 3, -1, r5)
+#undef DSL_ROW_STEP
+#undef DSL_ISSUE
+
+  own_commit<NV, S>(c, r6, buf, xl, v, tid);
+  __syncthreads();
+  cpx<T> res[4][3];
   {
     constexpr int CF = ADJ ? +1 : -1, CB = -CF;
     // x hops from the own row: x + 1 at index xl + 2, x - 1 (and its link) at index xl
-    lds_hop<0, CF, false, NV, S, T>(own + (xl + 2) * SW, lown + (xl + 1) * 36, v, acc);
-    lds_hop<0, CB, true, NV, S, T>(own + xl * SW, lown + xl * 36, v, acc);
-    const W* self = own + (xl + 1) * SW;
-    W* o = nbr + xl * SW;
+    lds_hop<0, CF, false, NV, S, T>(buf + (xl + 2) * SSW, lown + (xl + 1) * 36, v, acc);
+    lds_hop<0, CB, true, NV, S, T>(buf + xl * SSW, lown + xl * 36, v, acc);
+    const W* self = buf + (xl + 1) * SSW;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) {
-        const int e = (sp * 3 + cc) * NV + v;
-        cpx<T> p = S::template load<T>(self + e);
-        cpx<T> r;
-        r.r = fma(diag, p.r, T(-0.5) * acc[sp][cc].r);
-        r.i = fma(diag, p.i, T(-0.5) * acc[sp][cc].i);
-        S::template store<T>(o + e, r);
+        cpx<T> p = S::template load<T>(self + (sp * 3 + cc) * NV + v);
+        res[sp][cc].r = fma(diag, p.r, T(-0.5) * acc[sp][cc].r);
+        res[sp][cc].i = fma(diag, p.i, T(-0.5) * acc[sp][cc].i);
       }
   }
   __syncthreads();
-  copy_pieces<CH>(out + size_t(c.row_base + c.x0) * SW, nbr, c.n * SITE_PIECES, tid, nth);
+  {
+    W* o = buf + xl * SSW;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) S::template store<T>(o + (sp * 3 + cc) * NV + v, res[sp][cc]);
+  }
+  __syncthreads();
+  {
+    // copy-out with the same site-local piece assignment as the staging
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
+    u32x4 r[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
+  }
 }
 
-template <int NV, class S, class T>
+template <int DEPTH, int NV, class S, class T>
 static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* U, const void* in,
                                 void* out, double mass, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
-  const size_t lds = rows_lds_words<NV>(R) * sizeof(W);
+  size_t lds = rows_lds_words<NV, S>(R) * sizeof(W);
+  // DSLASH_ROW_LDS_EXTRA (bytes) lowers the workgroups per CU (tuning).
+  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
   if (adj)
-    hipLaunchKernelGGL((wilson_rows_kernel<true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
+    hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
                        (const W*)in, (W*)out, diag);
   else
-    hipLaunchKernelGGL((wilson_rows_kernel<false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
+    hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
                        (const W*)in, (W*)out, diag);
   return hipGetLastError();
 }
@@ -251,15 +338,24 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
   if (R > g.n[0]) R = g.n[0];
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  // the own row's two halo sites (2 * 12 N_v words) must be at most one
+  // 16-byte piece per thread
+  const int word_bytes = int(dtype_bytes(dtype));
+  if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
   int bt = 8;
   if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
   bool xcd = true;
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
-  switch (dtype) {
-    case DT_C64: return wilson_rows_t<12, C64, float>(adj, g, R, bt, xcd, U, in, out, mass, st);
-    case DT_BF16: return wilson_rows_t<12, BF16, float>(adj, g, R, bt, xcd, U, in, out, mass, st);
-    case DT_F16: return wilson_rows_t<12, F16, float>(adj, g, R, bt, xcd, U, in, out, mass, st);
+  int depth = 3;
+  if (const char* e = getenv("DSLASH_ROW_DEPTH")) depth = atoi(e);
+#define DSL_RT(D)                                                                               \
+  switch (dtype) {                                                                              \
+    case DT_C64: return wilson_rows_t<D, 12, C64, float>(adj, g, R, bt, xcd, U, in, out, mass, st);   \
+    case DT_BF16: return wilson_rows_t<D, 12, BF16, float>(adj, g, R, bt, xcd, U, in, out, mass, st); \
+    case DT_F16: return wilson_rows_t<D, 12, F16, float>(adj, g, R, bt, xcd, U, in, out, mass, st);   \
   }
+  if (depth <= 2) { DSL_RT(2) } else if (depth <= 3) { DSL_RT(3) } else { DSL_RT(7) }
+#undef DSL_RT
   return hipErrorNotSupported;
 }
 

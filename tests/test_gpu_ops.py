@@ -194,10 +194,11 @@ def test_errors_raise():
 
 @pytest.mark.parametrize("dt", ["c64", "bf16", "f16"])
 @pytest.mark.parametrize("adj", [False, True])
-@pytest.mark.parametrize("dims", [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (32, 2, 3, 2)])
+@pytest.mark.parametrize("dims", [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (12, 2, 2, 3), (32, 2, 3, 2)])
 def test_wilson_row_staged_path(dt, adj, dims):
-    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged kernel; 20 and
-    # 32 sites split into chunks (a partial one for 20)
+    # N_v = 12 with rows of >= 12 sites (>= 11 in 16-bit storage) runs the LDS
+    # row-staged kernel, shorter rows the direct kernel; 20 and 32 sites split
+    # into chunks (a partial one for 20)
     nv = 12
     say(f"case wilson rows {dims} nv={nv} {dt} adj={adj}")
     u, p = _wil_fields(dims, nv, 81, 82, dt, "haar")
@@ -212,7 +213,7 @@ def test_row_staged_determinism_across_chunk_sizes():
     outs = []
     old = os.environ.get("DSLASH_ROW_SITES")
     try:
-        for r in ("11", "16", "21"):
+        for r in ("12", "16", "21"):
             os.environ["DSLASH_ROW_SITES"] = r
             say(f"case rows determinism R={r}")
             outs.append(D.apply("wilson", U, P, 0.1).cpu())
