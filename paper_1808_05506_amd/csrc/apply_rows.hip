@@ -342,7 +342,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // 16-byte piece per thread
   const int word_bytes = int(dtype_bytes(dtype));
   if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
-  int bt = 8;
+  int bt = 2;
   if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
   bool xcd = true;
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
