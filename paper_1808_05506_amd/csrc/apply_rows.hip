@@ -302,8 +302,10 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
     u32x4 r[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
+    // outputs are never read again by this kernel: stream them past the L2
+    // so its capacity stays with the input rows that neighbours reuse
 #pragma unroll
-    for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(r[j], &dst[j * NV + v]);
   }
 }
 
