@@ -336,7 +336,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (const char* e = getenv("DSLASH_ROWS"))
     if (atoi(e) == 0) return hipErrorNotSupported;
   if (g.nv != 12) return hipErrorNotSupported;
-  int R = 16;
+  int R = row_sites_default(g.n[0], g.nv);
   if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
   if (R > g.n[0]) R = g.n[0];
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;

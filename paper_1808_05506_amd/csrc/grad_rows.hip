@@ -1,0 +1,310 @@
+// Row-staged link gradients of D_W and D_S (see rows.hpp for the row
+// staging).  A workgroup owns an x-row chunk of R sites and all N_v
+// right-hand sides.  For G_mu(x) each site needs chi and psi at x and at
+// x + mu; every such input is a contiguous run (the chunk's own row with one
+// halo site at x0 + n, or the same x-range of the +y, +z, +t row), staged one
+// field at a time through one LDS buffer with coalesced loads.  A thread keeps
+// the chi and psi of its own (site, rhs) in registers; the two halves of each
+// term use one neighbour field each:
+//   Wilson     G_mu(x) = -1/2 sum_v sum_t [ (P_- chi(x))_t (x) conj((P_- psi(x+mu))_t)
+//                                        + (P_+ psi(x))_t (x) conj((P_+ chi(x+mu))_t) ]
+//   staggered  G_mu(x) = eta_mu(x)/2 sum_v [ chi(x) (x) conj(psi(x+mu)) - psi(x) (x) conj(chi(x+mu)) ]
+// The per-rhs shares are summed over v through LDS; G leaves through LDS with
+// coalesced stores, written once.
+#include <stdlib.h>
+
+#include "launch.hpp"
+#include "rows.hpp"
+
+namespace dsl {
+
+namespace {
+
+typedef unsigned int u32x4g __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2g __attribute__((ext_vector_type(2)));
+
+// 16-, 8- or 4-byte pieces, the largest that divides a lane's share of a site
+// (COMPS storage words: the lanes of a site are its N_v right-hand sides).
+template <int BYTES> struct PieceT;
+template <> struct PieceT<16> { typedef u32x4g type; };
+template <> struct PieceT<8> { typedef u32x2g type; };
+template <> struct PieceT<4> { typedef unsigned int type; };
+
+template <int COMPS, int NV, class S>
+struct Stage {
+  static constexpr int WB = int(sizeof(typename S::word));
+  static constexpr int LANE_BYTES = COMPS * WB;  // one lane's share of a site
+  static constexpr int PB = LANE_BYTES % 16 == 0 ? 16 : (LANE_BYTES % 8 == 0 ? 8 : 4);
+  typedef typename PieceT<PB>::type P;
+  static constexpr int CH = LANE_BYTES / PB;     // pieces per lane per site
+  static constexpr int SW = COMPS * NV;          // words per site
+  static constexpr int SWD = SW * WB / 4;        // dwords per site
+  static constexpr int WIN = NV * WB / 4;        // dwords of one component window
+  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
+  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % PB == 0) ? SWD + PAD : SWD;
+  static constexpr int SSW = DW * 4 / WB;        // padded LDS site stride in words
+  static constexpr int SSP = DW * 4 / PB;        // ... in pieces
+};
+
+// lane (x, v) moves pieces j * N_v + v of site x of a run starting at `base`
+// (clamped to the last live site); `halo` adds one piece of site `hs` into
+// slot CH for the lanes tid < pieces-per-site.
+template <int COMPS, int NV, class S, bool HALO>
+__device__ __forceinline__ void stage_issue(const typename S::word* __restrict__ f, uint32_t base, int n, uint32_t hs,
+                                            int xl, int v, int tid,
+                                            typename Stage<COMPS, NV, S>::P (&r)[Stage<COMPS, NV, S>::CH + 1]) {
+  typedef Stage<COMPS, NV, S> St;
+  typedef typename St::P P;
+  const int xc = xl < n ? xl : n - 1;
+  const P* src = reinterpret_cast<const P*>(f + size_t(base + xc) * St::SW);
+#pragma unroll
+  for (int j = 0; j < St::CH; ++j) r[j] = src[j * NV + v];
+  if (HALO) {
+    constexpr int SP = St::CH * NV;
+    const int h = tid < SP ? tid : SP - 1;
+    r[St::CH] = reinterpret_cast<const P*>(f + size_t(hs) * St::SW)[h];
+  }
+}
+
+template <int COMPS, int NV, class S, bool HALO>
+__device__ __forceinline__ void stage_commit(const typename Stage<COMPS, NV, S>::P (&r)[Stage<COMPS, NV, S>::CH + 1],
+                                             typename S::word* buf, int n, int xl, int v, int tid) {
+  typedef Stage<COMPS, NV, S> St;
+  typedef typename St::P P;
+  const int xc = xl < n ? xl : n - 1;
+  P* dst = reinterpret_cast<P*>(buf) + xc * St::SSP;
+#pragma unroll
+  for (int j = 0; j < St::CH; ++j) dst[j * NV + v] = r[j];
+  if (HALO) {
+    constexpr int SP = St::CH * NV;
+    const int h = tid < SP ? tid : SP - 1;
+    (reinterpret_cast<P*>(buf) + n * St::SSP)[h] = r[St::CH];
+  }
+}
+
+template <int COMPS, int NV, class S, class T>
+__device__ __forceinline__ void lds_column(const typename S::word* site, int v, cpx<T> (&p)[COMPS]) {
+#pragma unroll
+  for (int c = 0; c < COMPS; ++c) p[c] = S::template load<T>(site + c * NV + v);
+}
+
+// G_mu share: gm[a][b] += sum_t l[t][a] conj(r[t][b])
+template <int K, class T>
+__device__ __forceinline__ void outer_add(cpx<T> (&gm)[3][3], const cpx<T> (&l)[K][3], const cpx<T> (&r)[K][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int t = 0; t < K; ++t) gm[a][b] = cmaddj(gm[a][b], l[t][a], r[t][b]);
+}
+
+template <int MU, int C, class T>
+__device__ __forceinline__ void proj12(const cpx<T> (&p)[12], cpx<T> (&h)[2][3]) {
+  cpx<T> q[4][3];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[s][c] = p[s * 3 + c];
+  project<MU, C, T>(q, h);
+}
+
+// One term of G_mu from the neighbour field in LDS.  TERM 0 pairs the own chi
+// with the neighbour psi, TERM 1 the own psi with the neighbour chi.
+template <int OP, int MU, int TERM, int NV, class S, class T>
+__device__ __forceinline__ void grad_term(const typename S::word* nb, const cpx<T>* own_chi, const cpx<T>* own_psi,
+                                          int v, cpx<T> (&gm)[3][3]) {
+  if constexpr (OP == OP_WILSON) {
+    cpx<T> f[12];
+    lds_column<12, NV, S, T>(nb, v, f);
+    cpx<T> hl[2][3], hr[2][3];
+    cpx<T> own[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) own[c] = TERM == 0 ? own_chi[c] : own_psi[c];
+    // TERM 0: (1 - gamma) projections, TERM 1: (1 + gamma) projections
+    proj12<MU, (TERM == 0 ? -1 : +1), T>(own, hl);
+    proj12<MU, (TERM == 0 ? -1 : +1), T>(f, hr);
+    outer_add<2, T>(gm, hl, hr);
+  } else {
+    cpx<T> f[3];
+    lds_column<3, NV, S, T>(nb, v, f);
+    cpx<T> l[1][3], r[1][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      l[0][c] = TERM == 0 ? own_chi[c] : -own_psi[c];
+      r[0][c] = f[c];
+    }
+    outer_add<1, T>(gm, l, r);
+  }
+}
+
+}  // namespace
+
+template <int OP, int NV, class S, class T>
+__global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal tr, int xcd,
+                                                          const typename S::word* __restrict__ chi,
+                                                          const typename S::word* __restrict__ psi,
+                                                          typename S::word* __restrict__ G) {
+  constexpr int COMPS = OP == OP_WILSON ? 12 : 3;
+  typedef Stage<COMPS, NV, S> St;
+  typedef typename St::P P;
+  using W = typename S::word;
+  extern __shared__ uint4 smem_grad[];
+  const int R = int(tr.sb);
+  W* buf = reinterpret_cast<W*>(smem_grad);                         // (R + 1) padded sites
+  cpx<T>* red = reinterpret_cast<cpx<T>*>(buf + (R + 1) * St::SSW);  // [R][9][NV]
+  W* gout = reinterpret_cast<W*>(red + R * 9 * NV);                  // [R][36]
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const RowChunk c = row_chunk(g, tr, L);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v, nth = R * NV;
+  const uint32_t own_base = c.row_base + uint32_t(c.x0);
+  const uint32_t xp = c.row_base + uint32_t(wrap_x(g, c.x0 + c.n));
+  const int xc = xl < c.n ? xl : c.n - 1;
+
+  cpx<T> oc[COMPS], op[COMPS];  // own chi and psi of (x, v)
+  P ra[St::CH + 1], rb[St::CH + 1];
+  stage_issue<COMPS, NV, S, true>(psi, own_base, c.n, xp, xl, v, tid, ra);
+  stage_issue<COMPS, NV, S, true>(chi, own_base, c.n, xp, xl, v, tid, rb);
+
+  // mu = 0: psi row, then chi row (both with the x0 + n halo)
+  cpx<T> gm[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gm[a][b] = zero<T>();
+  cpx<T> pnext[COMPS];
+  stage_commit<COMPS, NV, S, true>(ra, buf, c.n, xl, v, tid);
+  __syncthreads();
+  stage_issue<COMPS, NV, S, false>(psi, row_base_shift(g, c, 1, +1) + uint32_t(c.x0), c.n, 0, xl, v, tid, ra);
+  lds_column<COMPS, NV, S, T>(buf + xc * St::SSW, v, op);
+  lds_column<COMPS, NV, S, T>(buf + (xc + 1) * St::SSW, v, pnext);
+  __syncthreads();
+  stage_commit<COMPS, NV, S, true>(rb, buf, c.n, xl, v, tid);
+  __syncthreads();
+  stage_issue<COMPS, NV, S, false>(chi, row_base_shift(g, c, 1, +1) + uint32_t(c.x0), c.n, 0, xl, v, tid, rb);
+  lds_column<COMPS, NV, S, T>(buf + xc * St::SSW, v, oc);
+  {
+    // term 0 with psi(x + 1) from registers, term 1 with chi(x + 1) from LDS
+    if constexpr (OP == OP_WILSON) {
+      cpx<T> hl[2][3], hr[2][3];
+      proj12<0, -1, T>(oc, hl);
+      proj12<0, -1, T>(pnext, hr);
+      outer_add<2, T>(gm, hl, hr);
+    } else {
+      cpx<T> l[1][3], r[1][3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        l[0][cc] = oc[cc];
+        r[0][cc] = pnext[cc];
+      }
+      outer_add<1, T>(gm, l, r);
+    }
+    grad_term<OP, 0, 1, NV, S, T>(buf + (xc + 1) * St::SSW, oc, op, v, gm);
+  }
+
+  // reduce the mu share over the right-hand sides and stage it in gout
+  auto reduce_mu = [&](int mu) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) red[(xl * 9 + a * 3 + b) * NV + v] = gm[a][b];
+    __syncthreads();
+    for (int o = tid; o < R * 9; o += nth) {
+      const int sl = o / 9, e = o - sl * 9;
+      cpx<T> z = zero<T>();
+#pragma unroll
+      for (int l = 0; l < NV; ++l) z += red[(sl * 9 + e) * NV + l];
+      T f;
+      if (OP == OP_WILSON) {
+        f = T(-0.5);
+      } else {
+        int pp = 0;
+        const int coord[4] = {c.x0 + sl, c.y, c.z, c.t};
+        for (int nu = 0; nu < mu; ++nu) pp += coord[nu];
+        f = (pp & 1) ? T(-0.5) : T(0.5);
+      }
+      S::template store<T>(gout + sl * 36 + mu * 9 + e, f * z);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gm[a][b] = zero<T>();
+  };
+  reduce_mu(0);
+  __syncthreads();
+
+  // mu = 1, 2, 3: the psi row of x + mu, then the chi row; the next row is
+  // requested while the current one is used
+#define DSL_GRAD_MU(MU, NEXT_MU)                                                                        \
+  stage_commit<COMPS, NV, S, false>(ra, buf, c.n, xl, v, tid);                                          \
+  __syncthreads();                                                                                      \
+  if (NEXT_MU > 0)                                                                                      \
+    stage_issue<COMPS, NV, S, false>(psi, row_base_shift(g, c, (NEXT_MU > 0 ? NEXT_MU : 1), +1) +       \
+                                              uint32_t(c.x0), c.n, 0, xl, v, tid, ra);                  \
+  grad_term<OP, MU, 0, NV, S, T>(buf + xc * St::SSW, oc, op, v, gm);                                    \
+  __syncthreads();                                                                                      \
+  stage_commit<COMPS, NV, S, false>(rb, buf, c.n, xl, v, tid);                                          \
+  __syncthreads();                                                                                      \
+  if (NEXT_MU > 0)                                                                                      \
+    stage_issue<COMPS, NV, S, false>(chi, row_base_shift(g, c, (NEXT_MU > 0 ? NEXT_MU : 1), +1) +       \
+                                              uint32_t(c.x0), c.n, 0, xl, v, tid, rb);                  \
+  grad_term<OP, MU, 1, NV, S, T>(buf + xc * St::SSW, oc, op, v, gm);                                    \
+  reduce_mu(MU);                                                                                        \
+  __syncthreads();
+  DSL_GRAD_MU(1, 2)
+  DSL_GRAD_MU(2, 3)
+  DSL_GRAD_MU(3, 0)
+#undef DSL_GRAD_MU
+
+  // G of the chunk: c.n * 36 words, contiguous
+  {
+    constexpr int GP = 36 * int(sizeof(W)) / 16;  // 16-byte pieces per site
+    const int pieces = c.n * GP;
+    const u32x4g* src = reinterpret_cast<const u32x4g*>(gout);
+    u32x4g* dst = reinterpret_cast<u32x4g*>(G + size_t(own_base) * 36);
+    for (int i = tid; i < pieces; i += nth) __builtin_nontemporal_store(src[i], &dst[i]);
+  }
+}
+
+template <int OP, int NV, class S, class T>
+static hipError_t grad_rows_t(const Geom& g, int R, int bt, bool xcd, const void* chi, const void* psi, void* G,
+                              hipStream_t st) {
+  using W = typename S::word;
+  constexpr int COMPS = OP == OP_WILSON ? 12 : 3;
+  const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+  const size_t lds = size_t(R + 1) * Stage<COMPS, NV, S>::SSW * sizeof(W) + size_t(R) * 9 * NV * sizeof(cpx<T>) +
+                     size_t(R) * 36 * sizeof(W);
+  hipLaunchKernelGGL((grad_rows_kernel<OP, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)chi,
+                     (const W*)psi, (W*)G);
+  return hipGetLastError();
+}
+
+// Row-staged link gradient for N_v = 12: D_W in C64, D_S in C64 and C128 (the
+// D_W C128 variant would not fit in registers).  Returns
+// hipErrorNotSupported when the configuration is not covered (the caller then
+// uses the direct kernel).  DSLASH_ROWS=0 disables it.
+hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
+                            hipStream_t st) {
+  if (const char* e = getenv("DSLASH_ROWS"))
+    if (atoi(e) == 0) return hipErrorNotSupported;
+  if (g.nv != 12 || (op != OP_WILSON && op != OP_STAGGERED)) return hipErrorNotSupported;
+  if (dtype != DT_C64 && !(dtype == DT_C128 && op == OP_STAGGERED)) return hipErrorNotSupported;
+  int R = row_sites_default(g.n[0], g.nv);
+  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  if (R > g.n[0]) R = g.n[0];
+  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  int bt = 2;
+  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bool xcd = true;
+  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  if (op == OP_WILSON) {
+    return grad_rows_t<OP_WILSON, 12, C64, float>(g, R, bt, xcd, chi, psi, G, st);
+  }
+  if (dtype == DT_C64) return grad_rows_t<OP_STAGGERED, 12, C64, float>(g, R, bt, xcd, chi, psi, G, st);
+  return grad_rows_t<OP_STAGGERED, 12, C128, double>(g, R, bt, xcd, chi, psi, G, st);
+}
+
+}  // namespace dsl

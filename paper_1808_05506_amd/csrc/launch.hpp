@@ -31,6 +31,8 @@ hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st);
+hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
+                            hipStream_t st);
 hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t st);
 
 // ---- solver BLAS-1 (fields of `comps` complex numbers per site times nv columns,

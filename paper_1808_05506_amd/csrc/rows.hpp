@@ -48,6 +48,17 @@ DSL_HD uint32_t row_base_shift(const Geom& g, const RowChunk& c, int mu, int sgn
   return uint32_t(g.stride[1] * q[1] + g.stride[2] * q[2] + g.stride[3] * q[3]);
 }
 
+// Default chunk length: split an x-row into the fewest chunks of at most 16
+// sites, evenly (24 -> 12 + 12 rather than 16 + 8), but keep at least 128
+// threads per workgroup.
+inline int row_sites_default(int nx, int nv) {
+  const int k = (nx + 15) / 16;
+  int r = (nx + k - 1) / k;
+  const int rmin = (128 + nv - 1) / nv;
+  if (r < rmin) r = nx < rmin ? nx : rmin;
+  return r;
+}
+
 DSL_HD int wrap_x(const Geom& g, int x) { return x < 0 ? x + g.n[0] : (x >= g.n[0] ? x - g.n[0] : x); }
 
 }  // namespace dsl

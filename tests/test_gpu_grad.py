@@ -91,3 +91,44 @@ def test_link_grad_24cube48_nv12(op, kind, seed):
     err = np.abs(got - fd)
     say(f"FD 16 links: max |GPU - FD| = {err.max():.3e} (rms grad {scale:.3e})")
     assert np.all(err <= 1e-5 * (np.abs(fd) + scale))
+
+
+_ROW_DIMS_W = [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (12, 2, 2, 3), (32, 2, 3, 2)]
+_ROW_DIMS_S = [(16, 4, 2, 6), (20, 2, 4, 6), (12, 2, 2, 4), (14, 2, 2, 2), (32, 2, 2, 2)]  # D_S: even extents
+
+
+@pytest.mark.parametrize("op,dt,dims", [("wilson", "c64", d) for d in _ROW_DIMS_W]
+                         + [("staggered", dt, d) for dt in ("c64", "c128") for d in _ROW_DIMS_S])
+def test_link_grad_row_staged_path(op, dt, dims):
+    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged gradient kernel
+    # (D_W in C64, D_S in C64 and C128); 20 sites split into chunks of 11 + 9,
+    # 32 into 16 + 16, 11 to 16 fill one chunk with the wrap-around halo
+    nv = 12
+    say(f"case link grad rows {op} {dims} nv={nv} {dt}")
+    u, chi, psi = _fields(op, dims, nv, 400, dt)
+    gU, _ = D.backward(op, up(u, dt), up(chi, dt), up(psi, dt), 0.2, need_grad_in=False)
+    compare(down(gU), grad.link_grad(op, chi, psi), dt, f"grad_U rows {op}")
+
+
+@pytest.mark.parametrize("op", ["wilson", "staggered"])
+def test_link_grad_rows_determinism_across_chunk_sizes(op):
+    import os
+
+    dims, nv, dt = (22, 4, 2, 4), 12, "c64"
+    u, chi, psi = _fields(op, dims, nv, 410, dt)
+    U, C, P = up(u, dt), up(chi, dt), up(psi, dt)
+    outs = []
+    old = os.environ.get("DSLASH_ROW_SITES")
+    try:
+        for r in ("12", "16", "21"):
+            os.environ["DSLASH_ROW_SITES"] = r
+            say(f"case link grad rows determinism {op} R={r}")
+            outs.append(D.backward(op, U, C, P, 0.0, need_grad_in=False)[0].cpu())
+    finally:
+        if old is None:
+            os.environ.pop("DSLASH_ROW_SITES", None)
+        else:
+            os.environ["DSLASH_ROW_SITES"] = old
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), grad.link_grad(op, chi, psi), dt, f"grad_U rows R sweep {op}")
