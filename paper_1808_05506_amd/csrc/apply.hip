@@ -134,7 +134,11 @@ static hipError_t apply_op(bool adj, int dtype, const Geom& g, const void* U, co
 hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                         double mass, hipStream_t st) {
   switch (op) {
-    case OP_STAGGERED: return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, mass, st);
+    case OP_STAGGERED: {
+      const hipError_t e = launch_staggered_rows(adj, dtype, g, U, in, out, mass, st);
+      if (e != hipErrorNotSupported) return e;
+      return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, mass, st);
+    }
     case OP_WILSON: {
       const hipError_t e = launch_wilson_rows(adj, dtype, g, U, in, out, mass, st);
       if (e != hipErrorNotSupported) return e;

@@ -1,17 +1,15 @@
-// Row-staged D_W kernel (see rows.hpp): a workgroup owns an x-row chunk of
+// Row-staged D_W kernels (see rows.hpp): a workgroup owns an x-row chunk of
 // R sites and all N_v right-hand sides; its inputs are copied into LDS with
 // coalesced 16-byte loads, the hops are evaluated from LDS, and the outputs
-// leave through LDS with coalesced 16-byte stores.
+// leave through LDS with coalesced 16-byte stores.  wilson_rows_kernel
+// computes one output row per workgroup; wilson_march_kernel (the default)
+// steps one workgroup through several consecutive t of the same (y, z).
 #include <stdlib.h>
 
 #include "launch.hpp"
 #include "rows.hpp"
 
 namespace dsl {
-
-// 16 bytes as a native vector (HIP's uint4 is a class around a union, which
-// keeps arrays of it in scratch memory instead of registers).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Copy `pieces` 16-byte pieces (both pointers 16-byte aligned) with the
 // workgroup's threads; consecutive threads move consecutive pieces and each
@@ -309,6 +307,293 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   }
 }
 
+// ---------------------------------------------------------------- t-marching variant
+// A workgroup owns the x-row chunk at (y, z) for T consecutive t and steps
+// through them.  The -t hop of step t + 1 is U_t(x, t)^dag (1 -/+ gamma_t) psi(x, t),
+// formed at step t from the own row already in LDS (a carry of one half
+// spinor per lane), so after the first step only six rows are staged per
+// output row: +y, -y, +z, -z, +t and the own row, and the +t row of one step
+// is the own row of the next, read again while it is still in L2.
+struct MarchTraversal {
+  uint32_t sb, chunks, rows;  // sites per chunk, chunks per x-row, chunks per t-plane
+  uint32_t T;                 // t steps per workgroup
+  FastDiv d_chunks, d_ny, d_rows;
+};
+
+inline MarchTraversal make_march_traversal(const Geom& g, uint32_t sb, uint32_t T) {
+  MarchTraversal m;
+  m.sb = sb;
+  m.chunks = (uint32_t(g.n[0]) + sb - 1) / sb;
+  m.rows = m.chunks * uint32_t(g.n[1]) * uint32_t(g.n[2]);
+  if (T < 1) T = 1;
+  if (T > uint32_t(g.n[3])) T = uint32_t(g.n[3]);
+  m.T = T;
+  m.d_chunks = FastDiv::make(m.chunks);
+  m.d_ny = FastDiv::make(uint32_t(g.n[1]));
+  m.d_rows = FastDiv::make(m.rows);
+  return m;
+}
+
+// Chunk `id` = (z Ny + y) chunks + chunk of t-plane t.
+DSL_HD RowChunk march_chunk(const Geom& g, const MarchTraversal& m, uint32_t id, int t) {
+  const uint32_t yz = m.d_chunks.div(id);
+  const uint32_t chunk = id - yz * m.chunks;
+  const uint32_t z = m.d_ny.div(yz);
+  const uint32_t y = yz - z * uint32_t(g.n[1]);
+  RowChunk c;
+  c.x0 = int(chunk * m.sb);
+  c.n = g.n[0] - c.x0 < int(m.sb) ? g.n[0] - c.x0 : int(m.sb);
+  c.y = int(y);
+  c.z = int(z);
+  c.t = t;
+  c.row_base = uint32_t(g.stride[1] * c.y + g.stride[2] * c.z + g.stride[3] * t);
+  return c;
+}
+
+// Row K of a step's sequence (0 +y, 1 -y, 2 +z, 3 -z, 4 +t, 5 -t, 6 own) into
+// its register array.
+template <int K, int NV, class S>
+__device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
+                                            const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
+                                            int tid, u32x4 (&r0)[RowPieces<S>::CH + 1],
+                                            u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
+                                            u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
+                                            u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1]) {
+  if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, U, in, xl, v, tid, r0);
+  if constexpr (K == 1) row_issue<1, -1, NV, S>(g, c, U, in, xl, v, tid, r1);
+  if constexpr (K == 2) row_issue<2, +1, NV, S>(g, c, U, in, xl, v, tid, r2);
+  if constexpr (K == 3) row_issue<2, -1, NV, S>(g, c, U, in, xl, v, tid, r3);
+  if constexpr (K == 4) row_issue<3, +1, NV, S>(g, c, U, in, xl, v, tid, r4);
+  if constexpr (K == 5) row_issue<3, -1, NV, S>(g, c, U, in, xl, v, tid, r5);
+  if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);
+}
+
+// Sequence of staged rows in a step: all seven in the first step of a
+// workgroup, without the -t row (K = 5) afterwards.
+template <bool FIRST> struct MarchSeq {
+  static constexpr int N = FIRST ? 7 : 6;
+  static constexpr int at(int p) { return FIRST ? p : (p < 5 ? p : 6); }
+};
+
+// Links of sites x0 - 1 .. x0 + n - 1 of a row (36 words each): up to 3
+// 16-byte pieces per thread for the chunk, one for the halo site.
+template <class S>
+struct LinkPieces {
+  static constexpr int PER_SITE = 36 * int(sizeof(typename S::word)) / 16;
+};
+
+template <class S>
+__device__ __forceinline__ void links_issue(const RowChunk& c, const typename S::word* __restrict__ U, int xm, int tid,
+                                            int nth, u32x4 (&lr)[4]) {
+  constexpr int LP = LinkPieces<S>::PER_SITE;
+  const u32x4* own = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + c.x0) * 36);
+  const int pieces = c.n * LP;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int i = tid + j * nth;
+    lr[j] = own[i < pieces ? i : pieces - 1];
+  }
+  const u32x4* halo = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + xm) * 36);
+  lr[3] = halo[tid < LP ? tid : LP - 1];
+}
+
+template <class S>
+__device__ __forceinline__ void links_commit(const RowChunk& c, const u32x4 (&lr)[4], typename S::word* lown, int tid,
+                                             int nth) {
+  constexpr int LP = LinkPieces<S>::PER_SITE;
+  u32x4* own = reinterpret_cast<u32x4*>(lown + 36);
+  const int pieces = c.n * LP;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int i = tid + j * nth;
+    own[i < pieces ? i : pieces - 1] = lr[j];
+  }
+  reinterpret_cast<u32x4*>(lown)[tid < LP ? tid : LP - 1] = lr[3];
+}
+
+template <class T>
+__device__ __forceinline__ void hold_acc(cpx<T> (&acc)[4][3]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) hold(acc[a][b]);
+}
+
+// Two or three rows in flight fit the 168 VGPRs of three waves per SIMD.
+template <int DEPTH> struct MarchWaves { static constexpr int value = DEPTH <= 3 ? 3 : 2; };
+
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T>
+__device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
+                                           const typename S::word* __restrict__ U,
+                                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                                           typename S::word* buf, typename S::word* lown, typename S::word* lnb,
+                                           int xm, int xp, int xl, int v, int tid, int nth, T diag,
+                                           u32x4 (&r0)[RowPieces<S>::CH + 1], u32x4 (&r1)[RowPieces<S>::CH + 1],
+                                           u32x4 (&r2)[RowPieces<S>::CH + 1], u32x4 (&r3)[RowPieces<S>::CH + 1],
+                                           u32x4 (&r4)[RowPieces<S>::CH + 1], u32x4 (&r5)[RowPieces<S>::CH + 1],
+                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[4], cpx<T> (&carry)[2][3]) {
+  using W = typename S::word;
+  using Q = MarchSeq<FIRST>;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
+  constexpr int CF = ADJ ? +1 : -1, CB = -CF;
+  // the first step's leading rows and links were requested by the caller; a
+  // later step requests them here, after the previous step's last barrier
+  if constexpr (!FIRST) {
+#define DSL_SISSUE(P) march_issue<Q::at(P), NV, S>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+    DSL_SISSUE(0);
+    if constexpr (DEPTH > 1) DSL_SISSUE(1);
+    if constexpr (DEPTH > 2) DSL_SISSUE(2);
+    if constexpr (DEPTH > 3) DSL_SISSUE(3);
+    if constexpr (DEPTH > 4) DSL_SISSUE(4);
+    if constexpr (DEPTH > 5) DSL_SISSUE(5);
+#undef DSL_SISSUE
+    links_issue<S>(c, U, xm, tid, nth, lr);
+  }
+  links_commit<S>(c, lr, lown, tid, nth);
+
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
+
+  W* const row = buf + SSW;
+#define DSL_MISSUE(P, CH_)                                                                             \
+  march_issue<Q::at(P), NV, S>(g, CH_, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+#define DSL_MSTEP(P, MU, SGN, CUR)                                        \
+  if constexpr (P < Q::N - 1) {                                           \
+    row_commit<SGN, NV, S>(c, CUR, row, lnb, xl, v, tid);                 \
+    __syncthreads();                                                      \
+    if constexpr (P + DEPTH < Q::N) DSL_MISSUE(P + DEPTH, c);             \
+    row_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);      \
+    hold_acc<T>(acc);                                                     \
+    __syncthreads();                                                      \
+  }
+  DSL_MSTEP(0, 1, +1, r0)
+  DSL_MSTEP(1, 1, -1, r1)
+  DSL_MSTEP(2, 2, +1, r2)
+  DSL_MSTEP(3, 2, -1, r3)
+  DSL_MSTEP(4, 3, +1, r4)
+  DSL_MSTEP(5, 3, -1, r5)
+#undef DSL_MSTEP
+
+  own_commit<NV, S>(c, r6, buf, xl, v, tid);
+  __syncthreads();
+#undef DSL_MISSUE
+  cpx<T> res[4][3];
+  {
+    lds_hop<0, CF, false, NV, S, T>(buf + (xl + 2) * SSW, lown + (xl + 1) * 36, v, acc);
+    lds_hop<0, CB, true, NV, S, T>(buf + xl * SSW, lown + xl * 36, v, acc);
+    if constexpr (!FIRST) reconstruct_add<3, CB, T>(acc, carry);
+    const W* self = buf + (xl + 1) * SSW;
+    cpx<T> p[4][3];
+    lds_spinor<S, T, NV>(self, v, p);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        res[sp][cc].r = fma(diag, p[sp][cc].r, T(-0.5) * acc[sp][cc].r);
+        res[sp][cc].i = fma(diag, p[sp][cc].i, T(-0.5) * acc[sp][cc].i);
+      }
+    // carry for the next step: U_t(x, t)^dag (1 + CB gamma_t) psi(x, t), projected
+    cpx<T> h[2][3];
+    project<3, CB, T>(p, h);
+    cpx<T> u[3][3];
+    const W* lt = lown + (xl + 1) * 36 + 27;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(lt + a * 3 + b);
+    su3_mul2<true, T>(u, h, carry);
+  }
+  __syncthreads();
+  {
+    W* o = buf + xl * SSW;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) S::template store<T>(o + (sp * 3 + cc) * NV + v, res[sp][cc]);
+  }
+  __syncthreads();
+  {
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
+    u32x4 r[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(r[j], &dst[j * NV + v]);
+  }
+  __syncthreads();
+}
+
+template <int DEPTH, bool ADJ, int NV, class S, class T>
+__global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
+    wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
+                        const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
+  using W = typename S::word;
+  constexpr int CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS;
+  extern __shared__ uint4 smem_march[];
+  const int R = int(m.sb);
+  W* buf = reinterpret_cast<W*>(smem_march);
+  W* lown = buf + (R + 2) * SSW;
+  W* lnb = lown + (R + 1) * 36;
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const uint32_t seg = m.d_rows.div(L);
+  const uint32_t id = L - seg * m.rows;
+  const int t0 = int(seg * m.T);
+  const int steps = g.n[3] - t0 < int(m.T) ? g.n[3] - t0 : int(m.T);
+  RowChunk c = march_chunk(g, m, id, t0);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v, nth = R * NV;
+  const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+
+  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  u32x4 lr[4];
+  cpx<T> carry[2][3];
+  using Q0 = MarchSeq<true>;
+#define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+  DSL_PISSUE(0);
+  if constexpr (DEPTH > 1) DSL_PISSUE(1);
+  if constexpr (DEPTH > 2) DSL_PISSUE(2);
+  if constexpr (DEPTH > 3) DSL_PISSUE(3);
+  if constexpr (DEPTH > 4) DSL_PISSUE(4);
+#undef DSL_PISSUE
+  links_issue<S>(c, U, xm, tid, nth, lr);
+  march_step<true, DEPTH, ADJ, NV, S, T>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
+                                         r0, r1, r2, r3, r4, r5, r6, lr, carry);
+#pragma nounroll
+  for (int k = 1; k < steps; ++k) {
+    c.t += 1;
+    c.row_base += uint32_t(g.stride[3]);
+    march_step<false, DEPTH, ADJ, NV, S, T>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
+                                            diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+  }
+}
+
+template <int DEPTH, int NV, class S, class T>
+static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, bool xcd, const void* U, const void* in,
+                                 void* out, double mass, hipStream_t st) {
+  using W = typename S::word;
+  const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
+  const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
+  const dim3 block(NV, R), grid(m.rows * nseg);
+  size_t lds = rows_lds_words<NV, S>(R) * sizeof(W);
+  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
+  const T diag = T(4) + T(mass);
+  if (adj)
+    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, true, NV, S, T>), grid, block, lds, st, g, m, int(xcd),
+                       (const W*)U, (const W*)in, (W*)out, diag);
+  else
+    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, false, NV, S, T>), grid, block, lds, st, g, m, int(xcd),
+                       (const W*)U, (const W*)in, (W*)out, diag);
+  return hipGetLastError();
+}
+
 template <int DEPTH, int NV, class S, class T>
 static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* U, const void* in,
                                 void* out, double mass, hipStream_t st) {
@@ -348,8 +633,25 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
   bool xcd = true;
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
-  int depth = 3;
-  if (const char* e = getenv("DSLASH_ROW_DEPTH")) depth = atoi(e);
+  // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
+  // 0 selects the kernel with one output row per workgroup).
+  // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 2 marching, 3 otherwise).
+  int tsteps = 8;
+  if (const char* e = getenv("DSLASH_TSTEPS")) tsteps = atoi(e);
+  const char* depth_env = getenv("DSLASH_ROW_DEPTH");
+  if (tsteps > 0) {
+    const int depth = depth_env ? atoi(depth_env) : 2;
+#define DSL_MT(D)                                                                                       \
+  switch (dtype) {                                                                                      \
+    case DT_C64: return wilson_march_t<D, 12, C64, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
+    case DT_BF16: return wilson_march_t<D, 12, BF16, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st); \
+    case DT_F16: return wilson_march_t<D, 12, F16, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
+  }
+    if (depth <= 2) { DSL_MT(2) } else { DSL_MT(3) }
+#undef DSL_MT
+    return hipErrorNotSupported;
+  }
+  const int depth = depth_env ? atoi(depth_env) : 3;
 #define DSL_RT(D)                                                                               \
   switch (dtype) {                                                                              \
     case DT_C64: return wilson_rows_t<D, 12, C64, float>(adj, g, R, bt, xcd, U, in, out, mass, st);   \

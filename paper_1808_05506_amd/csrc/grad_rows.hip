@@ -20,74 +20,6 @@ namespace dsl {
 
 namespace {
 
-typedef unsigned int u32x4g __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2g __attribute__((ext_vector_type(2)));
-
-// 16-, 8- or 4-byte pieces, the largest that divides a lane's share of a site
-// (COMPS storage words: the lanes of a site are its N_v right-hand sides).
-template <int BYTES> struct PieceT;
-template <> struct PieceT<16> { typedef u32x4g type; };
-template <> struct PieceT<8> { typedef u32x2g type; };
-template <> struct PieceT<4> { typedef unsigned int type; };
-
-template <int COMPS, int NV, class S>
-struct Stage {
-  static constexpr int WB = int(sizeof(typename S::word));
-  static constexpr int LANE_BYTES = COMPS * WB;  // one lane's share of a site
-  static constexpr int PB = LANE_BYTES % 16 == 0 ? 16 : (LANE_BYTES % 8 == 0 ? 8 : 4);
-  typedef typename PieceT<PB>::type P;
-  static constexpr int CH = LANE_BYTES / PB;     // pieces per lane per site
-  static constexpr int SW = COMPS * NV;          // words per site
-  static constexpr int SWD = SW * WB / 4;        // dwords per site
-  static constexpr int WIN = NV * WB / 4;        // dwords of one component window
-  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
-  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % PB == 0) ? SWD + PAD : SWD;
-  static constexpr int SSW = DW * 4 / WB;        // padded LDS site stride in words
-  static constexpr int SSP = DW * 4 / PB;        // ... in pieces
-};
-
-// lane (x, v) moves pieces j * N_v + v of site x of a run starting at `base`
-// (clamped to the last live site); `halo` adds one piece of site `hs` into
-// slot CH for the lanes tid < pieces-per-site.
-template <int COMPS, int NV, class S, bool HALO>
-__device__ __forceinline__ void stage_issue(const typename S::word* __restrict__ f, uint32_t base, int n, uint32_t hs,
-                                            int xl, int v, int tid,
-                                            typename Stage<COMPS, NV, S>::P (&r)[Stage<COMPS, NV, S>::CH + 1]) {
-  typedef Stage<COMPS, NV, S> St;
-  typedef typename St::P P;
-  const int xc = xl < n ? xl : n - 1;
-  const P* src = reinterpret_cast<const P*>(f + size_t(base + xc) * St::SW);
-#pragma unroll
-  for (int j = 0; j < St::CH; ++j) r[j] = src[j * NV + v];
-  if (HALO) {
-    constexpr int SP = St::CH * NV;
-    const int h = tid < SP ? tid : SP - 1;
-    r[St::CH] = reinterpret_cast<const P*>(f + size_t(hs) * St::SW)[h];
-  }
-}
-
-template <int COMPS, int NV, class S, bool HALO>
-__device__ __forceinline__ void stage_commit(const typename Stage<COMPS, NV, S>::P (&r)[Stage<COMPS, NV, S>::CH + 1],
-                                             typename S::word* buf, int n, int xl, int v, int tid) {
-  typedef Stage<COMPS, NV, S> St;
-  typedef typename St::P P;
-  const int xc = xl < n ? xl : n - 1;
-  P* dst = reinterpret_cast<P*>(buf) + xc * St::SSP;
-#pragma unroll
-  for (int j = 0; j < St::CH; ++j) dst[j * NV + v] = r[j];
-  if (HALO) {
-    constexpr int SP = St::CH * NV;
-    const int h = tid < SP ? tid : SP - 1;
-    (reinterpret_cast<P*>(buf) + n * St::SSP)[h] = r[St::CH];
-  }
-}
-
-template <int COMPS, int NV, class S, class T>
-__device__ __forceinline__ void lds_column(const typename S::word* site, int v, cpx<T> (&p)[COMPS]) {
-#pragma unroll
-  for (int c = 0; c < COMPS; ++c) p[c] = S::template load<T>(site + c * NV + v);
-}
-
 // G_mu share: gm[a][b] += sum_t l[t][a] conj(r[t][b])
 template <int K, class T>
 __device__ __forceinline__ void outer_add(cpx<T> (&gm)[3][3], const cpx<T> (&l)[K][3], const cpx<T> (&r)[K][3]) {
@@ -262,8 +194,8 @@ __global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal 
   {
     constexpr int GP = 36 * int(sizeof(W)) / 16;  // 16-byte pieces per site
     const int pieces = c.n * GP;
-    const u32x4g* src = reinterpret_cast<const u32x4g*>(gout);
-    u32x4g* dst = reinterpret_cast<u32x4g*>(G + size_t(own_base) * 36);
+    const u32x4* src = reinterpret_cast<const u32x4*>(gout);
+    u32x4* dst = reinterpret_cast<u32x4*>(G + size_t(own_base) * 36);
     for (int i = tid; i < pieces; i += nth) __builtin_nontemporal_store(src[i], &dst[i]);
   }
 }

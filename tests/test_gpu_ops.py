@@ -192,36 +192,101 @@ def test_errors_raise():
         D.apply("staggered", U, P, 0.1)           # wrong spinor shape for the op
 
 
+@pytest.mark.parametrize("kernel", ["march", "rows"])
 @pytest.mark.parametrize("dt", ["c64", "bf16", "f16"])
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("dims", [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (12, 2, 2, 3), (32, 2, 3, 2)])
-def test_wilson_row_staged_path(dt, adj, dims):
-    # N_v = 12 with rows of >= 12 sites (>= 11 in 16-bit storage) runs the LDS
-    # row-staged kernel, shorter rows the direct kernel; 20 and 32 sites split
-    # into chunks (a partial one for 20)
+def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
+    # N_v = 12 with rows of >= 12 sites (>= 11 in 16-bit storage) runs an LDS
+    # row-staged kernel (by default the t-marching one; DSLASH_TSTEPS=0 selects
+    # one output row per workgroup), shorter rows the direct kernel; 20 and 32
+    # sites split into chunks (a partial one for 20)
     nv = 12
-    say(f"case wilson rows {dims} nv={nv} {dt} adj={adj}")
+    monkeypatch.setenv("DSLASH_TSTEPS", "8" if kernel == "march" else "0")
+    say(f"case wilson {kernel} {dims} nv={nv} {dt} adj={adj}")
     u, p = _wil_fields(dims, nv, 81, 82, dt, "haar")
     out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
-    compare(down(out), wilson.apply(u, p, 0.1, adj), dt, "D_W rows")
+    compare(down(out), wilson.apply(u, p, 0.1, adj), dt, f"D_W {kernel}")
 
 
-def test_row_staged_determinism_across_chunk_sizes():
+@pytest.mark.parametrize("dims,tsteps", [((16, 2, 2, 11), "8"), ((12, 3, 2, 17), "8"), ((16, 2, 3, 7), "3"),
+                                         ((16, 2, 2, 5), "1"), ((16, 2, 2, 4), "64")])
+@pytest.mark.parametrize("adj", [False, True])
+def test_wilson_march_segments(dims, tsteps, adj, monkeypatch):
+    # t-marching workgroups over several t segments, a partial last one, one
+    # step per workgroup (no carried -t hop) and a segment longer than N_t
+    nv, dt = 12, "c64"
+    monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
+    say(f"case wilson march segments {dims} T={tsteps} adj={adj}")
+    u, p = _wil_fields(dims, nv, 83, 84, dt, "haar")
+    out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), wilson.apply(u, p, 0.1, adj), dt, "D_W march segments")
+
+
+@pytest.mark.parametrize("kernel", ["march", "rows"])
+def test_row_staged_determinism_across_chunk_sizes(kernel, monkeypatch):
     dims, nv = (22, 4, 4, 4), 12
+    monkeypatch.setenv("DSLASH_TSTEPS", "8" if kernel == "march" else "0")
     u, p = _wil_fields(dims, nv, 91, 92, "c64")
     U, P = up(u, "c64"), up(p, "c64")
     outs = []
-    old = os.environ.get("DSLASH_ROW_SITES")
-    try:
-        for r in ("12", "16", "21"):
-            os.environ["DSLASH_ROW_SITES"] = r
-            say(f"case rows determinism R={r}")
-            outs.append(D.apply("wilson", U, P, 0.1).cpu())
-    finally:
-        if old is None:
-            os.environ.pop("DSLASH_ROW_SITES", None)
-        else:
-            os.environ["DSLASH_ROW_SITES"] = old
+    for r in ("12", "16", "21"):
+        monkeypatch.setenv("DSLASH_ROW_SITES", r)
+        say(f"case {kernel} determinism R={r}")
+        outs.append(D.apply("wilson", U, P, 0.1).cpu())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), wilson.apply(u, p, 0.1), "c64", "D_W rows R sweep")
+
+
+_SROW_DIMS = [(16, 4, 2, 6), (20, 2, 4, 6), (12, 2, 2, 4), (14, 2, 2, 2), (32, 2, 2, 2), (24, 4, 2, 2)]
+
+
+@pytest.mark.parametrize("kernel", ["rows", "direct"])
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("dims", _SROW_DIMS)
+def test_staggered_row_staged_path(kernel, dt, adj, dims, monkeypatch):
+    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged D_S kernel
+    # (DSLASH_ROWS=0 forces the direct kernel); 20 sites split into 11 + 9,
+    # 24 into 12 + 12, 32 into 16 + 16, 12 to 16 fill one chunk
+    nv = 12
+    monkeypatch.setenv("DSLASH_ROWS", "1" if kernel == "rows" else "0")
+    say(f"case staggered {kernel} {dims} nv={nv} {dt} adj={adj}")
+    u, p = _stag_fields(dims, nv, 71, 72, dt)
+    out = D.apply("staggered", up(u, dt), up(p, dt), 0.15, adjoint=adj)
+    compare(down(out), staggered.apply(u, p, 0.15, adj), dt, f"D_S {kernel}")
+
+
+@pytest.mark.parametrize("depth", ["3", "7"])
+def test_staggered_rows_determinism_across_chunk_sizes(depth, monkeypatch):
+    dims, nv = (22, 4, 2, 4), 12
+    monkeypatch.setenv("DSLASH_ROW_DEPTH", depth)
+    u, p = _stag_fields(dims, nv, 73, 74, "c64")
+    U, P = up(u, "c64"), up(p, "c64")
+    outs = []
+    for r in ("12", "16", "21"):
+        monkeypatch.setenv("DSLASH_ROW_SITES", r)
+        say(f"case staggered rows determinism R={r} depth={depth}")
+        outs.append(D.apply("staggered", U, P, 0.0).cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), staggered.apply(u, p, 0.0), "c64", "D_S rows R sweep")
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_staggered_32to4_nv12_sampled(dt):
+    # 32^4, N_v = 12, Haar links (seed 2), rhs seed 102, m = 0: the
+    # row-staged kernel at full size against the oracle at sampled sites
+    dims, nv = (32, 32, 32, 32), 12
+    say(f"case staggered {dims} nv={nv} {dt} sampled")
+    u = rounded(synthetic.gauge_links(dims, "haar", 2), dt)
+    p = rounded(synthetic.staggered_spinor(dims, nv, 102), dt)
+    out = D.apply("staggered", up(u, dt), up(p, dt), 0.0)
+    sites = local.sample_sites(dims, 64, 8)
+    idx = (sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0])
+    it = torch.as_tensor(np.stack(idx), device=out.device)
+    got = out[it[0], it[1], it[2], it[3]].cpu().numpy().astype(np.complex128)
+    del out
+    torch.cuda.empty_cache()
+    compare(got, local.staggered_at(u, p, 0.0, sites), dt, "D_S 32^4 sampled")
