@@ -70,6 +70,35 @@ __device__ __forceinline__ void lds_hop(const typename S::word* __restrict__ sit
   reconstruct_add<MU, C, T>(acc, t);
 }
 
+// A storage word (4, 8 or 16 bytes) in the low bytes of a 16-byte register
+// group and back, by value (a memcpy through a local can leave the group in
+// scratch memory).
+template <class W>
+__device__ __forceinline__ u32x4 word_to_piece(W w) {
+  if constexpr (sizeof(W) == 16) {
+    return __builtin_bit_cast(u32x4, w);
+  } else if constexpr (sizeof(W) == 8) {
+    const u32x2 t = __builtin_bit_cast(u32x2, w);
+    return u32x4{t.x, t.y, 0u, 0u};
+  } else {
+    return u32x4{__builtin_bit_cast(unsigned, w), 0u, 0u, 0u};
+  }
+}
+
+template <class W>
+__device__ __forceinline__ W piece_to_word(u32x4 z) {
+  if constexpr (sizeof(W) == 16) {
+    return __builtin_bit_cast(W, z);
+  } else if constexpr (sizeof(W) == 8) {
+    return __builtin_bit_cast(W, u32x2{z.x, z.y});
+  } else {
+    // 4-byte words are uint32_t pairs of 16-bit halves: a plain conversion
+    // (a bit cast of a vector element is miscompiled by this compiler)
+    static_assert(__is_same(W, uint32_t), "4-byte storage words are uint32_t");
+    return z.x;
+  }
+}
+
 // One thread's share of a neighbour row in flight: CH 16-byte pieces of the
 // spinor run (pieces tid, tid + nth, ...) plus, for a backward hop, one word of
 // the V_mu piece of the row's links (held as a 16-byte register group so the
@@ -122,10 +151,12 @@ __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, cons
   if (SGN < 0) {
     const int w = tid < c.n * 9 ? tid : c.n * 9 - 1;
     const int k = w / 9, e = w - k * 9;
-    const W lk = U[(size_t(nrow + k) * 4 + MU) * 9 + e];
-    u32x4 z = {0u, 0u, 0u, 0u};
-    __builtin_memcpy(&z, &lk, sizeof(W));
-    r[CH] = z;
+    r[CH] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * 9 + e]);
+  } else {
+    // every row writes the whole array, so that call sites merged into one
+    // array store the same elements (the compiler's store sinking would
+    // otherwise make the array addressable and put it in scratch memory)
+    r[CH] = u32x4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -138,12 +169,7 @@ __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[R
   u32x4* dst = reinterpret_cast<u32x4*>(row) + xc * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
-  if (SGN < 0) {
-    W lk;
-    const u32x4 z = r[CH];
-    __builtin_memcpy(&lk, &z, sizeof(W));
-    lnb[tid < c.n * 9 ? tid : c.n * 9 - 1] = lk;
-  }
+  if (SGN < 0) lnb[tid < c.n * 9 ? tid : c.n * 9 - 1] = piece_to_word<W>(r[CH]);
 }
 
 // The chunk's own row in the same register shape: CH pieces of site x and,
@@ -382,33 +408,39 @@ struct LinkPieces {
   static constexpr int PER_SITE = 36 * int(sizeof(typename S::word)) / 16;
 };
 
-template <class S>
+// Pieces of the chunk's links per thread: ceil(LP / threads per site).
+template <class S, int THREADS_PER_SITE>
+struct LinkK {
+  static constexpr int value = (LinkPieces<S>::PER_SITE + THREADS_PER_SITE - 1) / THREADS_PER_SITE;
+};
+
+template <class S, int K>
 __device__ __forceinline__ void links_issue(const RowChunk& c, const typename S::word* __restrict__ U, int xm, int tid,
-                                            int nth, u32x4 (&lr)[4]) {
+                                            int nth, u32x4 (&lr)[K + 1]) {
   constexpr int LP = LinkPieces<S>::PER_SITE;
   const u32x4* own = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + c.x0) * 36);
   const int pieces = c.n * LP;
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
+  for (int j = 0; j < K; ++j) {
     const int i = tid + j * nth;
     lr[j] = own[i < pieces ? i : pieces - 1];
   }
   const u32x4* halo = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + xm) * 36);
-  lr[3] = halo[tid < LP ? tid : LP - 1];
+  lr[K] = halo[tid < LP ? tid : LP - 1];
 }
 
-template <class S>
-__device__ __forceinline__ void links_commit(const RowChunk& c, const u32x4 (&lr)[4], typename S::word* lown, int tid,
-                                             int nth) {
+template <class S, int K>
+__device__ __forceinline__ void links_commit(const RowChunk& c, const u32x4 (&lr)[K + 1], typename S::word* lown,
+                                             int tid, int nth) {
   constexpr int LP = LinkPieces<S>::PER_SITE;
   u32x4* own = reinterpret_cast<u32x4*>(lown + 36);
   const int pieces = c.n * LP;
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
+  for (int j = 0; j < K; ++j) {
     const int i = tid + j * nth;
     own[i < pieces ? i : pieces - 1] = lr[j];
   }
-  reinterpret_cast<u32x4*>(lown)[tid < LP ? tid : LP - 1] = lr[3];
+  reinterpret_cast<u32x4*>(lown)[tid < LP ? tid : LP - 1] = lr[K];
 }
 
 template <class T>
@@ -431,9 +463,11 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            u32x4 (&r0)[RowPieces<S>::CH + 1], u32x4 (&r1)[RowPieces<S>::CH + 1],
                                            u32x4 (&r2)[RowPieces<S>::CH + 1], u32x4 (&r3)[RowPieces<S>::CH + 1],
                                            u32x4 (&r4)[RowPieces<S>::CH + 1], u32x4 (&r5)[RowPieces<S>::CH + 1],
-                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[4], cpx<T> (&carry)[2][3]) {
+                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[LinkK<S, NV>::value + 1],
+                                           cpx<T> (&carry)[2][3]) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
+  constexpr int LK = LinkK<S, NV>::value;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
   constexpr int CF = ADJ ? +1 : -1, CB = -CF;
@@ -448,9 +482,9 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
     if constexpr (DEPTH > 4) DSL_SISSUE(4);
     if constexpr (DEPTH > 5) DSL_SISSUE(5);
 #undef DSL_SISSUE
-    links_issue<S>(c, U, xm, tid, nth, lr);
+    links_issue<S, LK>(c, U, xm, tid, nth, lr);
   }
-  links_commit<S>(c, lr, lown, tid, nth);
+  links_commit<S, LK>(c, lr, lown, tid, nth);
 
   cpx<T> acc[4][3];
 #pragma unroll
@@ -534,7 +568,7 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
   using W = typename S::word;
-  constexpr int CH = RowPieces<S>::CH;
+  constexpr int CH = RowPieces<S>::CH, LK = LinkK<S, NV>::value;
   constexpr int SSW = SiteStride<NV, S>::WORDS;
   extern __shared__ uint4 smem_march[];
   const int R = int(m.sb);
@@ -553,7 +587,7 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
 
   u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
-  u32x4 lr[4];
+  u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
   using Q0 = MarchSeq<true>;
 #define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
@@ -563,7 +597,7 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
   if constexpr (DEPTH > 3) DSL_PISSUE(3);
   if constexpr (DEPTH > 4) DSL_PISSUE(4);
 #undef DSL_PISSUE
-  links_issue<S>(c, U, xm, tid, nth, lr);
+  links_issue<S, LK>(c, U, xm, tid, nth, lr);
   march_step<true, DEPTH, ADJ, NV, S, T>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
                                          r0, r1, r2, r3, r4, r5, r6, lr, carry);
 #pragma nounroll

@@ -3,8 +3,10 @@
 // Fields are [site][comps][nv] complex with the column (right-hand side)
 // index fastest.  Per-column reductions accumulate in FP64: every thread sums
 // its rows in a fixed order, the block reduces through LDS in a fixed tree,
-// and a final kernel sums the kReduceBlocks block partials in index order, so
-// results are bitwise reproducible run to run.
+// and a final kernel sums the kReduceBlocks block partials in a fixed order
+// too, so results are bitwise reproducible run to run.  When 16 / (word
+// bytes) divides nv, the kernels move 16-byte chunks (several columns per
+// thread) instead of single words.
 #include "launch.hpp"
 
 namespace dsl {
@@ -110,29 +112,162 @@ __global__ void __launch_bounds__(256) norm2_kernel(const typename S::word* __re
   if (threadIdx.y == 0 && v < nv) partial[size_t(blockIdx.x) * nv + v] = tot;
 }
 
-__global__ void finish_sum_kernel(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out) {
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[size_t(b) * nv + v];
-    out[v] = s;
+// out[v] = sum over the kReduceBlocks partials of column v: one workgroup per
+// column, each thread adds a fixed strided subset in index order, then a
+// fixed LDS tree.
+__global__ void __launch_bounds__(256) finish_sum_kernel(const double* __restrict__ partial, int nb, int nv,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += partial[size_t(b) * nv + v];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[v] = sh[0];
 }
 
 static hipError_t finish(const double* partial, int nv, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(finish_sum_kernel, dim3((nv + 255) / 256), dim3(256), 0, st, partial, kReduceBlocks, nv, out);
+  hipLaunchKernelGGL(finish_sum_kernel, dim3(nv), dim3(256), 0, st, partial, kReduceBlocks, nv, out);
   return hipGetLastError();
+}
+
+// ---- 16-byte vectorised forms (used when VW = 16 / word bytes divides nv).
+// Thread (cx, y) of a (nv / VW, ry) block handles the 16-byte chunks
+// c = g, g + G, ... (g its global index, G the thread count, a multiple of
+// nv / VW), so its VW columns cx VW .. cx VW + VW - 1 never change and
+// consecutive lanes read consecutive 16 bytes.
+template <class S>
+struct Vec {
+  using W = typename S::word;
+  static constexpr int VW = 16 / int(sizeof(W));
+  static __device__ __forceinline__ void unpack(u32x4 z, W (&w)[VW]) {
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      if constexpr (VW == 1) {
+        w[k] = __builtin_bit_cast(W, z);
+      } else if constexpr (VW == 2) {
+        w[k] = __builtin_bit_cast(W, u32x2{z[2 * k], z[2 * k + 1]});
+      } else {
+        // 4-byte words are uint32_t: plain element reads (a bit cast of a
+        // vector element is miscompiled by this compiler: it reads element 0)
+        static_assert(__is_same(W, uint32_t), "4-byte storage words are uint32_t");
+        w[k] = z[k];
+      }
+    }
+  }
+  static __device__ __forceinline__ u32x4 pack(const W (&w)[VW]) {
+    u32x4 z;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      if constexpr (VW == 1) {
+        z = __builtin_bit_cast(u32x4, w[k]);
+      } else if constexpr (VW == 2) {
+        const u32x2 a = __builtin_bit_cast(u32x2, w[k]);
+        z[2 * k] = a[0];
+        z[2 * k + 1] = a[1];
+      } else {
+        z[k] = w[k];
+      }
+    }
+    return z;
+  }
+};
+
+// VW per-column accumulators of each thread summed over threadIdx.y, written
+// as the block's partial of columns cx VW + k.
+template <int VW>
+__device__ __forceinline__ void vec_block_partial(const double (&acc)[VW], double* sh, double* partial, int nv) {
+  const int cols = blockDim.x, ry = blockDim.y;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    sh[threadIdx.y * cols + threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 1; w < ry; w <<= 1) {
+      if ((threadIdx.y % (2 * w)) == 0 && threadIdx.y + w < ry)
+        sh[threadIdx.y * cols + threadIdx.x] += sh[(threadIdx.y + w) * cols + threadIdx.x];
+      __syncthreads();
+    }
+    if (threadIdx.y == 0) partial[size_t(blockIdx.x) * nv + threadIdx.x * VW + k] = sh[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) norm2_vec_kernel(const u32x4* __restrict__ x, size_t chunks, int nv,
+                                                        double* __restrict__ partial) {
+  using W = typename S::word;
+  constexpr int VW = Vec<S>::VW;
+  extern __shared__ double shd[];
+  const size_t G = size_t(gridDim.x) * blockDim.x * blockDim.y;
+  const size_t g0 = (size_t(blockIdx.x) * blockDim.y + threadIdx.y) * blockDim.x + threadIdx.x;
+  double acc[VW];
+#pragma unroll
+  for (int k = 0; k < VW; ++k) acc[k] = 0.0;
+  // four independent chunks in flight per thread
+  for (size_t c = g0; c < chunks; c += 4 * G) {
+    u32x4 z[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t cu = c + u * G;
+      z[u] = x[cu < chunks ? cu : c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c + u * G < chunks) {
+        W w[VW];
+        Vec<S>::unpack(z[u], w);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+          const cpx<double> q = S::template load<double>(&w[k]);
+          acc[k] = fma(q.r, q.r, fma(q.i, q.i, acc[k]));
+        }
+      }
+    }
+  }
+  vec_block_partial<VW>(acc, shd, partial, nv);
+}
+
+template <class S>
+static bool vec_ok(int nv, const void* p) {
+  return nv % Vec<S>::VW == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+template <class S>
+static void norm2_vec(const void* x, size_t n, int nv, double* partial, hipStream_t st) {
+  const int cols = nv / Vec<S>::VW;
+  const int ry = 256 / cols > 0 ? 256 / cols : 1;
+  const size_t lds = size_t(cols) * ry * sizeof(double);
+  hipLaunchKernelGGL(norm2_vec_kernel<S>, dim3(kReduceBlocks), dim3(cols, ry), lds, st, (const u32x4*)x,
+                     n / Vec<S>::VW, nv, partial);
 }
 
 hipError_t launch_norm2(int dtype, const void* x, size_t sites, int comps, int nv, double* partial, double* out,
                         hipStream_t st) {
   const ColShape c = col_shape(nv);
   const size_t rows = sites * comps;
+  const size_t n = rows * nv;
   const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
   switch (dtype) {
-    case DT_C64: hipLaunchKernelGGL(norm2_kernel<C64>, c.grid, c.block, lds, st, (const float2*)x, rows, nv, partial); break;
-    case DT_C128: hipLaunchKernelGGL(norm2_kernel<C128>, c.grid, c.block, lds, st, (const double2*)x, rows, nv, partial); break;
-    case DT_BF16: hipLaunchKernelGGL(norm2_kernel<BF16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial); break;
-    case DT_F16: hipLaunchKernelGGL(norm2_kernel<F16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial); break;
+    case DT_C64:
+      if (nv <= 512 && vec_ok<C64>(nv, x)) norm2_vec<C64>(x, n, nv, partial, st);
+      else hipLaunchKernelGGL(norm2_kernel<C64>, c.grid, c.block, lds, st, (const float2*)x, rows, nv, partial);
+      break;
+    case DT_C128:
+      if (nv <= 256 && vec_ok<C128>(nv, x)) norm2_vec<C128>(x, n, nv, partial, st);
+      else hipLaunchKernelGGL(norm2_kernel<C128>, c.grid, c.block, lds, st, (const double2*)x, rows, nv, partial);
+      break;
+    case DT_BF16:
+      if (nv <= 1024 && vec_ok<BF16>(nv, x)) norm2_vec<BF16>(x, n, nv, partial, st);
+      else hipLaunchKernelGGL(norm2_kernel<BF16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial);
+      break;
+    case DT_F16:
+      if (nv <= 1024 && vec_ok<F16>(nv, x)) norm2_vec<F16>(x, n, nv, partial, st);
+      else hipLaunchKernelGGL(norm2_kernel<F16>, c.grid, c.block, lds, st, (const uint32_t*)x, rows, nv, partial);
+      break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -231,23 +366,99 @@ __global__ void __launch_bounds__(256) cg_update_xr_kernel(typename S::word* __r
   if (threadIdx.y == 0 && v < nv) partial[size_t(blockIdx.x) * nv + v] = tot;
 }
 
+// Vectorised e += alpha p; r -= alpha q with the |r|^2 partials of the stored
+// (rounded) residual.
+template <class S>
+__global__ void __launch_bounds__(256) cg_update_xr_vec_kernel(u32x4* __restrict__ e, u32x4* __restrict__ r,
+                                                               const u32x4* __restrict__ p,
+                                                               const u32x4* __restrict__ q,
+                                                               const double* __restrict__ alpha, size_t chunks, int nv,
+                                                               double* __restrict__ partial) {
+  using W = typename S::word;
+  constexpr int VW = Vec<S>::VW;
+  extern __shared__ double shd[];
+  const size_t G = size_t(gridDim.x) * blockDim.x * blockDim.y;
+  const size_t g0 = (size_t(blockIdx.x) * blockDim.y + threadIdx.y) * blockDim.x + threadIdx.x;
+  float a[VW];
+  double acc[VW];
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    a[k] = float(alpha[threadIdx.x * VW + k]);
+    acc[k] = 0.0;
+  }
+  for (size_t c = g0; c < chunks; c += 2 * G) {
+    u32x4 ze[2], zp[2], zr[2], zq[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const size_t cu = c + u * G < chunks ? c + u * G : c;
+      ze[u] = e[cu];
+      zp[u] = p[cu];
+      zr[u] = r[cu];
+      zq[u] = q[cu];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (c + u * G < chunks) {
+        W we[VW], wp[VW], wr[VW], wq[VW];
+        Vec<S>::unpack(ze[u], we);
+        Vec<S>::unpack(zp[u], wp);
+        Vec<S>::unpack(zr[u], wr);
+        Vec<S>::unpack(zq[u], wq);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+          S::template store<float>(&we[k], rmadd(S::template load<float>(&we[k]), a[k], S::template load<float>(&wp[k])));
+          S::template store<float>(&wr[k], rmadd(S::template load<float>(&wr[k]), -a[k], S::template load<float>(&wq[k])));
+          const cpx<double> rs = S::template load<double>(&wr[k]);
+          acc[k] = fma(rs.r, rs.r, fma(rs.i, rs.i, acc[k]));
+        }
+        e[c + u * G] = Vec<S>::pack(we);
+        r[c + u * G] = Vec<S>::pack(wr);
+      }
+    }
+  }
+  vec_block_partial<VW>(acc, shd, partial, nv);
+}
+
+template <class S>
+static void cg_update_xr_vec(void* e, void* r, const void* p, const void* q, const double* alpha, size_t n, int nv,
+                             double* partial, hipStream_t st) {
+  const int cols = nv / Vec<S>::VW;
+  const int ry = 256 / cols > 0 ? 256 / cols : 1;
+  const size_t lds = size_t(cols) * ry * sizeof(double);
+  hipLaunchKernelGGL(cg_update_xr_vec_kernel<S>, dim3(kReduceBlocks), dim3(cols, ry), lds, st, (u32x4*)e, (u32x4*)r,
+                     (const u32x4*)p, (const u32x4*)q, alpha, n / Vec<S>::VW, nv, partial);
+}
+
+template <class S>
+static bool vec_ok4(int nv, const void* a, const void* b, const void* c, const void* d) {
+  return vec_ok<S>(nv, a) && vec_ok<S>(nv, b) && vec_ok<S>(nv, c) && vec_ok<S>(nv, d) &&
+         nv / Vec<S>::VW <= 256;
+}
+
 hipError_t launch_cg_update_xr(int dtype, void* e, void* r, const void* p, const void* q, const double* alpha,
                                size_t sites, int comps, int nv, double* partial, double* out, hipStream_t st) {
   const ColShape c = col_shape(nv);
   const size_t rows = sites * comps;
   const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
+  const size_t n = rows * nv;
   switch (dtype) {
     case DT_C64:
-      hipLaunchKernelGGL(cg_update_xr_kernel<C64>, c.grid, c.block, lds, st, (float2*)e, (float2*)r, (const float2*)p,
-                         (const float2*)q, alpha, rows, nv, partial);
+      if (vec_ok4<C64>(nv, e, r, p, q)) cg_update_xr_vec<C64>(e, r, p, q, alpha, n, nv, partial, st);
+      else
+        hipLaunchKernelGGL(cg_update_xr_kernel<C64>, c.grid, c.block, lds, st, (float2*)e, (float2*)r,
+                           (const float2*)p, (const float2*)q, alpha, rows, nv, partial);
       break;
     case DT_BF16:
-      hipLaunchKernelGGL(cg_update_xr_kernel<BF16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
-                         (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
+      if (vec_ok4<BF16>(nv, e, r, p, q)) cg_update_xr_vec<BF16>(e, r, p, q, alpha, n, nv, partial, st);
+      else
+        hipLaunchKernelGGL(cg_update_xr_kernel<BF16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
+                           (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
       break;
     case DT_F16:
-      hipLaunchKernelGGL(cg_update_xr_kernel<F16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
-                         (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
+      if (vec_ok4<F16>(nv, e, r, p, q)) cg_update_xr_vec<F16>(e, r, p, q, alpha, n, nv, partial, st);
+      else
+        hipLaunchKernelGGL(cg_update_xr_kernel<F16>, c.grid, c.block, lds, st, (uint32_t*)e, (uint32_t*)r,
+                           (const uint32_t*)p, (const uint32_t*)q, alpha, rows, nv, partial);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -20,6 +20,11 @@
 
 namespace dsl {
 
+// 16 and 8 bytes as native vectors (HIP's uint4 is a class around a union,
+// which keeps arrays of it in scratch memory instead of registers).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 template <class T>
 struct cpx {
   T r, i;

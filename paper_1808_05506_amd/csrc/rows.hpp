@@ -73,10 +73,6 @@ __device__ __forceinline__ void hold(cpx<T>& z) {
 // fields with COMPS components per site (12 for Wilson spinors, 3 for
 // staggered ones), N_v right-hand sides fastest.
 
-// 16 and 8 bytes as native vectors (HIP's uint4 is a class around a union,
-// which keeps arrays of it in scratch memory instead of registers).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // 16-, 8- or 4-byte pieces, the largest that divides a lane's share of a site
 // (COMPS storage words: the lanes of a site are its N_v right-hand sides).

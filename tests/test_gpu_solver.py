@@ -75,3 +75,20 @@ def test_solve_iteration_limit_reports_noconv():
                       max_outer=1, max_inner=3)
     assert info["status"] == 5
     assert info["relres"][0] > 1e-10
+
+
+@pytest.mark.parametrize("inner,itol", [("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)])
+def test_wilson_solve_nv12_row_kernels(inner, itol):
+    # N_v = 12 on rows of 12 sites: the inner applies run the row-staged
+    # t-marching D_W kernel and the vector updates take their 16-byte forms
+    dims, nv, m0 = (12, 4, 2, 4), 12, 0.05
+    say(f"case solve wilson {dims} nv={nv} inner={inner}")
+    u = synthetic.gauge_links(dims, "smooth", 9)
+    b = synthetic.wilson_spinor(dims, nv, 109)
+    x, info = D.solve("wilson", up(u, "c128"), up(b, "c128"), m0, inner=inner, tol=1e-10, inner_tol=itol)
+    say(f"info {info}")
+    assert info["status"] == 0
+    res = solver.relative_residual(lambda v: wilson.apply(u, v, m0), b, down(x))
+    say(f"oracle residuals {res}")
+    assert np.all(res <= 1e-10)
+    assert np.allclose(info["relres"], res, rtol=1e-3, atol=1e-13)
