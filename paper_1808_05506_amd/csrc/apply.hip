@@ -144,7 +144,11 @@ hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* 
       if (e != hipErrorNotSupported) return e;
       return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, mass, st);
     }
-    case OP_BRILLOUIN: return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, mass, st);
+    case OP_BRILLOUIN: {
+      const hipError_t e = launch_brillouin_rows(adj, dtype, g, U, in, out, mass, st);
+      if (e != hipErrorNotSupported) return e;
+      return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, mass, st);
+    }
   }
   return hipErrorInvalidValue;
 }

@@ -109,24 +109,6 @@ struct RowPieces {
   static constexpr int CH = 12 * int(sizeof(typename S::word)) / 16;
 };
 
-// LDS stride of one site in the row buffer, in storage words.  For a fixed
-// spin-colour component the lanes of one site read a window of N_v words;
-// consecutive sites are placed so that their windows fall on consecutive LDS
-// banks (stride = window mod 64 dwords), which makes the per-component reads
-// of a wave conflict-free.  The unpadded stride (12 N_v words) is a multiple
-// of 64 dwords for FP32 N_v = 12 and would put every site on the same banks.
-// Padding is skipped when it would cost more than a quarter of the row.
-template <int NV, class S>
-struct SiteStride {
-  static constexpr int WB = int(sizeof(typename S::word));
-  static constexpr int SWD = 12 * NV * WB / 4;                // dwords per site, unpadded
-  static constexpr int WIN = NV * WB / 4;                     // dwords per component window
-  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
-  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % 16 == 0) ? SWD + PAD : SWD;
-  static constexpr int WORDS = DW * 4 / WB;                   // site stride in storage words
-  static constexpr int PIECES = DW * 4 / 16;                  // site stride in 16-byte pieces
-};
-
 template <int NV, class S>
 size_t rows_lds_words(int R) {
   return size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R + 1) * 36 + size_t(R) * 9;

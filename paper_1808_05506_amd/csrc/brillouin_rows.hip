@@ -1,0 +1,321 @@
+// Row-staged D_B (Sec. 5; see rows.hpp for the row staging).  A workgroup
+// owns an x-row chunk of R sites and all N_v right-hand sides (thread (x, v)).
+// The 80 hops of the 3^4 stencil reach the 27 rows (y + dy, z + dz, t + dt),
+// dy, dz, dt in {-1, 0, 1}; each such row is staged once, with the halo sites
+// x0 - 1 and x0 + n, through one LDS buffer with coalesced 16-byte loads, and
+// serves the hops d = (dx, dy, dz, dt), dx in {-1, 0, 1}.  With each row come
+// the three link columns those hops need: W_d(x) at the chunk's own sites when
+// d is one of the 40 stored directions, else W_{-d}(x + d) at the neighbour
+// row's sites, applied as its adjoint.  Thread (x, v) accumulates
+//   out(x) = (m0 + 15/8) psi(x) + sum_d (-lambda_k / 2 + rho_k d.gamma) W_d(x) psi(x + d)
+// (rho_k -> -rho_k for the adjoint) in registers over the 27 rows and writes
+// its output once, through LDS with coalesced 16-byte stores.
+#include <stdlib.h>
+
+#include "launch.hpp"
+#include "rows.hpp"
+
+namespace dsl {
+
+namespace {
+
+constexpr int kBriRows = 27;  // (dy, dz, dt) in {-1, 0, 1}^3, row 13 is the own row
+
+DSL_HD void bri_row_offset(int r, int& dy, int& dz, int& dt) {
+  dy = r % 3 - 1;
+  dz = (r / 3) % 3 - 1;
+  dt = r / 9 - 1;
+}
+
+DSL_HD uint32_t bri_row_base(const Geom& g, const RowChunk& c, int dy, int dz, int dt) {
+  int y = c.y + dy, z = c.z + dz, t = c.t + dt;
+  y = y < 0 ? y + g.n[1] : (y >= g.n[1] ? y - g.n[1] : y);
+  z = z < 0 ? z + g.n[2] : (z >= g.n[2] ? z - g.n[2] : z);
+  t = t < 0 ? t + g.n[3] : (t >= g.n[3] ? t - g.n[3] : t);
+  return uint32_t(g.stride[1] * y + g.stride[2] * z + g.stride[3] * t);
+}
+
+// base-3 code n(d) = sum_mu (d_mu + 1) 3^mu; d is stored (in slot n - 41) iff n > 40
+DSL_HD int bri_code(int dx, int dy, int dz, int dt) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1) + 27 * (dt + 1); }
+
+template <int NV, class S>
+struct BriStage {
+  using W = typename S::word;
+  static constexpr int SW = 12 * NV;                  // words per site
+  static constexpr int SP = SW * int(sizeof(W)) / 16; // 16-byte pieces per site
+  static constexpr int CH = SP / NV;                  // pieces per lane
+  static constexpr int KW = (27 + NV - 1) / NV;       // link words per thread (27 n words per row)
+  // halo pieces per thread for a chunk of at least 12 sites (the launcher checks)
+  static constexpr int HK = (2 * SP + 12 * NV - 1) / (12 * NV);
+};
+
+// A staged row in flight: the lane's pieces of its site, one piece of the halo
+// sites, and its words of the row's three link columns.
+template <int NV, class S>
+struct BriRowRegs {
+  u32x4 p[BriStage<NV, S>::CH];
+  u32x4 halo[BriStage<NV, S>::HK];
+  typename S::word w[BriStage<NV, S>::KW];
+};
+
+template <int NV, class S>
+__device__ __forceinline__ void bri_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ Wl,
+                                          const typename S::word* __restrict__ in, int r, int xm, int xp, int xl,
+                                          int v, int tid, int nth, BriRowRegs<NV, S>& q) {
+  using St = BriStage<NV, S>;
+  int dy, dz, dt;
+  bri_row_offset(r, dy, dz, dt);
+  const uint32_t nb = bri_row_base(g, c, dy, dz, dt);
+  const int xc = xl < c.n ? xl : c.n - 1;
+  const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(nb + c.x0) * St::SW);
+#pragma unroll
+  for (int j = 0; j < St::CH; ++j) q.p[j] = src[xc * St::SP + j * NV + v];
+#pragma unroll
+  for (int k = 0; k < St::HK; ++k) {
+    int h = tid + k * nth;
+    h = h < 2 * St::SP ? h : 2 * St::SP - 1;
+    const int hs = h < St::SP ? xm : xp;
+    q.halo[k] = reinterpret_cast<const u32x4*>(in + size_t(nb + hs) * St::SW)[h < St::SP ? h : h - St::SP];
+  }
+  // link columns dx = -1, 0, 1: 9 words per site of the chunk
+  const int nw = 27 * c.n;
+#pragma unroll
+  for (int k = 0; k < St::KW; ++k) {
+    int w = tid + k * nth;
+    w = w < nw ? w : nw - 1;
+    const int col = w / (9 * c.n), rem = w - col * 9 * c.n;
+    const int site = rem / 9, e = rem - site * 9;
+    const int dx = col - 1;
+    const int code = bri_code(dx, dy, dz, dt);
+    size_t idx;
+    if (code > 40) {
+      idx = (size_t(c.row_base + c.x0 + site) * 40 + (code - 41)) * 9 + e;  // W_d(x), stored
+    } else {
+      // W_{-d}(x + d), slot n(-d) - 41 = 39 - n(d); for d = 0 any valid word (unused)
+      const int slot = code == 40 ? 0 : 39 - code;
+      idx = (size_t(nb + wrap_x(g, c.x0 + site + dx)) * 40 + slot) * 9 + e;
+    }
+    q.w[k] = Wl[idx];
+  }
+}
+
+template <int NV, class S>
+__device__ __forceinline__ void bri_commit(const RowChunk& c, const BriRowRegs<NV, S>& q, typename S::word* buf,
+                                           typename S::word* wbuf, int R, int xl, int v, int tid, int nth) {
+  using St = BriStage<NV, S>;
+  constexpr int SSP = SiteStride<NV, S>::PIECES;
+  const int xc = xl < c.n ? xl : c.n - 1;
+  u32x4* dst = reinterpret_cast<u32x4*>(buf) + (xc + 1) * SSP;
+#pragma unroll
+  for (int j = 0; j < St::CH; ++j) dst[j * NV + v] = q.p[j];
+#pragma unroll
+  for (int k = 0; k < St::HK; ++k) {
+    int h = tid + k * nth;
+    h = h < 2 * St::SP ? h : 2 * St::SP - 1;
+    u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < St::SP ? 0 : (c.n + 1) * SSP);
+    hdst[h < St::SP ? h : h - St::SP] = q.halo[k];
+  }
+  const int nw = 27 * c.n;
+#pragma unroll
+  for (int k = 0; k < St::KW; ++k) {
+    int w = tid + k * nth;
+    w = w < nw ? w : nw - 1;
+    const int col = w / (9 * c.n), rem = w - col * 9 * c.n;
+    wbuf[col * R * 9 + rem] = q.w[k];
+  }
+}
+
+// acc += (a + b d.gamma) chi for chi = W' psi, one hop of row (dy, dz, dt)
+template <int NV, class S, class T>
+__device__ __forceinline__ void bri_hop(const typename S::word* site, const typename S::word* link, bool dag, int v,
+                                        T a, T B1, T B2, T B3, T B4, int d0, int d1, int d2, int d3,
+                                        cpx<T> (&acc)[4][3]) {
+  cpx<T> u[3][3], p[4][3];
+  // W' = link or its adjoint (dag is the same for every lane)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const cpx<T> l = S::template load<T>(link + (dag ? j * 3 + i : i * 3 + j));
+      u[i][j].r = l.r;
+      u[i][j].i = dag ? -l.i : l.i;
+    }
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) p[sp][cc] = S::template load<T>(site + (sp * 3 + cc) * NV + v);
+  // one colour row of chi = W' psi at a time (the spin factor does not mix
+  // colours): upper spins += S chi_low, lower += S^dag chi_up with
+  // S = sum_mu d_mu s_mu; d_mu is the same for every lane (uniform branches)
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    cpx<T> chi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cpx<T> t = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t = cmadd(t, u[cc][b], p[q][b]);
+      chi[q] = t;
+      acc[q][cc] = rmadd(acc[q][cc], a, t);
+    }
+    if (d3 != 0) {
+      acc[0][cc] = rmadd(acc[0][cc], B4, chi[2]);
+      acc[1][cc] = rmadd(acc[1][cc], B4, chi[3]);
+      acc[2][cc] = rmadd(acc[2][cc], B4, chi[0]);
+      acc[3][cc] = rmadd(acc[3][cc], B4, chi[1]);
+    }
+    if (d2 != 0) {
+      acc[0][cc] = cmadd_i(acc[0][cc], -B3, chi[2]);
+      acc[1][cc] = cmadd_i(acc[1][cc], B3, chi[3]);
+      acc[2][cc] = cmadd_i(acc[2][cc], B3, chi[0]);
+      acc[3][cc] = cmadd_i(acc[3][cc], -B3, chi[1]);
+    }
+    if (d1 != 0) {
+      acc[0][cc] = rmadd(acc[0][cc], -B2, chi[3]);
+      acc[1][cc] = rmadd(acc[1][cc], B2, chi[2]);
+      acc[2][cc] = rmadd(acc[2][cc], B2, chi[1]);
+      acc[3][cc] = rmadd(acc[3][cc], -B2, chi[0]);
+    }
+    if (d0 != 0) {
+      acc[0][cc] = cmadd_i(acc[0][cc], -B1, chi[3]);
+      acc[1][cc] = cmadd_i(acc[1][cc], -B1, chi[2]);
+      acc[2][cc] = cmadd_i(acc[2][cc], B1, chi[1]);
+      acc[3][cc] = cmadd_i(acc[3][cc], B1, chi[0]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) hold(acc[q][cc]);
+}
+
+// The three hops of staged row r (and the diagonal term for the own row).
+template <bool ADJ, int NV, class S, class T>
+__device__ __forceinline__ void bri_row_compute(int r, const typename S::word* buf, const typename S::word* wbuf,
+                                                int R, int xl, int v, T diag, cpx<T> (&acc)[4][3]) {
+  constexpr int SSW = SiteStride<NV, S>::WORDS;
+  int dy, dz, dt;
+  bri_row_offset(r, dy, dz, dt);
+#pragma unroll
+  for (int dx = -1; dx <= 1; ++dx) {
+    const int k = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
+    const typename S::word* site = buf + (xl + 1 + dx) * SSW;
+    if (k == 0) {
+      // own site: the diagonal term
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          acc[q][cc] = rmadd(acc[q][cc], diag, S::template load<T>(site + (q * 3 + cc) * NV + v));
+      continue;
+    }
+    const T a = T(-0.5) * bri_lambda<T>(k);
+    const T b = (ADJ ? T(-1) : T(1)) * bri_rho<T>(k);
+    const typename S::word* link = wbuf + (dx + 1) * R * 9 + xl * 9;
+    bri_hop<NV, S, T>(site, link, bri_code(dx, dy, dz, dt) <= 40, v, a, b * T(dx), b * T(dy), b * T(dz), b * T(dt),
+                      dx, dy, dz, dt, acc);
+  }
+}
+
+
+}  // namespace
+
+template <bool ADJ, int NV, class S, class T>
+__global__ void __launch_bounds__(256, 3)
+    brillouin_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ Wl,
+                          const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
+  using W = typename S::word;
+  using St = BriStage<NV, S>;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
+  extern __shared__ uint4 smem_bri[];
+  const int R = int(tr.sb);
+  W* buf = reinterpret_cast<W*>(smem_bri);
+  W* wbuf = buf + (R + 2) * SSW;  // [3][R][9]
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const RowChunk c = row_chunk(g, tr, L);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v, nth = R * NV;
+  const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) acc[q][cc] = zero<T>();
+
+  // one row in flight while the previous one is applied (three hops of
+  // about a thousand instructions per lane hide the load latency); the
+  // request after the last row repeats it, unused, so every load is
+  // unconditional and in bounds
+  BriRowRegs<NV, S> q;
+  bri_issue<NV, S>(g, c, Wl, in, 0, xm, xp, xl, v, tid, nth, q);
+#pragma nounroll
+  for (int r = 0; r < kBriRows; ++r) {
+    bri_commit<NV, S>(c, q, buf, wbuf, R, xl, v, tid, nth);
+    __syncthreads();
+    bri_issue<NV, S>(g, c, Wl, in, r + 1 < kBriRows ? r + 1 : kBriRows - 1, xm, xp, xl, v, tid, nth, q);
+    bri_row_compute<ADJ, NV, S, T>(r, buf, wbuf, R, xl, v, diag, acc);
+    __syncthreads();
+  }
+  // output through LDS, coalesced 16-byte stores
+  {
+    W* o = buf + xl * SSW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) S::template store<T>(o + (q * 3 + cc) * NV + v, acc[q][cc]);
+  }
+  __syncthreads();
+  {
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0) * St::SW);
+    u32x4 o[St::CH];
+#pragma unroll
+    for (int j = 0; j < St::CH; ++j) o[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < St::CH; ++j) __builtin_nontemporal_store(o[j], &dst[xc * St::SP + j * NV + v]);
+  }
+}
+
+template <int NV, class S, class T>
+static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* Wl, const void* in,
+                                   void* out, double mass, hipStream_t st) {
+  using W = typename S::word;
+  const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+  const size_t lds = (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(3 * R) * 9) * sizeof(W);
+  const T diag = T(mass) + T(15.0 / 8.0);
+  if (adj)
+    hipLaunchKernelGGL((brillouin_rows_kernel<true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl,
+                       (const W*)in, (W*)out, diag);
+  else
+    hipLaunchKernelGGL((brillouin_rows_kernel<false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl,
+                       (const W*)in, (W*)out, diag);
+  return hipGetLastError();
+}
+
+// Row-staged D_B for N_v = 12 in C64.  Returns hipErrorNotSupported
+// when the configuration is not covered (the caller then uses the direct
+// kernel).  DSLASH_ROWS=0 disables it.
+hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
+                                 double mass, hipStream_t st) {
+  if (const char* e = getenv("DSLASH_ROWS"))
+    if (atoi(e) == 0) return hipErrorNotSupported;
+  // FP32 only: the FP64 variant would not fit in registers
+  if (g.nv != 12 || dtype != DT_C64) return hipErrorNotSupported;
+  int R = row_sites_default(g.n[0], g.nv);
+  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  if (R > g.n[0]) R = g.n[0];
+  // at least 12 sites: the halo sites (2 * 12 N_v words) take at most one
+  // 16-byte piece per thread
+  if (R < 12 || R * g.nv > 256) return hipErrorNotSupported;
+  int bt = 2;
+  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bool xcd = true;
+  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  return brillouin_rows_t<12, C64, float>(adj, g, R, bt, xcd, Wl, in, out, mass, st);
+}
+
+}  // namespace dsl

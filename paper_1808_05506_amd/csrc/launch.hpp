@@ -30,6 +30,8 @@ hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void
                               double mass, hipStream_t st);
 hipError_t launch_staggered_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st);
+hipError_t launch_brillouin_rows(bool adjoint, int dtype, const Geom& g, const void* W, const void* in, void* out,
+                                 double mass, hipStream_t st);
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st);

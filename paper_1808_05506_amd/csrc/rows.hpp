@@ -61,6 +61,24 @@ inline int row_sites_default(int nx, int nv) {
 
 DSL_HD int wrap_x(const Geom& g, int x) { return x < 0 ? x + g.n[0] : (x >= g.n[0] ? x - g.n[0] : x); }
 
+// LDS stride of one site in the row buffer, in storage words.  For a fixed
+// spin-colour component the lanes of one site read a window of N_v words;
+// consecutive sites are placed so that their windows fall on consecutive LDS
+// banks (stride = window mod 64 dwords), which makes the per-component reads
+// of a wave conflict-free.  The unpadded stride (12 N_v words) is a multiple
+// of 64 dwords for FP32 N_v = 12 and would put every site on the same banks.
+// Padding is skipped when it would cost more than a quarter of the row.
+template <int NV, class S>
+struct SiteStride {
+  static constexpr int WB = int(sizeof(typename S::word));
+  static constexpr int SWD = 12 * NV * WB / 4;                // dwords per site, unpadded
+  static constexpr int WIN = NV * WB / 4;                     // dwords per component window
+  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
+  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % 16 == 0) ? SWD + PAD : SWD;
+  static constexpr int WORDS = DW * 4 / WB;                   // site stride in storage words
+  static constexpr int PIECES = DW * 4 / 16;                  // site stride in 16-byte pieces
+};
+
 // Empty register constraint on an accumulator: keeps a hop's arithmetic
 // before the next barrier.  Without it the scheduler may sink all hops of a
 // workgroup to its end, keeping every staged operand live in registers.

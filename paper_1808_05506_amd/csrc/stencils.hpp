@@ -234,6 +234,13 @@ DSL_HD void su3_mul4(const cpx<T> (&w)[3][3], const cpx<T> (&p)[4][3], cpx<T> (&
 }
 
 // (alpha + i beta) * y added to acc
+// acc + i beta y
+template <class T> DSL_HD cpx<T> cmadd_i(cpx<T> acc, T beta, cpx<T> y) {
+  acc.r = fma(-beta, y.i, acc.r);
+  acc.i = fma(beta, y.r, acc.i);
+  return acc;
+}
+
 template <class T> DSL_HD cpx<T> cmadd_ab(cpx<T> acc, T alpha, T beta, cpx<T> y) {
   acc.r = fma(alpha, y.r, acc.r);
   acc.r = fma(-beta, y.i, acc.r);
@@ -291,23 +298,54 @@ DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W
       load_wspinor<S, T>(in, size_t(sm) * sps + v, nv, p);
       su3_mul4<true, T>(w, p, chi_m);
     }
+    // a (chi_+ + chi_-) + b (d.gamma)(chi_+ - chi_-); with S = sum_mu d_mu s_mu
+    // (s_k = -i sigma_k, s_4 = 1) the upper spins take S y_low and the lower
+    // ones S^dag y_up.  Each axis contributes only if d_mu != 0: the test is
+    // uniform over the wave (one direction per iteration for every lane), so
+    // the k-hop directions pay for k axes, not four.
+    cpx<T> y[4][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cpx<T> y[4];
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int c = 0; c < 3; ++c) {
         acc[q][c] = rmadd(acc[q][c], a, chi_p[q][c] + chi_m[q][c]);
-        y[q] = chi_p[q][c] - chi_m[q][c];
+        y[q][c] = chi_p[q][c] - chi_m[q][c];
       }
-      // upper += S y_low, lower += S^dag y_up
-      acc[0][c] = cmadd_ab(acc[0][c], B4, -B3, y[2]);
-      acc[0][c] = cmadd_ab(acc[0][c], -B2, -B1, y[3]);
-      acc[1][c] = cmadd_ab(acc[1][c], B2, -B1, y[2]);
-      acc[1][c] = cmadd_ab(acc[1][c], B4, B3, y[3]);
-      acc[2][c] = cmadd_ab(acc[2][c], B4, B3, y[0]);
-      acc[2][c] = cmadd_ab(acc[2][c], B2, B1, y[1]);
-      acc[3][c] = cmadd_ab(acc[3][c], -B2, B1, y[0]);
-      acc[3][c] = cmadd_ab(acc[3][c], B4, -B3, y[1]);
+    if (d[3] != 0) {  // s_4 = 1
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[0][c] = rmadd(acc[0][c], B4, y[2][c]);
+        acc[1][c] = rmadd(acc[1][c], B4, y[3][c]);
+        acc[2][c] = rmadd(acc[2][c], B4, y[0][c]);
+        acc[3][c] = rmadd(acc[3][c], B4, y[1][c]);
+      }
+    }
+    if (d[2] != 0) {  // s_3 = diag(-i, i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[0][c] = cmadd_i(acc[0][c], -B3, y[2][c]);
+        acc[1][c] = cmadd_i(acc[1][c], B3, y[3][c]);
+        acc[2][c] = cmadd_i(acc[2][c], B3, y[0][c]);
+        acc[3][c] = cmadd_i(acc[3][c], -B3, y[1][c]);
+      }
+    }
+    if (d[1] != 0) {  // s_2 = [[0, -1], [1, 0]]
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[0][c] = rmadd(acc[0][c], -B2, y[3][c]);
+        acc[1][c] = rmadd(acc[1][c], B2, y[2][c]);
+        acc[2][c] = rmadd(acc[2][c], B2, y[1][c]);
+        acc[3][c] = rmadd(acc[3][c], -B2, y[0][c]);
+      }
+    }
+    if (d[0] != 0) {  // s_1 = [[0, -i], [-i, 0]]
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[0][c] = cmadd_i(acc[0][c], -B1, y[3][c]);
+        acc[1][c] = cmadd_i(acc[1][c], -B1, y[2][c]);
+        acc[2][c] = cmadd_i(acc[2][c], B1, y[1][c]);
+        acc[3][c] = cmadd_i(acc[3][c], B1, y[0][c]);
+      }
     }
   }
   const size_t base = size_t(s) * sps + v;

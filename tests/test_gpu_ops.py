@@ -290,3 +290,21 @@ def test_staggered_32to4_nv12_sampled(dt):
     del out
     torch.cuda.empty_cache()
     compare(got, local.staggered_at(u, p, 0.0, sites), dt, "D_S 32^4 sampled")
+
+
+@pytest.mark.parametrize("kernel", ["rows", "direct"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("dims", [(16, 3, 2, 4), (12, 2, 3, 3), (24, 3, 2, 2), (20, 2, 2, 3)])
+def test_brillouin_row_staged_path(kernel, adj, dims, monkeypatch):
+    # N_v = 12 in FP32 with rows of >= 12 sites runs the row-staged D_B kernel
+    # (27 staged rows per output row, own-site and neighbour-site links);
+    # 24 sites split into 12 + 12, 20 sites fall back to the direct kernel
+    # (the even split 10 + 10 is below 12 sites); DSLASH_ROWS=0 forces the direct one
+    nv, dt = 12, "c64"
+    monkeypatch.setenv("DSLASH_ROWS", "1" if kernel == "rows" else "0")
+    say(f"case brillouin {kernel} {dims} nv={nv} {dt} adj={adj}")
+    v = synthetic.gauge_links(dims, "haar", 33)
+    w = rounded(brillouin.build(v), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 34), dt)
+    out = D.apply("brillouin", up(w, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), brillouin.apply(w, p, 0.1, adj), dt, f"D_B {kernel}")
