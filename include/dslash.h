@@ -166,6 +166,52 @@ int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int 
                  int max_inner, void* workspace, size_t ws_bytes, double* final_relres, int* iters,
                  void* stream);
 
+/*
+ * Even-odd (checkerboard) form of D_W, the eo-decomposition named as a next
+ * tuning step at the end of Sec. 4.  All four extents must be even (E_ARG
+ * otherwise).  parity(x) = (x + y + z + t) mod 2; every hop of D_W joins
+ * opposite parities, so D_W = [[A, H_eo], [H_oe, A]] with A = 4 + m0 and
+ *   H in(x) = -1/2 sum_mu [(1 - gamma_mu) V_mu(x) in(x+mu) + (1 + gamma_mu) V_mu(x-mu)^dag in(x-mu)].
+ * Packed layout of one parity p: [Nt][Nz][Ny][Nx/2][...], the packed index
+ * i of row (y, z, t) holding x = 2 i + ((p + y + z + t) mod 2).
+ *
+ * dslash_eo_pack: split a full-lattice array with site_bytes bytes per site
+ * (e.g. 12 Nc Nv or 4 Nc Nc storage words) into its even and odd packed
+ * halves; dslash_eo_unpack is the inverse.  No arithmetic; any dtype (the
+ * caller states the bytes).  Outputs may not overlap inputs (E_ALIAS).
+ */
+int dslash_eo_pack(const void* full, void* even, void* odd, const int dims[4], size_t site_bytes, void* stream);
+int dslash_eo_unpack(const void* even, const void* odd, void* full, const int dims[4], size_t site_bytes,
+                     void* stream);
+
+/*
+ * out = H in restricted to output parity `parity_out` (0 or 1): in is a
+ * packed field of parity 1 - parity_out, out a packed field of parity
+ * parity_out, both [..][Nx/2][4][Nc][Nv].  U_even, U_odd: the links V packed
+ * by parity ([..][Nx/2][4][Nc][Nc] each; V_mu(x) of the forward hops comes
+ * from the output parity, V_mu(x - mu) of the backward hops from the other).
+ * adjoint != 0: gamma_mu -> -gamma_mu (H^dag = gamma_5 H gamma_5).  Any dtype;
+ * in == out -> E_ALIAS.
+ */
+int dslash_eo_hop(const void* U_even, const void* U_odd, const void* in, void* out, const int dims[4], int Nc,
+                  int Nv, int parity_out, int adjoint, int dtype, void* stream);
+
+/* Workspace bytes dslash_solve_eo needs (0 on bad arguments). */
+size_t dslash_solve_eo_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype);
+
+/*
+ * Solve D_W x = b as dslash_solve(WILSON, ...) does -- the same FP64 outer
+ * defect correction on the full lattice, the same arguments and results --
+ * with the inner solve on the even-site Schur complement
+ *   M = A - H_eo A^-1 H_oe:   M e_e = rhat_e - H_eo A^-1 rhat_o  (CG on M^dag M),
+ *   e_o = A^-1 (rhat_o - H_oe e_e),
+ * in inner_dtype storage (C64, BF16 or F16) with FP32 arithmetic.  All
+ * extents must be even.  Synchronises the stream.
+ */
+int dslash_solve_eo(const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv, double m0,
+                    int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner, void* workspace,
+                    size_t ws_bytes, double* final_relres, int* iters, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* dslash_status_string(int status);
 

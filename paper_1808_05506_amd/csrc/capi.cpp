@@ -78,7 +78,7 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 100; }
+int dslash_version(void) { return 101; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
                         int Nv, double mass, int dtype, void* stream) {
@@ -215,6 +215,112 @@ int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int 
   a.final_relres = final_relres;
   a.iters = iters;
   a.stream = (hipStream_t)stream;
+  return dsl::solve(a);
+}
+
+// ---------------------------------------------------------------- even-odd
+static int check_even(const int dims[4]) {
+  for (int i = 0; i < 4; ++i)
+    if (dims[i] & 1) return fail(DSLASH_E_ARG, "even-odd form needs even extents (dims[%d] = %d)", i, dims[i]);
+  return DSLASH_OK;
+}
+
+static int eo_copy_common(bool to_packed, const void* full, const void* even, const void* odd, const int dims[4],
+                          size_t site_bytes, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_WILSON, dims, 3, 1)) return rc;
+  if (int rc = check_even(dims)) return rc;
+  if (!full || !even || !odd) return fail(DSLASH_E_ARG, "NULL field pointer");
+  if (site_bytes == 0 || site_bytes % 4) return fail(DSLASH_E_ARG, "site_bytes must be a positive multiple of 4");
+  const size_t half = size_t(volume(dims) / 2) * site_bytes;
+  if (overlap(full, 2 * half, even, half) || overlap(full, 2 * half, odd, half) || overlap(even, half, odd, half))
+    return fail(DSLASH_E_ALIAS, "full, even and odd arrays must not overlap");
+  const dsl::EoGeom e = dsl::make_eo_geom(dims, 1);
+  hipError_t err = dsl::launch_eo_copy(to_packed, e, 0, to_packed ? full : even, to_packed ? (void*)even : (void*)full,
+                                       site_bytes, (hipStream_t)stream);
+  if (err == hipSuccess)
+    err = dsl::launch_eo_copy(to_packed, e, 1, to_packed ? full : odd, to_packed ? (void*)odd : (void*)full,
+                              site_bytes, (hipStream_t)stream);
+  if (err != hipSuccess) return hip_fail(err, "dslash_eo copy launch");
+  return DSLASH_OK;
+}
+
+int dslash_eo_pack(const void* full, void* even, void* odd, const int dims[4], size_t site_bytes, void* stream) {
+  return eo_copy_common(true, full, even, odd, dims, site_bytes, stream);
+}
+
+int dslash_eo_unpack(const void* even, const void* odd, void* full, const int dims[4], size_t site_bytes,
+                     void* stream) {
+  return eo_copy_common(false, full, even, odd, dims, site_bytes, stream);
+}
+
+int dslash_eo_hop(const void* U_even, const void* U_odd, const void* in, void* out, const int dims[4], int Nc,
+                  int Nv, int parity_out, int adjoint, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_WILSON, dims, Nc, Nv)) return rc;
+  if (int rc = check_even(dims)) return rc;
+  if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
+  if (parity_out != 0 && parity_out != 1) return fail(DSLASH_E_ARG, "parity_out must be 0 or 1 (got %d)", parity_out);
+  if (!U_even || !U_odd || !in || !out) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t hspin = size_t(volume(dims) / 2) * 12 * Nv * eb, hlink = size_t(volume(dims) / 2) * 36 * eb;
+  if (overlap(in, hspin, out, hspin)) return fail(DSLASH_E_ALIAS, "in and out overlap");
+  if (overlap(U_even, hlink, out, hspin) || overlap(U_odd, hlink, out, hspin))
+    return fail(DSLASH_E_ALIAS, "links and out overlap");
+  const dsl::EoGeom e = dsl::make_eo_geom(dims, Nv);
+  const void* Uo = parity_out == 0 ? U_even : U_odd;
+  const void* Ui = parity_out == 0 ? U_odd : U_even;
+  hipError_t err = dsl::launch_wilson_eo_hop(adjoint != 0, dtype, e, parity_out, Uo, Ui, in, out, nullptr, 0.0, 1.0,
+                                             (hipStream_t)stream);
+  if (err != hipSuccess) return hip_fail(err, "dslash_eo_hop launch");
+  return DSLASH_OK;
+}
+
+size_t dslash_solve_eo_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype) {
+  if (check_geom(DSLASH_WILSON, dims, Nc, Nv) || check_even(dims)) return 0;
+  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16) return 0;
+  return dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, true);
+}
+
+int dslash_solve_eo(const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv, double m0,
+                    int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner, void* workspace,
+                    size_t ws_bytes, double* final_relres, int* iters, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_WILSON, dims, Nc, Nv)) return rc;
+  if (int rc = check_even(dims)) return rc;
+  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16)
+    return fail(DSLASH_E_ARG, "inner dtype must be C64, BF16 or F16 (got %d)", inner_dtype);
+  if (!U64 || !b64 || !x64) return fail(DSLASH_E_ARG, "NULL field pointer");
+  if (!(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1)) return fail(DSLASH_E_ARG, "need tol > 0, 0 < inner_tol < 1");
+  if (max_outer < 1 || max_inner < 1) return fail(DSLASH_E_ARG, "iteration limits must be >= 1");
+  if (!(4.0 + m0 != 0.0)) return fail(DSLASH_E_ARG, "4 + m0 must be non-zero");
+  const size_t need = dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, true);
+  if (!workspace || ws_bytes < need)
+    return fail(DSLASH_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, workspace ? ws_bytes : size_t(0));
+  const uint64_t vol = volume(dims);
+  const size_t nspin = size_t(vol) * 12 * Nv * 16;
+  const size_t nlink = size_t(vol) * 36 * 16;
+  if (overlap(x64, nspin, b64, nspin) || overlap(x64, nspin, U64, nlink) || overlap(x64, nspin, workspace, need) ||
+      overlap(workspace, need, U64, nlink) || overlap(workspace, need, b64, nspin))
+    return fail(DSLASH_E_ALIAS, "x, b, U and workspace must not overlap");
+  dsl::SolveArgs a;
+  a.op = DSLASH_WILSON;
+  a.U64 = U64;
+  a.b64 = b64;
+  a.x64 = x64;
+  for (int i = 0; i < 4; ++i) a.dims[i] = dims[i];
+  a.nv = Nv;
+  a.mass = m0;
+  a.inner_dtype = inner_dtype;
+  a.tol = tol;
+  a.inner_tol = inner_tol;
+  a.max_outer = max_outer;
+  a.max_inner = max_inner;
+  a.workspace = workspace;
+  a.final_relres = final_relres;
+  a.iters = iters;
+  a.stream = (hipStream_t)stream;
+  a.eo = true;
   return dsl::solve(a);
 }
 

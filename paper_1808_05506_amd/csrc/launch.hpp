@@ -39,6 +39,23 @@ hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, c
                             hipStream_t st);
 hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t st);
 
+// ---- even-odd (checkerboard) form of D_W (eo.hip)
+struct EoGeom {
+  int n[4];       // full extents (all even)
+  int nh;         // Nx / 2: packed sites per row
+  uint32_t hvol;  // sites of one parity
+  int nv;
+  FastDiv dnh, dy, dz;
+};
+EoGeom make_eo_geom(const int dims[4], int nv);
+// full <-> packed parity `parity` copy of `site_bytes` bytes per site
+hipError_t launch_eo_copy(bool to_packed, const EoGeom& e, int parity, const void* src, void* dst, size_t site_bytes,
+                          hipStream_t st);
+// out = c_add add + c_hop H in on the packed parity-`parity` sites (add may be null)
+hipError_t launch_wilson_eo_hop(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
+                                const void* in, void* out, const void* add, double c_add, double c_hop,
+                                hipStream_t st);
+
 // ---- solver BLAS-1 (fields of `comps` complex numbers per site times nv columns,
 //      column index fastest; per-column scalars are device arrays of nv doubles)
 constexpr int kReduceBlocks = 512;

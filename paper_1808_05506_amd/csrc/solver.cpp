@@ -8,6 +8,11 @@
 //                  ||r_inner|| / ||r_inner,0|| <= inner_tol
 //   update (FP64): x += rms(r) * e
 //
+// Even-odd variant (WILSON): the inner solve works on the even-site Schur
+// complement M = A - H_eo A^-1 H_oe of D_W = [[A, H_eo], [H_oe, A]] in the
+// packed checkerboard layout: CG on M^dag M e_e = M^dag (rhat_e - H_eo rhat_o / A),
+// then e_o = (rhat_o - H_oe e_e) / A; the outer loop is unchanged.
+//
 // Every vector operation runs in a HIP kernel; the host only sequences the
 // launches and reads the per-column norms (Nv doubles) to decide convergence.
 #include "solver.hpp"
@@ -31,7 +36,44 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t u_lo, e, r, p, q, s, t64, r64, partial, scal, total;
   size_t field_lo, field64, links_lo;
+  // even-odd only: full-lattice links before packing, the scaled residual
+  // (full), its packed halves, the odd temporary and the odd solution
+  size_t u_full, rfull, re, ro, tmp, eodd;
 };
+
+Layout layout_eo(const int dims[4], int nv, int lodt) {
+  const size_t vol = size_t(dims[0]) * dims[1] * dims[2] * dims[3];
+  Layout L;
+  L.links_lo = vol * 4 * 9;
+  L.field_lo = vol * 12 * nv;
+  L.field64 = L.field_lo;
+  const size_t half = L.field_lo / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t eb = dtype_bytes(lodt);
+  L.u_lo = take(L.links_lo * eb);  // even half, then odd half
+  L.u_full = take(L.links_lo * eb);
+  L.rfull = take(L.field_lo * eb);
+  L.re = take(half * eb);
+  L.ro = take(half * eb);
+  L.e = take(half * eb);
+  L.r = take(half * eb);
+  L.p = take(half * eb);
+  L.q = take(half * eb);
+  L.s = take(half * eb);
+  L.tmp = take(half * eb);
+  L.eodd = take(half * eb);
+  L.t64 = take(L.field64 * 16);
+  L.r64 = take(L.field64 * 16);
+  L.partial = take(size_t(kReduceBlocks) * nv * sizeof(double));
+  L.scal = take(size_t(12) * nv * sizeof(double));
+  L.total = off;
+  return L;
+}
 
 Layout layout(int op, const int dims[4], int nv, int lodt) {
   const size_t vol = size_t(dims[0]) * dims[1] * dims[2] * dims[3];
@@ -75,11 +117,14 @@ int hipfail(hipError_t e, const char* where) {
 
 }  // namespace
 
-size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype) {
-  return layout(op, dims, nv, inner_dtype).total;
+size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype, bool eo) {
+  return eo ? layout_eo(dims, nv, inner_dtype).total : layout(op, dims, nv, inner_dtype).total;
 }
 
+static int solve_eo(const SolveArgs& a);
+
 int solve(const SolveArgs& a) {
+  if (a.eo) return solve_eo(a);
   const int nv = a.nv;
   const int lodt = a.inner_dtype;
   const Layout L = layout(a.op, a.dims, nv, lodt);
@@ -162,6 +207,120 @@ int solve(const SolveArgs& a) {
       if (!any) break;
     }
     DSL_TRY(launch_axpy_promote(a.x64, lodt, e, scale, vol, comps, nv, st), "x update");
+  }
+  if (a.final_relres)
+    for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];
+  if (a.iters) {
+    a.iters[0] = total_inner;
+    a.iters[1] = outer;
+  }
+  return status;
+}
+
+// Even-odd inner solve (see the header comment).  Schur operator on packed
+// even fields: tmp = H_oe in (odd), out = A in - H_eo tmp / A, both hops with
+// the adjoint flag for M^dag.
+static int solve_eo(const SolveArgs& a) {
+  const int nv = a.nv;
+  const int lodt = a.inner_dtype;
+  const Layout L = layout_eo(a.dims, nv, lodt);
+  unsigned char* ws = static_cast<unsigned char*>(a.workspace);
+  const size_t eb = dtype_bytes(lodt);
+  void* u_even = ws + L.u_lo;
+  void* u_odd = ws + L.u_lo + L.links_lo / 2 * eb;
+  void* u_full = ws + L.u_full;
+  void* rfull = ws + L.rfull;
+  void *re = ws + L.re, *ro = ws + L.ro, *e = ws + L.e, *r = ws + L.r, *p = ws + L.p, *q = ws + L.q, *s = ws + L.s;
+  void *tmp = ws + L.tmp, *eodd = ws + L.eodd;
+  void* t64 = ws + L.t64;
+  void* r64 = ws + L.r64;
+  double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* sc = reinterpret_cast<double*>(ws + L.scal);
+  double *rr = sc, *rr_new = sc + nv, *pq = sc + 2 * nv, *rr0 = sc + 3 * nv, *alpha = sc + 4 * nv,
+         *beta = sc + 5 * nv, *active = sc + 6 * nv, *nb2 = sc + 7 * nv, *nr2 = sc + 8 * nv,
+         *scale = sc + 9 * nv, *inv = sc + 10 * nv;
+  hipStream_t st = a.stream;
+  const Geom g = make_geom(a.dims, nv);
+  const EoGeom eg = make_eo_geom(a.dims, nv);
+  const size_t vol = g.vol, hvol = eg.hvol;
+  const int comps = 12;
+  const double nelem = double(vol) * comps;
+  const double A = 4.0 + a.mass;
+  const size_t spin_site = size_t(12) * nv * eb, link_site = size_t(36) * eb;
+  const size_t half = L.field_lo / 2;
+
+  auto schur = [&](bool adj, const void* in, void* out) -> hipError_t {
+    hipError_t err = launch_wilson_eo_hop(adj, lodt, eg, 1, u_odd, u_even, in, tmp, nullptr, 0.0, 1.0, st);
+    if (err != hipSuccess) return err;
+    return launch_wilson_eo_hop(adj, lodt, eg, 0, u_even, u_odd, tmp, out, in, A, -1.0 / A, st);
+  };
+
+  DSL_TRY(launch_convert(a.U64, DT_C128, u_full, lodt, L.links_lo, st), "link conversion");
+  DSL_TRY(launch_eo_copy(true, eg, 0, u_full, u_even, link_site, st), "pack even links");
+  DSL_TRY(launch_eo_copy(true, eg, 1, u_full, u_odd, link_site, st), "pack odd links");
+  DSL_TRY(launch_norm2(DT_C128, a.b64, vol, comps, nv, partial, nb2, st), "norm of b");
+  std::vector<double> hb(nv), hr(nv), hact(nv), hsc(2 * nv);
+  DSL_TRY(hipMemcpyAsync(hb.data(), nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
+  DSL_TRY(hipStreamSynchronize(st), "sync");
+
+  int total_inner = 0, outer = 0, status = DSLASH_OK;
+  std::vector<double> relres(nv, 0.0);
+  for (;;) {
+    DSL_TRY(launch_apply(OP_WILSON, false, DT_C128, g, a.U64, a.x64, t64, a.mass, st), "outer apply");
+    DSL_TRY(launch_xmy(a.b64, t64, r64, L.field64, st), "outer residual");
+    DSL_TRY(launch_norm2(DT_C128, r64, vol, comps, nv, partial, nr2, st), "outer norm");
+    DSL_TRY(hipMemcpyAsync(hr.data(), nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
+    DSL_TRY(hipStreamSynchronize(st), "sync");
+    bool done = true;
+    for (int v = 0; v < nv; ++v) {
+      relres[v] = hb[v] > 0 ? sqrt(hr[v] / hb[v]) : sqrt(hr[v]);
+      if (relres[v] > a.tol) done = false;
+    }
+    if (done) break;
+    if (outer == a.max_outer) {
+      status = set_error(DSLASH_E_NOCONV, "outer iteration limit reached");
+      break;
+    }
+    ++outer;
+    for (int v = 0; v < nv; ++v) {
+      const bool work = relres[v] > a.tol && hr[v] > 0;
+      const double rms = sqrt(hr[v] / nelem);
+      hsc[v] = work ? rms : 0.0;
+      hsc[nv + v] = work ? 1.0 / rms : 0.0;
+    }
+    DSL_TRY(hipMemcpyAsync(scale, hsc.data(), 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
+    DSL_TRY(launch_scale_to(r64, lodt, rfull, inv, vol, comps, nv, st), "scale residual");
+    DSL_TRY(launch_eo_copy(true, eg, 0, rfull, re, spin_site, st), "pack even residual");
+    DSL_TRY(launch_eo_copy(true, eg, 1, rfull, ro, spin_site, st), "pack odd residual");
+    // Schur right-hand side rhat_e - H_eo rhat_o / A, then CG on M^dag M
+    DSL_TRY(launch_wilson_eo_hop(false, lodt, eg, 0, u_even, u_odd, ro, q, re, 1.0, -1.0 / A, st), "Schur rhs");
+    DSL_TRY(schur(true, q, r), "inner rhs");
+    DSL_TRY(launch_zero(lodt, e, half, st), "zero e");
+    DSL_TRY(launch_convert(r, lodt, p, lodt, half, st), "p = r");
+    DSL_TRY(launch_norm2(lodt, r, hvol, comps, nv, partial, rr, st), "inner norm");
+    DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
+    for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
+    DSL_TRY(hipMemcpyAsync(active, hact.data(), nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    for (int k = 0; k < a.max_inner; ++k) {
+      DSL_TRY(schur(false, p, q), "inner M p");
+      DSL_TRY(launch_norm2(lodt, q, hvol, comps, nv, partial, pq, st), "|Mp|^2");
+      DSL_TRY(launch_cg_scalars(0, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "alpha");
+      DSL_TRY(schur(true, q, s), "inner M^dag q");
+      DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, hvol, comps, nv, partial, rr_new, st), "x/r update");
+      DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
+      DSL_TRY(launch_cg_update_p(lodt, p, r, beta, hvol, comps, nv, st), "p update");
+      ++total_inner;
+      DSL_TRY(hipMemcpyAsync(hact.data(), active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
+      DSL_TRY(hipStreamSynchronize(st), "sync");
+      bool any = false;
+      for (int v = 0; v < nv; ++v) any = any || hact[v] != 0.0;
+      if (!any) break;
+    }
+    // odd half e_o = (rhat_o - H_oe e_e) / A, then the full correction
+    DSL_TRY(launch_wilson_eo_hop(false, lodt, eg, 1, u_odd, u_even, e, eodd, ro, 1.0 / A, -1.0 / A, st), "odd half");
+    DSL_TRY(launch_eo_copy(false, eg, 0, e, rfull, spin_site, st), "unpack even");
+    DSL_TRY(launch_eo_copy(false, eg, 1, eodd, rfull, spin_site, st), "unpack odd");
+    DSL_TRY(launch_axpy_promote(a.x64, lodt, rfull, scale, vol, comps, nv, st), "x update");
   }
   if (a.final_relres)
     for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];

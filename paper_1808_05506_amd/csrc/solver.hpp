@@ -21,9 +21,10 @@ struct SolveArgs {
   double* final_relres;
   int* iters;
   hipStream_t stream;
+  bool eo = false;  // inner solve on the even-site Schur complement (WILSON only)
 };
 
-size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype);
+size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype, bool eo = false);
 int solve(const SolveArgs& a);
 int set_error(int code, const char* msg);
 

@@ -50,10 +50,18 @@ def _load():
     lib.dslash_solve_workspace_bytes.restype = sz
     lib.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                  ctypes.POINTER(ctypes.c_double), ip, vp]
+    lib.dslash_eo_pack.argtypes = [vp, vp, vp, ip, sz, vp]
+    lib.dslash_eo_unpack.argtypes = [vp, vp, vp, ip, sz, vp]
+    lib.dslash_eo_hop.argtypes = [vp, vp, vp, vp, ip, i, i, i, i, i, vp]
+    lib.dslash_solve_eo_workspace_bytes.argtypes = [ip, i, i, i]
+    lib.dslash_solve_eo_workspace_bytes.restype = sz
+    lib.dslash_solve_eo.argtypes = [vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                                    ctypes.POINTER(ctypes.c_double), ip, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
-                 "dslash_convert", "dslash_solve", "dslash_version"):
+                 "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
+                 "dslash_eo_hop", "dslash_solve_eo"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -215,32 +223,97 @@ def convert(x: torch.Tensor, dtype: str) -> torch.Tensor:
 
 
 def solve(op, U: torch.Tensor, b: torch.Tensor, mass: float, inner: str = "bf16", tol: float = 1e-10,
-          inner_tol: float = 0.05, max_outer: int = 100, max_inner: int = 20000, x0: torch.Tensor | None = None):
+          inner_tol: float = 0.05, max_outer: int = 100, max_inner: int = 20000, x0: torch.Tensor | None = None,
+          eo: bool = False):
     """Solve D x = b by FP64 defect correction around a low-precision CG on D^dag D.
 
-    U, b: complex128.  Returns (x, info) with info = {relres: per-column FP64
-    ||b - D x||/||b||, inner_iters, outer_iters, status}.  Raises on argument
-    errors; non-convergence is reported in info['status'] (5).
+    U, b: complex128.  eo=True (WILSON only): the inner solve runs on the
+    even-site Schur complement (dslash_solve_eo).  Returns (x, info) with
+    info = {relres: per-column FP64 ||b - D x||/||b||, inner_iters,
+    outer_iters, status}.  Raises on argument errors; non-convergence is
+    reported in info['status'] (5).
     """
     op = op_code(op)
     lat, nv = _validate(op, U, b)
     if U.dtype != torch.complex128:
         raise ValueError("solve takes complex128 links and right-hand sides")
+    if eo and op != WILSON:
+        raise ValueError("the even-odd solve is built for WILSON only")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     code = _NAMES[inner]
     dims = _dims_c(lat)
-    nbytes = _lib.dslash_solve_workspace_bytes(op, dims, 3, nv, code)
+    if eo:
+        nbytes = _lib.dslash_solve_eo_workspace_bytes(dims, 3, nv, code)
+    else:
+        nbytes = _lib.dslash_solve_workspace_bytes(op, dims, 3, nv, code)
     if nbytes == 0:
-        raise ValueError(f"unsupported solver configuration (inner={inner})")
+        raise ValueError(f"unsupported solver configuration (inner={inner}, eo={eo})")
     ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     relres = (ctypes.c_double * nv)()
     iters = (ctypes.c_int * 2)()
-    rc = _lib.dslash_solve(op, _ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
-                           float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
-                           _stream(b))
+    if eo:
+        rc = _lib.dslash_solve_eo(_ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
+                                  float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
+                                  _stream(b))
+    else:
+        rc = _lib.dslash_solve(op, _ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
+                               float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
+                               _stream(b))
     if rc not in (0, 5):
-        raise DslashError(rc, "dslash_solve")
+        raise DslashError(rc, "dslash_solve_eo" if eo else "dslash_solve")
     return x, {"relres": list(relres), "inner_iters": iters[0], "outer_iters": iters[1], "status": rc}
+
+
+def _site_bytes(t: torch.Tensor) -> int:
+    per = 1
+    for n in t.shape[4:]:
+        per *= n
+    return per * t.element_size()
+
+
+def eo_pack(field: torch.Tensor):
+    """(even, odd) packed halves [Nt][Nz][Ny][Nx/2][...] of a full-lattice field."""
+    _require(field, "field")
+    nt, nz, ny, nx = field.shape[:4]
+    shape = (nt, nz, ny, nx // 2) + tuple(field.shape[4:])
+    even = torch.empty(shape, dtype=field.dtype, device=field.device)
+    odd = torch.empty_like(even)
+    _check(_lib.dslash_eo_pack(_ptr(field), _ptr(even), _ptr(odd), _dims_c(field.shape), _site_bytes(field),
+                               _stream(field)), "dslash_eo_pack")
+    return even, odd
+
+
+def eo_unpack(even: torch.Tensor, odd: torch.Tensor) -> torch.Tensor:
+    """Full-lattice field from its packed even and odd halves."""
+    _require(even, "even")
+    _require(odd, "odd")
+    if even.shape != odd.shape or even.dtype != odd.dtype:
+        raise ValueError("even and odd halves must match in shape and dtype")
+    nt, nz, ny, nh = even.shape[:4]
+    full = torch.empty((nt, nz, ny, 2 * nh) + tuple(even.shape[4:]), dtype=even.dtype, device=even.device)
+    _check(_lib.dslash_eo_unpack(_ptr(even), _ptr(odd), _ptr(full), _dims_c(full.shape), _site_bytes(even),
+                                 _stream(even)), "dslash_eo_unpack")
+    return full
+
+
+def eo_hop(U_even: torch.Tensor, U_odd: torch.Tensor, psi: torch.Tensor, parity_out: int,
+           adjoint: bool = False) -> torch.Tensor:
+    """H psi on the packed sites of parity parity_out; psi packed on the other parity."""
+    for t, n in ((U_even, "U_even"), (U_odd, "U_odd"), (psi, "psi")):
+        _require(t, n)
+    cs = _core_shape(psi)
+    if len(cs) != 7 or cs[4:6] != (4, 3):
+        raise ValueError(f"psi must be packed [Nt,Nz,Ny,Nx/2,4,3,Nv], got {cs}")
+    if _core_shape(U_even) != cs[:4] + (4, 3, 3) or U_odd.shape != U_even.shape:
+        raise ValueError("U_even/U_odd must be packed [Nt,Nz,Ny,Nx/2,4,3,3] matching psi")
+    if _dtype_code(U_even) != _dtype_code(psi) or _dtype_code(U_odd) != _dtype_code(psi):
+        raise ValueError("links and psi must share the storage dtype")
+    nt, nz, ny, nh = cs[:4]
+    out = torch.empty_like(psi)
+    dims = (ctypes.c_int * 4)(2 * nh, ny, nz, nt)
+    _check(_lib.dslash_eo_hop(_ptr(U_even), _ptr(U_odd), _ptr(psi), _ptr(out), dims, 3, cs[6], int(parity_out),
+                              int(bool(adjoint)), _dtype_code(psi), _stream(psi)), "dslash_eo_hop")
+    return out
 
 
 class _DslashFn(torch.autograd.Function):

@@ -28,6 +28,13 @@ def lib():
     l.dslash_solve_workspace_bytes.restype = sz
     l.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                ctypes.POINTER(ctypes.c_double), ip, vp]
+    l.dslash_eo_pack.argtypes = [vp, vp, vp, ip, sz, vp]
+    l.dslash_eo_unpack.argtypes = [vp, vp, vp, ip, sz, vp]
+    l.dslash_eo_hop.argtypes = [vp, vp, vp, vp, ip, i, i, i, i, i, vp]
+    l.dslash_solve_eo_workspace_bytes.argtypes = [ip, i, i, i]
+    l.dslash_solve_eo_workspace_bytes.restype = sz
+    l.dslash_solve_eo.argtypes = [vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                                  ctypes.POINTER(ctypes.c_double), ip, vp]
     return l
 
 
@@ -38,10 +45,10 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 10
+    assert len(declared) == 15
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 100
+    assert lib.dslash_version() == 101
 
 
 def test_status_strings(lib):
@@ -116,3 +123,24 @@ def test_binding_rejects_cpu_tensors():
         D.apply("wilson", u, p, 0.1)
     with pytest.raises(ValueError):
         D.op_code("clover")
+
+
+def test_even_odd_validation(lib):
+    even, odd = _dims(4, 4, 4, 4), _dims(4, 3, 4, 4)
+    D = 0x20000000
+    assert lib.dslash_eo_pack(A, B, C, odd, 96, None) == 1                   # odd extent
+    assert lib.dslash_eo_pack(A, B, C, even, 0, None) == 1                   # no bytes
+    assert lib.dslash_eo_pack(A, A, C, even, 96, None) == 3                  # full overlaps even
+    assert lib.dslash_eo_unpack(None, B, C, even, 96, None) == 1             # NULL
+    assert lib.dslash_eo_hop(A, B, C, D, even, 3, 2, 2, 0, 0, None) == 1     # parity 2
+    assert lib.dslash_eo_hop(A, B, C, C, even, 3, 2, 0, 0, 0, None) == 3     # in == out
+    assert lib.dslash_eo_hop(A, B, C, D, odd, 3, 2, 0, 0, 0, None) == 1      # odd extent
+    assert lib.dslash_eo_hop(A, B, C, D, even, 2, 2, 0, 0, 0, None) == 2     # Nc != 3
+    assert lib.dslash_solve_eo_workspace_bytes(odd, 3, 2, 2) == 0
+    assert lib.dslash_solve_eo_workspace_bytes(even, 3, 2, 1) == 0          # FP64 inner
+    assert lib.dslash_solve_eo_workspace_bytes(even, 3, 2, 2) > 0
+    rel = (ctypes.c_double * 2)()
+    it = (ctypes.c_int * 2)()
+    assert lib.dslash_solve_eo(A, B, C, odd, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1
+    assert lib.dslash_solve_eo(A, B, C, even, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 16, rel, it, None) == 6
+    assert lib.dslash_solve_eo(A, B, C, even, 3, 2, -4.0, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1

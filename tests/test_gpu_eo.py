@@ -1,0 +1,76 @@
+"""GPU parity of the even-odd form of D_W (packing, the parity-restricted hop,
+the Schur-complement solve) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import evenodd, solver, wilson
+from tests.gpu_util import compare, down, rounded, say, up
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1808_05506_amd import dslash as D  # noqa: E402
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16"])
+@pytest.mark.parametrize("dims,nv", [((4, 2, 2, 4), 3), ((6, 4, 2, 2), 2), ((16, 4, 2, 2), 12)])
+def test_pack_unpack_bit_exact(dt, dims, nv):
+    f = rounded(synthetic.wilson_spinor(dims, nv, 61), dt)
+    F = up(f, dt)
+    E, O = D.eo_pack(F)
+    assert np.array_equal(down(E), evenodd.pack(f, 0))
+    assert np.array_equal(down(O), evenodd.pack(f, 1))
+    assert torch.equal(D.eo_unpack(E, O), F)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128", "bf16", "f16"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("dims,nv", [((4, 2, 2, 4), 3), ((6, 4, 2, 2), 1), ((8, 2, 4, 2), 12)])
+def test_eo_hop_matches_oracle(dt, adj, parity, dims, nv):
+    say(f"case eo hop {dims} nv={nv} {dt} parity={parity} adj={adj}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 62), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 63), dt)
+    pin = evenodd.pack(p, 1 - parity)
+    ue, uo = evenodd.pack(u, 0), evenodd.pack(u, 1)
+    out = D.eo_hop(up(ue, dt), up(uo, dt), up(pin, dt), parity, adjoint=adj)
+    compare(down(out), evenodd.hop_eo(u, pin, parity, adj), dt, "eo hop")
+
+
+def test_eo_hop_split_reproduces_full_operator():
+    # (4 + m0) psi + (H_eo psi_o, H_oe psi_e) equals the full D_W of the library
+    dims, nv, m0, dt = (8, 4, 2, 4), 12, 0.1, "c64"
+    u = rounded(synthetic.gauge_links(dims, "smooth", 64), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 65), dt)
+    U, P = up(u, dt), up(p, dt)
+    Ue, Uo = D.eo_pack(U)
+    Pe, Po = D.eo_pack(P)
+    he = D.eo_hop(Ue, Uo, Po, 0)
+    ho = D.eo_hop(Ue, Uo, Pe, 1)
+    split = (4 + m0) * P + D.eo_unpack(he, ho)
+    full = D.apply("wilson", U, P, m0)
+    compare(down(split), down(full).astype(np.complex128), dt, "eo split vs full D_W")
+
+
+@pytest.mark.parametrize("inner,itol", [("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)])
+@pytest.mark.parametrize("dims,nv", [((4, 4, 4, 4), 3), ((12, 4, 2, 4), 12)])
+def test_solve_eo(inner, itol, dims, nv):
+    m0 = 0.05
+    say(f"case solve eo {dims} nv={nv} inner={inner}")
+    u = synthetic.gauge_links(dims, "smooth", 66)
+    b = synthetic.wilson_spinor(dims, nv, 67)
+    x, info = D.solve("wilson", up(u, "c128"), up(b, "c128"), m0, inner=inner, tol=1e-10, inner_tol=itol, eo=True)
+    say(f"info {info}")
+    assert info["status"] == 0
+    res = solver.relative_residual(lambda v: wilson.apply(u, v, m0), b, down(x))
+    say(f"oracle residuals {res}")
+    assert np.all(res <= 1e-10)
+    assert np.allclose(info["relres"], res, rtol=1e-3, atol=1e-13)
+    # the Schur form needs fewer inner iterations than CG on the full normal equations
+    _, full = D.solve("wilson", up(u, "c128"), up(b, "c128"), m0, inner=inner, tol=1e-10, inner_tol=itol)
+    say(f"inner iterations: eo {info['inner_iters']}, full {full['inner_iters']}")
+    assert info["inner_iters"] < full["inner_iters"]
