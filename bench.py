@@ -230,6 +230,22 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     for k in ("bf16", "f16"):
         solve[k]["speedup_vs_fp32_inner"] = base / solve[k]["seconds"]
     rows["solve_wilson_32^3x64_nv12"] = solve
+    # the same solves with the inner CG on the even-site Schur complement
+    solve_eo = {}
+    for inner, itol in (("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = D.solve("wilson", U, B, 0.05, inner=inner, tol=1e-10, inner_tol=itol, eo=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        solve_eo[inner] = {"seconds": t, "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
+                           "max_relres": max(info["relres"]), "status": info["status"], "inner_tol": itol,
+                           "speedup_vs_full_lattice": solve[inner]["seconds"] / t,
+                           "speedup_vs_fp32_inner_full_lattice": base / t}
+        log(f"solve eo inner={inner}: {t:.2f} s, {info['inner_iters']} inner / {info['outer_iters']} outer, "
+            f"max relres {max(info['relres']):.2e}")
+        del x
+    rows["solve_wilson_eo_32^3x64_nv12"] = solve_eo
     return rows
 
 
