@@ -610,6 +610,178 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, boo
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- even-odd hop
+// out = c_add add + c_hop H in on the packed sites of parity p (even-odd form
+// of D_W, see eo.hip), staged like wilson_rows_kernel on the packed geometry
+// (Nx/2 sites per row): the y, z, t neighbours of packed site i sit at packed
+// index i of the neighbour rows of `in`; the x neighbours are in the same row
+// of `in` at i + r (x + 1) and i - 1 + r (x - 1), r = (p + y + z + t) mod 2.
+// Forward links come from Uo (parity p), backward ones from Ui (parity 1 - p).
+template <int DEPTH, bool ADJ, int NV, class S, class T>
+__global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
+    wilson_eo_rows_kernel(Geom g, RowTraversal tr, int xcd, int p, const typename S::word* __restrict__ Uo,
+                          const typename S::word* __restrict__ Ui, const typename S::word* __restrict__ in,
+                          typename S::word* __restrict__ out, const typename S::word* __restrict__ add, T c_add,
+                          T c_hop) {
+  using W = typename S::word;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
+  extern __shared__ uint4 smem_eo[];
+  const int R = int(tr.sb);
+  W* buf = reinterpret_cast<W*>(smem_eo);
+  W* lown = buf + (R + 2) * SSW;  // [R + 1][36], index x - x0 + 1
+  W* lnb = lown + (R + 1) * 36;   // [R][9]
+  W* lxb = lnb + R * 9;           // [R][9]: V_x(x - 1) from Ui
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const RowChunk c = row_chunk(g, tr, L);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v, nth = R * NV;
+  const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+  const int r = (p + c.y + c.z + c.t) & 1;
+
+  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+#define DSL_ISSUE(K)                                                                   \
+  do {                                                                                 \
+    if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, Ui, in, xl, v, tid, r0);       \
+    if constexpr (K == 1) row_issue<1, -1, NV, S>(g, c, Ui, in, xl, v, tid, r1);       \
+    if constexpr (K == 2) row_issue<2, +1, NV, S>(g, c, Ui, in, xl, v, tid, r2);       \
+    if constexpr (K == 3) row_issue<2, -1, NV, S>(g, c, Ui, in, xl, v, tid, r3);       \
+    if constexpr (K == 4) row_issue<3, +1, NV, S>(g, c, Ui, in, xl, v, tid, r4);       \
+    if constexpr (K == 5) row_issue<3, -1, NV, S>(g, c, Ui, in, xl, v, tid, r5);       \
+    if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);             \
+  } while (0)
+  DSL_ISSUE(0);
+  if constexpr (DEPTH > 1) DSL_ISSUE(1);
+  if constexpr (DEPTH > 2) DSL_ISSUE(2);
+  if constexpr (DEPTH > 3) DSL_ISSUE(3);
+  if constexpr (DEPTH > 4) DSL_ISSUE(4);
+  if constexpr (DEPTH > 5) DSL_ISSUE(5);
+  if constexpr (DEPTH > 6) DSL_ISSUE(6);
+  {
+    // links of the chunk's own sites (forward hops) and V_x(x - 1) of the x - 1
+    // neighbours, which live in the other parity's row
+    constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16;
+    copy_pieces<3>(lown + 36, Uo + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
+    const int w = tid < c.n * 9 ? tid : c.n * 9 - 1;
+    const int k = w / 9, e = w - k * 9;
+    lxb[w] = Ui[size_t(c.row_base + wrap_x(g, c.x0 + k - 1 + r)) * 36 + e];
+  }
+
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
+
+  W* const row = buf + SSW;
+#define DSL_ROW_STEP(K, MU, SGN, CUR)                                         \
+  row_commit<SGN, NV, S>(c, CUR, row, lnb, xl, v, tid);                       \
+  __syncthreads();                                                            \
+  if constexpr (K + DEPTH < 7) DSL_ISSUE(K + DEPTH);                          \
+  row_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);            \
+  hold_acc<T>(acc);                                                           \
+  __syncthreads();
+  DSL_ROW_STEP(0, 1, +1, r0)
+  DSL_ROW_STEP(1, 1, -1, r1)
+  DSL_ROW_STEP(2, 2, +1, r2)
+  DSL_ROW_STEP(3, 2, -1, r3)
+  DSL_ROW_STEP(4, 3, +1, r4)
+  DSL_ROW_STEP(5, 3, -1, r5)
+#undef DSL_ROW_STEP
+#undef DSL_ISSUE
+
+  own_commit<NV, S>(c, r6, buf, xl, v, tid);
+  __syncthreads();
+  cpx<T> res[4][3];
+  {
+    constexpr int CF = ADJ ? +1 : -1, CB = -CF;
+    // x + 1 at packed i + r (buffer index xl + 1 + r), x - 1 at i - 1 + r
+    lds_hop<0, CF, false, NV, S, T>(buf + (xl + 1 + r) * SSW, lown + (xl + 1) * 36, v, acc);
+    lds_hop<0, CB, true, NV, S, T>(buf + (xl + r) * SSW, lxb + xl * 9, v, acc);
+    const T ch = T(-0.5) * c_hop;
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const W* a = add + size_t(c.row_base + c.x0 + xc) * SW + v;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        res[sp][cc].r = ch * acc[sp][cc].r;
+        res[sp][cc].i = ch * acc[sp][cc].i;
+        if (add) {
+          const cpx<T> q = S::template load<T>(a + (sp * 3 + cc) * NV);
+          res[sp][cc].r = fma(c_add, q.r, res[sp][cc].r);
+          res[sp][cc].i = fma(c_add, q.i, res[sp][cc].i);
+        }
+      }
+  }
+  __syncthreads();
+  {
+    W* o = buf + xl * SSW;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) S::template store<T>(o + (sp * 3 + cc) * NV + v, res[sp][cc]);
+  }
+  __syncthreads();
+  {
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
+    u32x4 o[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) o[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(o[j], &dst[j * NV + v]);
+  }
+}
+
+template <int NV, class S, class T>
+static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, int parity, const void* Uo,
+                                   const void* Ui, const void* in, void* out, const void* add, double c_add,
+                                   double c_hop, hipStream_t st) {
+  using W = typename S::word;
+  const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+  const size_t lds = (rows_lds_words<NV, S>(R) + size_t(R) * 9) * sizeof(W);
+  if (adj)
+    hipLaunchKernelGGL((wilson_eo_rows_kernel<3, true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), parity,
+                       (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop));
+  else
+    hipLaunchKernelGGL((wilson_eo_rows_kernel<3, false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), parity,
+                       (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop));
+  return hipGetLastError();
+}
+
+// Row-staged even-odd hop for N_v = 12 (C64, BF16, F16 storage) on rows of
+// at least 11 packed sites; hipErrorNotSupported otherwise (the caller then
+// uses the direct kernel).  DSLASH_ROWS=0 disables it.
+hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
+                                 const void* in, void* out, const void* add, double c_add, double c_hop,
+                                 hipStream_t st) {
+  if (const char* env = getenv("DSLASH_ROWS"))
+    if (atoi(env) == 0) return hipErrorNotSupported;
+  if (e.nv != 12) return hipErrorNotSupported;
+  const int pdims[4] = {e.nh, e.n[1], e.n[2], e.n[3]};
+  const Geom g = make_geom(pdims, e.nv);
+  int R = row_sites_default(g.n[0], g.nv);
+  if (const char* env = getenv("DSLASH_ROW_SITES")) R = atoi(env);
+  if (R > g.n[0]) R = g.n[0];
+  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  const int word_bytes = int(dtype_bytes(dtype));
+  if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
+  int bt = 2;
+  if (const char* env = getenv("DSLASH_TBAND")) bt = atoi(env);
+  bool xcd = true;
+  if (const char* env = getenv("DSLASH_XCD")) xcd = atoi(env) != 0;
+  switch (dtype) {
+    case DT_C64: return wilson_eo_rows_t<12, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
+    case DT_BF16: return wilson_eo_rows_t<12, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
+    case DT_F16: return wilson_eo_rows_t<12, F16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
+  }
+  return hipErrorNotSupported;
+}
+
 template <int DEPTH, int NV, class S, class T>
 static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* U, const void* in,
                                 void* out, double mass, hipStream_t st) {

@@ -55,6 +55,9 @@ hipError_t launch_eo_copy(bool to_packed, const EoGeom& e, int parity, const voi
 hipError_t launch_wilson_eo_hop(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                 const void* in, void* out, const void* add, double c_add, double c_hop,
                                 hipStream_t st);
+hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
+                                 const void* in, void* out, const void* add, double c_add, double c_hop,
+                                 hipStream_t st);
 
 // ---- solver BLAS-1 (fields of `comps` complex numbers per site times nv columns,
 //      column index fastest; per-column scalars are device arrays of nv doubles)

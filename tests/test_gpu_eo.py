@@ -41,6 +41,36 @@ def test_eo_hop_matches_oracle(dt, adj, parity, dims, nv):
     compare(down(out), evenodd.hop_eo(u, pin, parity, adj), dt, "eo hop")
 
 
+# Packed rows of 12, 27 and 32 sites at N_v = 12 take the row-staged hop
+# kernel (one chunk; two chunks of 14 and 13; two chunks of 16).
+@pytest.mark.parametrize("dt", ["c64", "bf16", "f16"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("dims", [(24, 2, 2, 2), (54, 2, 4, 2), (64, 2, 2, 4)])
+def test_eo_hop_row_staged_matches_oracle(dt, adj, parity, dims):
+    say(f"case eo hop rows {dims} nv=12 {dt} parity={parity} adj={adj}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 68), dt)
+    p = rounded(synthetic.wilson_spinor(dims, 12, 69), dt)
+    pin = evenodd.pack(p, 1 - parity)
+    ue, uo = evenodd.pack(u, 0), evenodd.pack(u, 1)
+    out = D.eo_hop(up(ue, dt), up(uo, dt), up(pin, dt), parity, adjoint=adj)
+    compare(down(out), evenodd.hop_eo(u, pin, parity, adj), dt, "eo hop rows")
+
+
+def test_eo_hop_row_staged_equals_direct_kernel(monkeypatch):
+    dims, dt = (54, 2, 4, 2), "c64"
+    say(f"case eo hop rows vs direct {dims}")
+    U = up(synthetic.gauge_links(dims, "haar", 70), dt)
+    P = up(synthetic.wilson_spinor(dims, 12, 71), dt)
+    Ue, Uo = D.eo_pack(U)
+    Pe, _ = D.eo_pack(P)
+    rows = D.eo_hop(Ue, Uo, Pe, 1)
+    monkeypatch.setenv("DSLASH_ROWS", "0")
+    direct = D.eo_hop(Ue, Uo, Pe, 1)
+    torch.cuda.synchronize()
+    compare(down(rows), down(direct).astype(np.complex128), dt, "eo hop rows vs direct")
+
+
 def test_eo_hop_split_reproduces_full_operator():
     # (4 + m0) psi + (H_eo psi_o, H_oe psi_e) equals the full D_W of the library
     dims, nv, m0, dt = (8, 4, 2, 4), 12, 0.1, "c64"
@@ -57,7 +87,7 @@ def test_eo_hop_split_reproduces_full_operator():
 
 
 @pytest.mark.parametrize("inner,itol", [("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)])
-@pytest.mark.parametrize("dims,nv", [((4, 4, 4, 4), 3), ((12, 4, 2, 4), 12)])
+@pytest.mark.parametrize("dims,nv", [((4, 4, 4, 4), 3), ((12, 4, 2, 4), 12), ((24, 4, 2, 4), 12)])
 def test_solve_eo(inner, itol, dims, nv):
     m0 = 0.05
     say(f"case solve eo {dims} nv={nv} inner={inner}")
