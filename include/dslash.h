@@ -104,6 +104,38 @@ int dslash_apply_adjoint(int op, const void* U, const void* in, void* out, const
                          int Nv, double mass, int dtype, void* stream);
 
 /*
+ * Clover term (eqs. def_wils and def_bril, the term -(c_SW/2) sum_{mu<nu}
+ * sigma_{mu nu} F_{mu nu}(x) delta_{x,y}; the paper benchmarks c_SW = 0 and
+ * defines neither sigma nor F).  Built as
+ *   sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu]   (chiral basis, as for D_W),
+ *   F_{mu nu}(x)  = (Q_{mu nu}(x) - Q_{mu nu}(x)^dag) / (8 i),
+ * Q_{mu nu}(x) = the four plaquettes of the (mu, nu) plane starting and
+ * ending at x, each run x -> x+a -> x+a+b -> x+b -> x for (a, b) = (mu, nu),
+ * (nu, -mu), (-mu, -nu), (-nu, mu); no trace subtraction.  The term is
+ * Hermitian and block diagonal: block b acts on spins 2b, 2b+1 with row index
+ * 3 s' + c.
+ *
+ * C (output): [Nt][Nz][Ny][Nx][2][18] storage words; per block the real
+ * diagonal pairwise as (H_00, H_11), (H_22, H_33), (H_44, H_55) in (re, im),
+ * then the upper triangle H_ij, i < j, row by row.  Same storage dtype as V
+ * (36 words per site, the size of the links).  V: [..][4][3][3], read only.
+ * V and C must not overlap (E_ALIAS).  Asynchronous on `stream`.
+ */
+int dslash_clover_field(const void* V, void* C, const int dims[4], int Nc, double c_sw, int dtype,
+                        void* stream);
+
+/*
+ * out = (D + C) in, or (D^dag + C) in if adjoint != 0 (C is Hermitian), for
+ * op = WILSON (U = V) or BRILLOUIN (U = the stored W), with C from
+ * dslash_clover_field (same dtype).  Other ops -> E_ARG; C == NULL -> E_ARG;
+ * otherwise the arguments and errors of dslash_apply, and out must not
+ * overlap C (E_ALIAS).  N_v = 12 with FP32 arithmetic runs the row-staged
+ * kernels with the term fused into their last step.
+ */
+int dslash_apply_clover(int op, const void* U, const void* C, const void* in, void* out, const int dims[4],
+                        int Nc, int Nv, double mass, int adjoint, int dtype, void* stream);
+
+/*
  * Backward pass of out = D[U] in for a real loss L with grad_out = dL/dout
  * (PyTorch convention for complex tensors: dL/dRe + i dL/dIm).
  *   grad_in = D^dag grad_out                                   (nullable)

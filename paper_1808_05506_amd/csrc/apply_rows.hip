@@ -11,30 +11,6 @@
 
 namespace dsl {
 
-// Copy `pieces` 16-byte pieces (both pointers 16-byte aligned) with the
-// workgroup's threads; consecutive threads move consecutive pieces and each
-// thread moves at most K.  Loads and stores are both unconditional: indices
-// past the end are clamped to the last piece, so a surplus lane rewrites that
-// piece with the value it already holds.  Predicated loads would be sunk by
-// the compiler into their store's branch and waited for one at a time.
-template <int K>
-__device__ __forceinline__ void copy_pieces(void* __restrict__ dst, const void* __restrict__ src, int pieces,
-                                            int tid, int nth) {
-  const u32x4* s = static_cast<const u32x4*>(src);
-  u32x4* d = static_cast<u32x4*>(dst);
-  u32x4 r[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int i = tid + j * nth;
-    r[j] = s[i < pieces ? i : pieces - 1];
-  }
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int i = tid + j * nth;
-    d[i < pieces ? i : pieces - 1] = r[j];
-  }
-}
-
 // LDS layout, in storage words (one complex number each):
 //   buf  [(R + 2) * 12 NV]  one staged row at index x - x0 + 1: a neighbour row
 //                           fills 1 .. n, the chunk's own row 0 .. n + 1 (with
@@ -200,10 +176,13 @@ __device__ __forceinline__ void row_compute(const typename S::word* nbr, const t
 // registers (about 28 VGPRs per FP32 row) and runs fewer waves per SIMD.
 template <int DEPTH> struct RowsWaves { static constexpr int value = DEPTH <= 2 ? 4 : (DEPTH <= 4 ? 3 : 2); };
 
-template <int DEPTH, bool ADJ, int NV, class S, class T>
+// CLOV: adds the site-local clover term C(x) in(x) (packed, 36 words per
+// site, staged in LDS after lnb).
+template <int DEPTH, bool ADJ, bool CLOV, int NV, class S, class T>
 __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
     wilson_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ U,
-                       const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
+                       const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                       const typename S::word* __restrict__ C, T diag) {
   using W = typename S::word;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
@@ -212,6 +191,7 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   W* buf = reinterpret_cast<W*>(smem_rows);
   W* lown = buf + (R + 2) * SSW;
   W* lnb = lown + (R + 1) * 36;
+  W* lcl = lnb + ((R * 9 + 3) & ~3);  // [R][36] clover words of the chunk's sites (CLOV), 16-byte aligned
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const RowChunk c = row_chunk(g, tr, L);
@@ -246,6 +226,7 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16;
   copy_pieces<3>(lown + 36, U + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
   copy_pieces<1>(lown, U + size_t(c.row_base + xm) * 36, LINK_PIECES, tid, nth);
+  if constexpr (CLOV) copy_pieces<3>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
 
   cpx<T> acc[4][3];
 #pragma unroll
@@ -282,14 +263,27 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
     lds_hop<0, CF, false, NV, S, T>(buf + (xl + 2) * SSW, lown + (xl + 1) * 36, v, acc);
     lds_hop<0, CB, true, NV, S, T>(buf + xl * SSW, lown + xl * 36, v, acc);
     const W* self = buf + (xl + 1) * SSW;
+    if constexpr (CLOV) {
+      cpx<T> p[4][3];
+      lds_spinor<S, T, NV>(self, v, p);
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+      for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        cpx<T> p = S::template load<T>(self + (sp * 3 + cc) * NV + v);
-        res[sp][cc].r = fma(diag, p.r, T(-0.5) * acc[sp][cc].r);
-        res[sp][cc].i = fma(diag, p.i, T(-0.5) * acc[sp][cc].i);
-      }
+        for (int cc = 0; cc < 3; ++cc) {
+          res[sp][cc].r = fma(diag, p[sp][cc].r, T(-0.5) * acc[sp][cc].r);
+          res[sp][cc].i = fma(diag, p[sp][cc].i, T(-0.5) * acc[sp][cc].i);
+        }
+      clover_madd<S, T>(lcl + xl * 36, p, res);
+    } else {
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          cpx<T> p = S::template load<T>(self + (sp * 3 + cc) * NV + v);
+          res[sp][cc].r = fma(diag, p.r, T(-0.5) * acc[sp][cc].r);
+          res[sp][cc].i = fma(diag, p.i, T(-0.5) * acc[sp][cc].i);
+        }
+    }
   }
   __syncthreads();
   {
@@ -784,20 +778,23 @@ hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parit
 
 template <int DEPTH, int NV, class S, class T>
 static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* U, const void* in,
-                                void* out, double mass, hipStream_t st) {
+                                void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
-  size_t lds = rows_lds_words<NV, S>(R) * sizeof(W);
+  size_t lds = (rows_lds_words<NV, S>(R) + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   // DSLASH_ROW_LDS_EXTRA (bytes) lowers the workgroups per CU (tuning).
   if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
-  if (adj)
-    hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
-                       (const W*)in, (W*)out, diag);
-  else
-    hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U,
-                       (const W*)in, (W*)out, diag);
+#define DSL_RK(A, CL)                                                                                      \
+  hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, A, CL, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U, \
+                     (const W*)in, (W*)out, (const W*)C, diag)
+  if (C) {
+    if (adj) DSL_RK(true, true); else DSL_RK(false, true);
+  } else {
+    if (adj) DSL_RK(true, false); else DSL_RK(false, false);
+  }
+#undef DSL_RK
   return hipGetLastError();
 }
 
@@ -805,7 +802,7 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
 // Returns hipErrorNotSupported when the configuration is not covered (the
 // caller then uses the direct-load kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st) {
+                              double mass, hipStream_t st, const void* clover) {
   if (const char* e = getenv("DSLASH_ROWS"))
     if (atoi(e) == 0) return hipErrorNotSupported;
   if (g.nv != 12) return hipErrorNotSupported;
@@ -827,7 +824,8 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   int tsteps = 8;
   if (const char* e = getenv("DSLASH_TSTEPS")) tsteps = atoi(e);
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
-  if (tsteps > 0) {
+  // the clover term is fused into the one-row-per-workgroup kernel only
+  if (tsteps > 0 && !clover) {
     const int depth = depth_env ? atoi(depth_env) : 2;
 #define DSL_MT(D)                                                                                       \
   switch (dtype) {                                                                                      \
@@ -842,9 +840,9 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   const int depth = depth_env ? atoi(depth_env) : 3;
 #define DSL_RT(D)                                                                               \
   switch (dtype) {                                                                              \
-    case DT_C64: return wilson_rows_t<D, 12, C64, float>(adj, g, R, bt, xcd, U, in, out, mass, st);   \
-    case DT_BF16: return wilson_rows_t<D, 12, BF16, float>(adj, g, R, bt, xcd, U, in, out, mass, st); \
-    case DT_F16: return wilson_rows_t<D, 12, F16, float>(adj, g, R, bt, xcd, U, in, out, mass, st);   \
+    case DT_C64: return wilson_rows_t<D, 12, C64, float>(adj, g, R, bt, xcd, U, in, out, clover, mass, st);   \
+    case DT_BF16: return wilson_rows_t<D, 12, BF16, float>(adj, g, R, bt, xcd, U, in, out, clover, mass, st); \
+    case DT_F16: return wilson_rows_t<D, 12, F16, float>(adj, g, R, bt, xcd, U, in, out, clover, mass, st);   \
   }
   if (depth <= 2) { DSL_RT(2) } else if (depth <= 3) { DSL_RT(3) } else { DSL_RT(7) }
 #undef DSL_RT

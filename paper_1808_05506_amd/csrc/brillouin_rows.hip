@@ -189,10 +189,12 @@ __device__ __forceinline__ void bri_hop(const typename S::word* site, const type
     for (int cc = 0; cc < 3; ++cc) hold(acc[q][cc]);
 }
 
-// The three hops of staged row r (and the diagonal term for the own row).
-template <bool ADJ, int NV, class S, class T>
+// The three hops of staged row r (and the diagonal term, with the clover term
+// if CLOV, for the own row).
+template <bool ADJ, bool CLOV, int NV, class S, class T>
 __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* buf, const typename S::word* wbuf,
-                                                int R, int xl, int v, T diag, cpx<T> (&acc)[4][3]) {
+                                                const typename S::word* lcl, int R, int xl, int v, T diag,
+                                                cpx<T> (&acc)[4][3]) {
   constexpr int SSW = SiteStride<NV, S>::WORDS;
   int dy, dz, dt;
   bri_row_offset(r, dy, dz, dt);
@@ -202,11 +204,23 @@ __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* b
     const typename S::word* site = buf + (xl + 1 + dx) * SSW;
     if (k == 0) {
       // own site: the diagonal term
+      if constexpr (CLOV) {
+        cpx<T> p[4][3];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-          acc[q][cc] = rmadd(acc[q][cc], diag, S::template load<T>(site + (q * 3 + cc) * NV + v));
+          for (int cc = 0; cc < 3; ++cc) {
+            p[q][cc] = S::template load<T>(site + (q * 3 + cc) * NV + v);
+            acc[q][cc] = rmadd(acc[q][cc], diag, p[q][cc]);
+          }
+        clover_madd<S, T>(lcl + xl * 36, p, acc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            acc[q][cc] = rmadd(acc[q][cc], diag, S::template load<T>(site + (q * 3 + cc) * NV + v));
+      }
       continue;
     }
     const T a = T(-0.5) * bri_lambda<T>(k);
@@ -220,10 +234,13 @@ __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* b
 
 }  // namespace
 
-template <bool ADJ, int NV, class S, class T>
+// CLOV: adds the site-local clover term (packed, 36 words per site, staged
+// in LDS after the link columns).
+template <bool ADJ, bool CLOV, int NV, class S, class T>
 __global__ void __launch_bounds__(256, 3)
     brillouin_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ Wl,
-                          const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
+                          const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                          const typename S::word* __restrict__ C, T diag) {
   using W = typename S::word;
   using St = BriStage<NV, S>;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
@@ -231,6 +248,7 @@ __global__ void __launch_bounds__(256, 3)
   const int R = int(tr.sb);
   W* buf = reinterpret_cast<W*>(smem_bri);
   W* wbuf = buf + (R + 2) * SSW;  // [3][R][9]
+  W* lcl = wbuf + ((27 * R + 3) & ~3);  // [R][36] (CLOV), 16-byte aligned
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const RowChunk c = row_chunk(g, tr, L);
@@ -248,6 +266,8 @@ __global__ void __launch_bounds__(256, 3)
   // about a thousand instructions per lane hide the load latency); the
   // request after the last row repeats it, unused, so every load is
   // unconditional and in bounds
+  if constexpr (CLOV)
+    copy_pieces<3>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * (36 * int(sizeof(W)) / 16), tid, nth);
   BriRowRegs<NV, S> q;
   bri_issue<NV, S>(g, c, Wl, in, 0, xm, xp, xl, v, tid, nth, q);
 #pragma nounroll
@@ -255,7 +275,7 @@ __global__ void __launch_bounds__(256, 3)
     bri_commit<NV, S>(c, q, buf, wbuf, R, xl, v, tid, nth);
     __syncthreads();
     bri_issue<NV, S>(g, c, Wl, in, r + 1 < kBriRows ? r + 1 : kBriRows - 1, xm, xp, xl, v, tid, nth, q);
-    bri_row_compute<ADJ, NV, S, T>(r, buf, wbuf, R, xl, v, diag, acc);
+    bri_row_compute<ADJ, CLOV, NV, S, T>(r, buf, wbuf, lcl, R, xl, v, diag, acc);
     __syncthreads();
   }
   // output through LDS, coalesced 16-byte stores
@@ -281,18 +301,22 @@ __global__ void __launch_bounds__(256, 3)
 
 template <int NV, class S, class T>
 static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* Wl, const void* in,
-                                   void* out, double mass, hipStream_t st) {
+                                   void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
-  const size_t lds = (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(3 * R) * 9) * sizeof(W);
+  const size_t lds =
+      (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(3 * R) * 9 + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   const T diag = T(mass) + T(15.0 / 8.0);
-  if (adj)
-    hipLaunchKernelGGL((brillouin_rows_kernel<true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl,
-                       (const W*)in, (W*)out, diag);
-  else
-    hipLaunchKernelGGL((brillouin_rows_kernel<false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl,
-                       (const W*)in, (W*)out, diag);
+#define DSL_BK(A, CL)                                                                                        \
+  hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl, \
+                     (const W*)in, (W*)out, (const W*)C, diag)
+  if (C) {
+    if (adj) DSL_BK(true, true); else DSL_BK(false, true);
+  } else {
+    if (adj) DSL_BK(true, false); else DSL_BK(false, false);
+  }
+#undef DSL_BK
   return hipGetLastError();
 }
 
@@ -300,7 +324,7 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 // when the configuration is not covered (the caller then uses the direct
 // kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
-                                 double mass, hipStream_t st) {
+                                 double mass, hipStream_t st, const void* clover) {
   if (const char* e = getenv("DSLASH_ROWS"))
     if (atoi(e) == 0) return hipErrorNotSupported;
   // FP32 only: the FP64 variant would not fit in registers
@@ -315,7 +339,7 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
   if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
   bool xcd = true;
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
-  return brillouin_rows_t<12, C64, float>(adj, g, R, bt, xcd, Wl, in, out, mass, st);
+  return brillouin_rows_t<12, C64, float>(adj, g, R, bt, xcd, Wl, in, out, clover, mass, st);
 }
 
 }  // namespace dsl

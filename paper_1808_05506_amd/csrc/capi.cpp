@@ -78,10 +78,10 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 101; }
+int dslash_version(void) { return 102; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
-                        int Nv, double mass, int dtype, void* stream) {
+                        int Nv, double mass, int dtype, void* stream, const void* C = nullptr) {
   g_err[0] = 0;
   if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
   if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
@@ -92,8 +92,9 @@ static int apply_common(bool adj, int op, const void* U, const void* in, void* o
   const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * eb;
   if (overlap(in, nspin, out, nspin)) return fail(DSLASH_E_ALIAS, "in and out overlap");
   if (overlap(U, nlink, out, nspin)) return fail(DSLASH_E_ALIAS, "U and out overlap");
+  if (C && overlap(C, size_t(vol) * 36 * eb, out, nspin)) return fail(DSLASH_E_ALIAS, "C and out overlap");
   const dsl::Geom g = dsl::make_geom(dims, Nv);
-  hipError_t e = dsl::launch_apply(op, adj, dtype, g, U, in, out, mass, (hipStream_t)stream);
+  hipError_t e = dsl::launch_apply(op, adj, dtype, g, U, in, out, mass, (hipStream_t)stream, C);
   if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
   return DSLASH_OK;
 }
@@ -106,6 +107,29 @@ int dslash_apply(int op, const void* U, const void* in, void* out, const int dim
 int dslash_apply_adjoint(int op, const void* U, const void* in, void* out, const int dims[4], int Nc, int Nv,
                          double mass, int dtype, void* stream) {
   return apply_common(true, op, U, in, out, dims, Nc, Nv, mass, dtype, stream);
+}
+
+int dslash_clover_field(const void* V, void* C, const int dims[4], int Nc, double c_sw, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_WILSON, dims, Nc, 1)) return rc;
+  if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
+  if (!V || !C) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  if (overlap(V, size_t(vol) * 36 * eb, C, size_t(vol) * 36 * eb)) return fail(DSLASH_E_ALIAS, "V and C overlap");
+  const dsl::Geom g = dsl::make_geom(dims, 1);
+  hipError_t e = dsl::launch_clover_field(dtype, g, V, C, c_sw, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_clover_field launch");
+  return DSLASH_OK;
+}
+
+int dslash_apply_clover(int op, const void* U, const void* C, const void* in, void* out, const int dims[4], int Nc,
+                        int Nv, double mass, int adjoint, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (op != DSLASH_WILSON && op != DSLASH_BRILLOUIN)
+    return fail(DSLASH_E_ARG, "the clover term belongs to WILSON and BRILLOUIN (got op %d)", op);
+  if (!C) return fail(DSLASH_E_ARG, "C is NULL");
+  return apply_common(adjoint != 0, op, U, in, out, dims, Nc, Nv, mass, dtype, stream, C);
 }
 
 int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U, void* grad_in,

@@ -24,15 +24,18 @@ struct Shape {
 };
 Shape site_v_shape(uint32_t vol, int nv);
 
+// clover: packed site-local clover term (36 words per site) added to D_W or
+// D_B, or nullptr; STAGGERED takes none.
 hipError_t launch_apply(int op, bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                        double mass, hipStream_t st);
+                        double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st);
+                              double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_staggered_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st);
 hipError_t launch_brillouin_rows(bool adjoint, int dtype, const Geom& g, const void* W, const void* in, void* out,
-                                 double mass, hipStream_t st);
+                                 double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
+hipError_t launch_clover_field(int dtype, const Geom& g, const void* V, void* C, double c_sw, hipStream_t st);
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st);
 hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,

@@ -158,4 +158,28 @@ __device__ __forceinline__ void lds_column(const typename S::word* site, int v, 
 }
 
 
+// Copy `pieces` 16-byte pieces (both pointers 16-byte aligned) with the
+// workgroup's threads; consecutive threads move consecutive pieces and each
+// thread moves at most K.  Loads and stores are both unconditional: indices
+// past the end are clamped to the last piece, so a surplus lane rewrites that
+// piece with the value it already holds.  Predicated loads would be sunk by
+// the compiler into their store's branch and waited for one at a time.
+template <int K>
+__device__ __forceinline__ void copy_pieces(void* __restrict__ dst, const void* __restrict__ src, int pieces,
+                                            int tid, int nth) {
+  const u32x4* s = static_cast<const u32x4*>(src);
+  u32x4* d = static_cast<u32x4*>(dst);
+  u32x4 r[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int i = tid + j * nth;
+    r[j] = s[i < pieces ? i : pieces - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int i = tid + j * nth;
+    d[i < pieces ? i : pieces - 1] = r[j];
+  }
+}
+
 }  // namespace dsl

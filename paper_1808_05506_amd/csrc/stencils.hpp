@@ -36,6 +36,61 @@ DSL_HD void load_wspinor(const typename S::word* __restrict__ in, size_t base, i
     for (int c = 0; c < 3; ++c) p[sp][c] = S::template load<T>(in + base + size_t(sp * 3 + c) * nv);
 }
 
+// ---------------------------------------------------------------- clover term
+// res += C(x) p for the site-local clover term -(c_SW/2) sum_{mu<nu} sigma_{mu nu}
+// F_{mu nu}(x) of eqs. def_wils / def_bril.  In the chiral basis it is block
+// diagonal: block b acts on spins 2b, 2b+1, row index 3 s' + c.  Each block is
+// Hermitian and stored in 18 complex words: words 0..2 hold the real diagonal
+// pairwise, (H_00, H_11), (H_22, H_33), (H_44, H_55); words 3..17 the upper
+// triangle H_ij (i < j) row by row.  C points at the site's 36 words.
+template <class S, class T>
+DSL_HD void clover_madd(const typename S::word* C, const cpx<T> (&p)[4][3], cpx<T> (&res)[4][3]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const typename S::word* h = C + 18 * b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const cpx<T> d = S::template load<T>(h + k);
+      const int i0 = 2 * k, i1 = 2 * k + 1;
+      res[2 * b + i0 / 3][i0 % 3] = rmadd(res[2 * b + i0 / 3][i0 % 3], d.r, p[2 * b + i0 / 3][i0 % 3]);
+      res[2 * b + i1 / 3][i1 % 3] = rmadd(res[2 * b + i1 / 3][i1 % 3], d.i, p[2 * b + i1 / 3][i1 % 3]);
+    }
+    int w = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j, ++w) {
+        const cpx<T> hij = S::template load<T>(h + w);
+        cpx<T>& ri = res[2 * b + i / 3][i % 3];
+        cpx<T>& rj = res[2 * b + j / 3][j % 3];
+        ri = cmadd(ri, hij, p[2 * b + j / 3][j % 3]);
+        rj = cjmadd(rj, hij, p[2 * b + i / 3][i % 3]);
+      }
+  }
+}
+
+// out(x) = diag in(x) + ca acc (+ C(x) in(x) if C is given) for one (site, rhs)
+// of the direct kernels.
+template <class S, class T>
+DSL_HD void site_finish(const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
+                        const typename S::word* __restrict__ C, uint32_t s, size_t base, int nv, T diag, T ca,
+                        const cpx<T> (&acc)[4][3]) {
+  cpx<T> p[4][3], res[4][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      p[sp][c] = S::template load<T>(in + base + size_t(sp * 3 + c) * nv);
+      res[sp][c].r = fma(diag, p[sp][c].r, ca * acc[sp][c].r);
+      res[sp][c].i = fma(diag, p[sp][c].i, ca * acc[sp][c].i);
+    }
+  if (C) clover_madd<S, T>(C + size_t(s) * 36, p, res);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(out + base + size_t(sp * 3 + c) * nv, res[sp][c]);
+}
+
 // h = psi_up + c A_mu psi_low
 template <int MU, int C, class T>
 DSL_HD void project(const cpx<T> (&p)[4][3], cpx<T> (&h)[2][3]) {
@@ -116,7 +171,7 @@ DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S:
 template <bool ADJ, class S, class T>
 DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
-                        uint32_t s, const SiteNbr& nb, int v, T diag) {
+                        const typename S::word* __restrict__ C, uint32_t s, const SiteNbr& nb, int v, T diag) {
   constexpr int CF = ADJ ? +1 : -1;  // forward projector 1 + CF gamma
   constexpr int CB = -CF;            // backward projector 1 + CB gamma
   const int nv = g.nv;
@@ -140,18 +195,7 @@ DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
   wilson_hop<3, CF, false, S, T>(U, in, (size_t(s) * 4 + 3) * 9, sf3 * sps + v, nv, acc);
   wilson_hop<3, CB, true, S, T>(U, in, (size_t(sb3) * 4 + 3) * 9, sb3 * sps + v, nv, acc);
 
-  const size_t base = size_t(s) * sps + v;
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t e = base + size_t(sp * 3 + c) * nv;
-      cpx<T> p = S::template load<T>(in + e);
-      cpx<T> o;
-      o.r = fma(diag, p.r, T(-0.5) * acc[sp][c].r);
-      o.i = fma(diag, p.i, T(-0.5) * acc[sp][c].i);
-      S::template store<T>(out + e, o);
-    }
+  site_finish<S, T>(in, out, C, s, size_t(s) * sps + v, nv, diag, T(-0.5), acc);
 }
 
 // D_S (Sec. 3): out(x) = m in(x) + sum_mu eta_mu(x)/2 [V_mu(x) in(x+mu) - V_mu(x-mu)^dag in(x-mu)],
@@ -260,7 +304,7 @@ template <class T> DSL_HD cpx<T> cmadd_ab(cpx<T> acc, T alpha, T beta, cpx<T> y)
 template <bool ADJ, class S, class T>
 DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W,
                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
-                           uint32_t s, const SiteNbr& nb, int v, T diag) {
+                           const typename S::word* __restrict__ C, uint32_t s, const SiteNbr& nb, int v, T diag) {
   const int nv = g.nv;
   const size_t sps = size_t(12) * nv;
   cpx<T> acc[4][3];
@@ -348,18 +392,7 @@ DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W
       }
     }
   }
-  const size_t base = size_t(s) * sps + v;
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const size_t e = base + size_t(q * 3 + c) * nv;
-      cpx<T> p = S::template load<T>(in + e);
-      cpx<T> o;
-      o.r = fma(diag, p.r, acc[q][c].r);
-      o.i = fma(diag, p.i, acc[q][c].i);
-      S::template store<T>(out + e, o);
-    }
+  site_finish<S, T>(in, out, C, s, size_t(s) * sps + v, nv, diag, T(1), acc);
 }
 
 // ---------------------------------------------------------------- W build

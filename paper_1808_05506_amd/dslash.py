@@ -22,7 +22,8 @@ import torch
 
 __all__ = [
     "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
-    "backward", "brillouin_links", "convert", "solve", "dslash", "op_code",
+    "backward", "brillouin_links", "convert", "solve", "dslash", "op_code", "clover_field", "eo_pack", "eo_unpack",
+    "eo_hop",
 ]
 
 STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
@@ -57,11 +58,13 @@ def _load():
     lib.dslash_solve_eo_workspace_bytes.restype = sz
     lib.dslash_solve_eo.argtypes = [vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                     ctypes.POINTER(ctypes.c_double), ip, vp]
+    lib.dslash_clover_field.argtypes = [vp, vp, ip, i, d, i, vp]
+    lib.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
                  "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
-                 "dslash_eo_hop", "dslash_solve_eo"):
+                 "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -154,8 +157,9 @@ def _validate(op: int, U: torch.Tensor, psi: torch.Tensor):
 
 
 def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
-          out: torch.Tensor | None = None) -> torch.Tensor:
-    """out = D psi (or D^dag psi); no autograd (see ``dslash``)."""
+          out: torch.Tensor | None = None, clover: torch.Tensor | None = None) -> torch.Tensor:
+    """out = D psi (or D^dag psi), plus C psi for a clover field C from
+    ``clover_field`` (WILSON, BRILLOUIN); no autograd (see ``dslash``)."""
     op = op_code(op)
     lat, nv = _validate(op, U, psi)
     if out is None:
@@ -164,10 +168,31 @@ def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bo
         _require(out, "out")
         if out.shape != psi.shape or out.dtype != psi.dtype:
             raise ValueError("out must match psi in shape and dtype")
+    if clover is not None:
+        _require(clover, "clover")
+        if _core_shape(clover) != tuple(lat) + (2, 18) or _dtype_code(clover) != _dtype_code(psi):
+            raise ValueError(f"clover must be [Nt,Nz,Ny,Nx,2,18] in the dtype of psi, got {tuple(clover.shape)}")
+        _check(_lib.dslash_apply_clover(op, _ptr(U), _ptr(clover), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv,
+                                        float(mass), int(bool(adjoint)), _dtype_code(psi), _stream(psi)),
+               "dslash_apply_clover")
+        return out
     fn = _lib.dslash_apply_adjoint if adjoint else _lib.dslash_apply
     _check(fn(op, _ptr(U), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass), _dtype_code(psi),
               _stream(psi)), "dslash_apply")
     return out
+
+
+def clover_field(V: torch.Tensor, c_sw: float) -> torch.Tensor:
+    """Packed clover term -(c_SW/2) sum sigma F of the links V: [Nt,Nz,Ny,Nx,2,18]."""
+    _require(V, "V")
+    vs = _core_shape(V)
+    if len(vs) != 7 or vs[4:] != (4, 3, 3):
+        raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
+    pair = _dtype_code(V) in (BF16, F16)
+    C = torch.empty(vs[:4] + (2, 18) + ((2,) if pair else ()), dtype=V.dtype, device=V.device)
+    _check(_lib.dslash_clover_field(_ptr(V), _ptr(C), _dims_c(vs), 3, float(c_sw), _dtype_code(V), _stream(V)),
+           "dslash_clover_field")
+    return C
 
 
 def apply_adjoint(op, U, psi, mass: float = 0.0, out=None):

@@ -35,6 +35,8 @@ def lib():
     l.dslash_solve_eo_workspace_bytes.restype = sz
     l.dslash_solve_eo.argtypes = [vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                   ctypes.POINTER(ctypes.c_double), ip, vp]
+    l.dslash_clover_field.argtypes = [vp, vp, ip, i, d, i, vp]
+    l.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     return l
 
 
@@ -45,10 +47,10 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 15
+    assert len(declared) == 17
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 101
+    assert lib.dslash_version() == 102
 
 
 def test_status_strings(lib):
@@ -144,3 +146,17 @@ def test_even_odd_validation(lib):
     assert lib.dslash_solve_eo(A, B, C, odd, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1
     assert lib.dslash_solve_eo(A, B, C, even, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 16, rel, it, None) == 6
     assert lib.dslash_solve_eo(A, B, C, even, 3, 2, -4.0, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1
+
+
+def test_clover_validation(lib):
+    dims = _dims(4, 4, 4, 4)
+    D = 0x20000000
+    assert lib.dslash_clover_field(None, B, dims, 3, 1.0, 0, None) == 1           # NULL V
+    assert lib.dslash_clover_field(A, A, dims, 3, 1.0, 0, None) == 3              # V == C
+    assert lib.dslash_clover_field(A, B, _dims(4, 1, 4, 4), 3, 1.0, 0, None) == 1  # extent 1
+    assert lib.dslash_clover_field(A, B, dims, 2, 1.0, 0, None) == 2              # Nc != 3
+    assert lib.dslash_clover_field(A, B, dims, 3, 1.0, 7, None) == 1              # dtype
+    assert lib.dslash_apply_clover(0, A, B, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # staggered
+    assert lib.dslash_apply_clover(1, A, None, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # no C
+    assert lib.dslash_apply_clover(1, A, B, C, C, dims, 3, 2, 0.1, 0, 0, None) == 3  # in == out
+    assert lib.dslash_apply_clover(1, A, B, C, B, dims, 3, 2, 0.1, 0, 0, None) == 3  # out == C
