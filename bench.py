@@ -12,9 +12,10 @@ well above the 256 MB Infinity Cache.
 
 Further rows (``rows`` in the JSON line), each timed the same way:
 D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
-BF16 storage, link gradients at 24^3 x 48, and the mixed-precision solve at
-32^3 x 64 (time to ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16
-inner storage).
+BF16 storage, D_W and D_B with the clover term (c_SW = 1), link gradients at
+24^3 x 48, and the mixed-precision solve at 32^3 x 64 (time to
+||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16 inner storage, on the
+full lattice and on the even-odd Schur complement).
 
 cpu_baseline: the FP64 numpy oracle applying the same operator on the host
 cores (BLAS pinned to one thread), on the full headline workload.
@@ -36,6 +37,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_PEAK = 78.6e12       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
 FP64_VALU_PEAK = 78.6e12
 FLOPS = {"staggered": 570, "wilson": 1320, "brillouin": 28224}   # per site and right-hand side
+CLOVER_FLOPS = 576             # two 6x6 complex matrix-vector products and their addition, per site and rhs
 
 
 def log(*a):
@@ -88,24 +90,28 @@ def timed(torch, launch, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def rotated_sets(torch, U, P, count: int):
-    """``count`` distinct input sets: lattice translations of (U, P) along t."""
-    sets = [(U, P)]
+def rotated_sets(torch, U, P, count: int, C=None):
+    """``count`` distinct input sets: lattice translations of (U, P[, C]) along t."""
+    roll = lambda x, k: None if x is None else torch.roll(x, shifts=k, dims=0).contiguous()  # noqa: E731
+    sets = [(U, P, C)]
     for k in range(1, count):
-        sets.append((torch.roll(U, shifts=k, dims=0).contiguous(), torch.roll(P, shifts=k, dims=0).contiguous()))
+        sets.append((roll(U, k), roll(P, k), roll(C, k)))
     return sets
 
 
-def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label):
-    sets = rotated_sets(torch, U, P, rotate)
+def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label, clover=None):
+    sets = rotated_sets(torch, U, P, rotate, clover)
     outs = [torch.empty_like(P) for _ in sets]
-    launch = lambda i: D.apply(op, sets[i % len(sets)][0], sets[i % len(sets)][1], mass, out=outs[i % len(sets)])
+
+    def launch(i):
+        u, p, c = sets[i % len(sets)]
+        D.apply(op, u, p, mass, out=outs[i % len(sets)], clover=c)
     t = timed(torch, launch, steps, warmup)
     nt, nz, ny, nx = P.shape[:4]
     vol = nt * nz * ny * nx
     nv = P.shape[-1] if P.dtype in (torch.complex64, torch.complex128) else P.shape[-2]
-    flops = FLOPS[op] * vol * nv
-    nbytes = site_bytes(op, nv, dtype_bytes) * vol
+    flops = (FLOPS[op] + (CLOVER_FLOPS if clover is not None else 0)) * vol * nv
+    nbytes = (site_bytes(op, nv, dtype_bytes) + (36 * dtype_bytes if clover is not None else 0)) * vol
     row = {"us": t * 1e6, "gflops": flops / t / 1e9, "gbs": nbytes / t / 1e9,
            "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": flops,
            "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
@@ -171,6 +177,22 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
         row["valu_peak_tflops"] = peak / 1e12
         row["w_build_ms"] = tw * 1e3
         rows[f"brillouin_32^4_nv12_{name}"] = row
+        if name == "fp32":
+            # with the clover term (c_SW = 1), built from V on the GPU (untimed setup)
+            V = up(v, cdt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C = D.clover_field(V, 1.0)
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            del V
+            row, t = bench_apply(torch, D, "brillouin", W, P, 0.1, max(3, steps // 10), 2, 1, eb,
+                                 "D_B + clover 32^4 fp32", clover=C)
+            row["valu_frac"] = row["flops_per_launch"] / t / peak
+            row["clover_build_ms"] = tc * 1e3
+            row["c_sw"] = 1.0
+            rows["brillouin_clover_32^4_nv12_fp32"] = row
+            del C
         del W, P
         torch.cuda.empty_cache()
     # D_W with BF16 storage (FP32 arithmetic) on the headline workload
@@ -181,6 +203,14 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     Pb = D.convert(up(p, np.complex64), "bf16")
     rows["wilson_16^3x32_nv12_bf16"], _ = bench_apply(torch, D, "wilson", Ub, Pb, 0.1, steps, warmup, 4, 4,
                                                       "D_W bf16")
+    del Ub, Pb
+    # D_W with the clover term (c_SW = 1) on the headline workload, FP32
+    U, P = up(u, np.complex64), up(p, np.complex64)
+    C = D.clover_field(U, 1.0)
+    row, _ = bench_apply(torch, D, "wilson", U, P, 0.1, steps, warmup, 4, 8, "D_W + clover fp32", clover=C)
+    row["c_sw"] = 1.0
+    rows["wilson_clover_16^3x32_nv12_fp32"] = row
+    del U, P, C
     # link gradients at 24^3 x 48, N_v = 12
     dims = (24, 24, 24, 48)
     for op, kind, seed in (("staggered", "haar", 4), ("wilson", "smooth", 5)):

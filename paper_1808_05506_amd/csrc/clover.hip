@@ -87,6 +87,8 @@ DSL_HD void add_scaled(cpx<T> (&dst)[3][3], const cpx<T> (&f)[3][3]) {
     }
 }
 
+}  // namespace
+
 template <class S, class T>
 __global__ void __launch_bounds__(128) clover_field_kernel(Geom g, const typename S::word* __restrict__ V,
                                                           typename S::word* __restrict__ C, T coef) {
@@ -174,6 +176,8 @@ __global__ void __launch_bounds__(128) clover_field_kernel(Geom g, const typenam
       }
   }
 }
+
+namespace {
 
 template <class S, class T>
 hipError_t clover_field_t(const Geom& g, const void* V, void* C, double c_sw, hipStream_t st) {
