@@ -136,6 +136,29 @@ int dslash_apply_clover(int op, const void* U, const void* C, const void* in, vo
                         int Nc, int Nv, double mass, int adjoint, int dtype, void* stream);
 
 /*
+ * Gauge compression (Sec. 4 names storing N_c - 1 colour rows of V as a next
+ * step; Sec. 5 notes that 36 of the 40 W are not special unitary, so it is
+ * offered for V only).  An SU(3) link is fixed by its first two rows: the
+ * third is u_2j = conj(u_0k u_1l - u_0l u_1k), (j, k, l) cyclic.
+ *
+ * dslash_compress_links: Vc[..][mu][a][b] = V[..][mu][a][b] for a = 0, 1;
+ * Vc is [Nt][Nz][Ny][Nx][4][2][3] (24 words per site instead of 36).  V must
+ * be SU(3) for the compressed operator to equal the full one; nothing checks
+ * this.  V and Vc must not overlap (E_ALIAS).  Asynchronous on `stream`.
+ */
+int dslash_compress_links(const void* V, void* Vc, const int dims[4], int Nc, int dtype, void* stream);
+
+/*
+ * out = D in (adjoint == 0) or D^dag in, for op = STAGGERED or WILSON, with
+ * the links read from their compressed form Vc and completed in the kernel.
+ * Other ops -> E_ARG; otherwise the arguments and errors of dslash_apply.
+ * N_v = 12 runs the row-staged kernels (STAGGERED: C64, C128; WILSON: FP32
+ * arithmetic on C64, BF16, F16 storage).
+ */
+int dslash_apply_compressed(int op, const void* Vc, const void* in, void* out, const int dims[4], int Nc,
+                            int Nv, double mass, int adjoint, int dtype, void* stream);
+
+/*
  * Backward pass of out = D[U] in for a real loss L with grad_out = dL/dout
  * (PyTorch convention for complex tensors: dL/dRe + i dL/dIm).
  *   grad_in = D^dag grad_out                                   (nullable)

@@ -79,7 +79,7 @@ static Launch make_launch(const Geom& g) {
   return L;
 }
 
-template <int OP, bool ADJ, class S, class T>
+template <int OP, bool ADJ, class S, class T, int LW>
 __global__ void __launch_bounds__(256) apply_kernel(Geom g, RowTraversal tr, int rows, int xcd,
                                                    const typename S::word* __restrict__ U,
                                                    const typename S::word* __restrict__ in,
@@ -99,57 +99,64 @@ __global__ void __launch_bounds__(256) apply_kernel(Geom g, RowTraversal tr, int
   }
   if (!live || v >= g.nv) return;
   if (OP == OP_STAGGERED)
-    staggered_site<ADJ, S, T>(g, U, in, out, s, nb, v, mass);
+    staggered_site<ADJ, S, T, LW>(g, U, in, out, s, nb, v, mass);
   else if (OP == OP_WILSON)
-    wilson_site<ADJ, S, T>(g, U, in, out, C, s, nb, v, T(4) + mass);
+    wilson_site<ADJ, S, T, LW>(g, U, in, out, C, s, nb, v, T(4) + mass);
   else
     brillouin_site<ADJ, S, T>(g, U, in, out, C, s, nb, v, mass + T(15.0 / 8.0));
 }
 
 template <int OP, class S, class T>
 static hipError_t apply_t(bool adj, const Geom& g, const void* U, const void* in, void* out, const void* C,
-                          double mass, hipStream_t st) {
+                          double mass, bool compressed, hipStream_t st) {
   using W = typename S::word;
   const Launch L = make_launch(g);
-  if (adj)
-    hipLaunchKernelGGL((apply_kernel<OP, true, S, T>), L.sh.grid, L.sh.block, 0, st, g, L.tr, int(L.rows),
-                       int(L.xcd), (const W*)U, (const W*)in, (W*)out, (const W*)C, T(mass));
-  else
-    hipLaunchKernelGGL((apply_kernel<OP, false, S, T>), L.sh.grid, L.sh.block, 0, st, g, L.tr, int(L.rows),
-                       int(L.xcd), (const W*)U, (const W*)in, (W*)out, (const W*)C, T(mass));
+#define DSL_AK(A, LW)                                                                                        \
+  hipLaunchKernelGGL((apply_kernel<OP, A, S, T, LW>), L.sh.grid, L.sh.block, 0, st, g, L.tr, int(L.rows), \
+                     int(L.xcd), (const W*)U, (const W*)in, (W*)out, (const W*)C, T(mass))
+  if constexpr (OP != OP_BRILLOUIN) {
+    if (compressed) {
+      if (adj) DSL_AK(true, 6); else DSL_AK(false, 6);
+      return hipGetLastError();
+    }
+  }
+  if (adj) DSL_AK(true, 9); else DSL_AK(false, 9);
+#undef DSL_AK
   return hipGetLastError();
 }
 
 template <int OP>
 static hipError_t apply_op(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                           const void* C, double mass, hipStream_t st) {
+                           const void* C, double mass, bool compressed, hipStream_t st) {
   switch (dtype) {
-    case DT_C64: return apply_t<OP, C64, float>(adj, g, U, in, out, C, mass, st);
-    case DT_C128: return apply_t<OP, C128, double>(adj, g, U, in, out, C, mass, st);
-    case DT_BF16: return apply_t<OP, BF16, float>(adj, g, U, in, out, C, mass, st);
-    case DT_F16: return apply_t<OP, F16, float>(adj, g, U, in, out, C, mass, st);
+    case DT_C64: return apply_t<OP, C64, float>(adj, g, U, in, out, C, mass, compressed, st);
+    case DT_C128: return apply_t<OP, C128, double>(adj, g, U, in, out, C, mass, compressed, st);
+    case DT_BF16: return apply_t<OP, BF16, float>(adj, g, U, in, out, C, mass, compressed, st);
+    case DT_F16: return apply_t<OP, F16, float>(adj, g, U, in, out, C, mass, compressed, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                        double mass, hipStream_t st, const void* clover) {
+                        double mass, hipStream_t st, const void* clover, bool compressed) {
   switch (op) {
     case OP_STAGGERED: {
       if (clover) return hipErrorInvalidValue;
-      const hipError_t e = launch_staggered_rows(adj, dtype, g, U, in, out, mass, st);
+      const hipError_t e = launch_staggered_rows(adj, dtype, g, U, in, out, mass, st, compressed);
       if (e != hipErrorNotSupported) return e;
-      return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, nullptr, mass, st);
+      return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, nullptr, mass, compressed, st);
     }
     case OP_WILSON: {
-      const hipError_t e = launch_wilson_rows(adj, dtype, g, U, in, out, mass, st, clover);
+      if (clover && compressed) return hipErrorInvalidValue;
+      const hipError_t e = launch_wilson_rows(adj, dtype, g, U, in, out, mass, st, clover, compressed);
       if (e != hipErrorNotSupported) return e;
-      return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, clover, mass, st);
+      return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, clover, mass, compressed, st);
     }
     case OP_BRILLOUIN: {
+      if (compressed) return hipErrorInvalidValue;
       const hipError_t e = launch_brillouin_rows(adj, dtype, g, U, in, out, mass, st, clover);
       if (e != hipErrorNotSupported) return e;
-      return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, clover, mass, st);
+      return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, clover, mass, false, st);
     }
   }
   return hipErrorInvalidValue;

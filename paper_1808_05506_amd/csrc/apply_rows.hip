@@ -17,7 +17,7 @@ namespace dsl {
 //                           the halo sites x0 - 1 and x0 + n); reused for the output
 //   lown [(R + 1) * 36]     links of sites x0 - 1 .. x0 + n - 1 (index x - x0 + 1)
 //   lnb  [R * 9]            V_mu of the backward neighbour row (current mu)
-template <int NV, class S>
+template <int NV, class S, int LW = 9>
 size_t rows_lds_words(int R);
 
 template <class S, class T, int NV>
@@ -29,7 +29,7 @@ DSL_HD void lds_spinor(const typename S::word* __restrict__ site, int v, cpx<T> 
 }
 
 // acc += (1 + C gamma_MU) U' psi with psi and U' read from LDS
-template <int MU, int C, bool DAG, int NV, class S, class T>
+template <int MU, int C, bool DAG, int NV, class S, class T, int LW = 9>
 __device__ __forceinline__ void lds_hop(const typename S::word* __restrict__ site,
                                        const typename S::word* __restrict__ link, int v, cpx<T> (&acc)[4][3]) {
   cpx<T> p[4][3];
@@ -37,10 +37,14 @@ __device__ __forceinline__ void lds_hop(const typename S::word* __restrict__ sit
   cpx<T> h[2][3];
   project<MU, C, T>(p, h);
   cpx<T> u[3][3];
+  if constexpr (LW == 9) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(link + a * 3 + b);
+      for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(link + a * 3 + b);
+  } else {
+    load_link_lw<LW, S, T>(link, u);
+  }
   cpx<T> t[2][3];
   su3_mul2<DAG, T>(u, h, t);
   reconstruct_add<MU, C, T>(acc, t);
@@ -85,9 +89,9 @@ struct RowPieces {
   static constexpr int CH = 12 * int(sizeof(typename S::word)) / 16;
 };
 
-template <int NV, class S>
+template <int NV, class S, int LW>
 size_t rows_lds_words(int R) {
-  return size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R + 1) * 36 + size_t(R) * 9;
+  return size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R + 1) * 4 * LW + size_t(R) * LW;
 }
 
 // Piece assignment of a staged row: lane (x, v) of the workgroup moves the
@@ -95,7 +99,7 @@ size_t rows_lds_words(int R) {
 // of a site read N_v consecutive 16-byte pieces per instruction and the LDS
 // position follows from the site without a division.  Lanes past a partial
 // chunk's end repeat the last site (same data to the same place).
-template <int MU, int SGN, int NV, class S>
+template <int MU, int SGN, int NV, class S, int LW = 9>
 __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                           const typename S::word* __restrict__ in, int xl, int v, int tid,
                                           u32x4 (&r)[RowPieces<S>::CH + 1]) {
@@ -107,9 +111,9 @@ __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, cons
 #pragma unroll
   for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
   if (SGN < 0) {
-    const int w = tid < c.n * 9 ? tid : c.n * 9 - 1;
-    const int k = w / 9, e = w - k * 9;
-    r[CH] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * 9 + e]);
+    const int w = tid < c.n * LW ? tid : c.n * LW - 1;
+    const int k = w / LW, e = w - k * LW;
+    r[CH] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * LW + e]);
   } else {
     // every row writes the whole array, so that call sites merged into one
     // array store the same elements (the compiler's store sinking would
@@ -118,7 +122,7 @@ __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, cons
   }
 }
 
-template <int SGN, int NV, class S>
+template <int SGN, int NV, class S, int LW = 9>
 __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
                                            typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
   using W = typename S::word;
@@ -127,7 +131,7 @@ __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[R
   u32x4* dst = reinterpret_cast<u32x4*>(row) + xc * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
-  if (SGN < 0) lnb[tid < c.n * 9 ? tid : c.n * 9 - 1] = piece_to_word<W>(r[CH]);
+  if (SGN < 0) lnb[tid < c.n * LW ? tid : c.n * LW - 1] = piece_to_word<W>(r[CH]);
 }
 
 // The chunk's own row in the same register shape: CH pieces of site x and,
@@ -162,14 +166,14 @@ __device__ __forceinline__ void own_commit(const RowChunk& c, const u32x4 (&r)[R
   hdst[h < SP ? h : h - SP] = r[CH];
 }
 
-template <int MU, int SGN, bool ADJ, int NV, class S, class T>
+template <int MU, int SGN, bool ADJ, int NV, class S, class T, int LW = 9>
 __device__ __forceinline__ void row_compute(const typename S::word* nbr, const typename S::word* lown,
                                             const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
   constexpr int SSW = SiteStride<NV, S>::WORDS;
   if (SGN > 0)
-    lds_hop<MU, (ADJ ? 1 : -1), false, NV, S, T>(nbr + xl * SSW, lown + (xl + 1) * 36 + MU * 9, v, acc);
+    lds_hop<MU, (ADJ ? 1 : -1), false, NV, S, T, LW>(nbr + xl * SSW, lown + (xl + 1) * 4 * LW + MU * LW, v, acc);
   else
-    lds_hop<MU, (ADJ ? -1 : 1), true, NV, S, T>(nbr + xl * SSW, lnb + xl * 9, v, acc);
+    lds_hop<MU, (ADJ ? -1 : 1), true, NV, S, T, LW>(nbr + xl * SSW, lnb + xl * LW, v, acc);
 }
 
 // Occupancy hint per prefetch depth: deeper prefetch holds more rows in
@@ -354,19 +358,19 @@ DSL_HD RowChunk march_chunk(const Geom& g, const MarchTraversal& m, uint32_t id,
 
 // Row K of a step's sequence (0 +y, 1 -y, 2 +z, 3 -z, 4 +t, 5 -t, 6 own) into
 // its register array.
-template <int K, int NV, class S>
+template <int K, int NV, class S, int LW = 9>
 __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                             const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
                                             int tid, u32x4 (&r0)[RowPieces<S>::CH + 1],
                                             u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
                                             u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
                                             u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1]) {
-  if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, U, in, xl, v, tid, r0);
-  if constexpr (K == 1) row_issue<1, -1, NV, S>(g, c, U, in, xl, v, tid, r1);
-  if constexpr (K == 2) row_issue<2, +1, NV, S>(g, c, U, in, xl, v, tid, r2);
-  if constexpr (K == 3) row_issue<2, -1, NV, S>(g, c, U, in, xl, v, tid, r3);
-  if constexpr (K == 4) row_issue<3, +1, NV, S>(g, c, U, in, xl, v, tid, r4);
-  if constexpr (K == 5) row_issue<3, -1, NV, S>(g, c, U, in, xl, v, tid, r5);
+  if constexpr (K == 0) row_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);
+  if constexpr (K == 1) row_issue<1, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r1);
+  if constexpr (K == 2) row_issue<2, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r2);
+  if constexpr (K == 3) row_issue<2, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r3);
+  if constexpr (K == 4) row_issue<3, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r4);
+  if constexpr (K == 5) row_issue<3, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r5);
   if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);
 }
 
@@ -379,37 +383,37 @@ template <bool FIRST> struct MarchSeq {
 
 // Links of sites x0 - 1 .. x0 + n - 1 of a row (36 words each): up to 3
 // 16-byte pieces per thread for the chunk, one for the halo site.
-template <class S>
+template <class S, int LW = 9>
 struct LinkPieces {
-  static constexpr int PER_SITE = 36 * int(sizeof(typename S::word)) / 16;
+  static constexpr int PER_SITE = 4 * LW * int(sizeof(typename S::word)) / 16;
 };
 
 // Pieces of the chunk's links per thread: ceil(LP / threads per site).
-template <class S, int THREADS_PER_SITE>
+template <class S, int THREADS_PER_SITE, int LW = 9>
 struct LinkK {
-  static constexpr int value = (LinkPieces<S>::PER_SITE + THREADS_PER_SITE - 1) / THREADS_PER_SITE;
+  static constexpr int value = (LinkPieces<S, LW>::PER_SITE + THREADS_PER_SITE - 1) / THREADS_PER_SITE;
 };
 
-template <class S, int K>
+template <class S, int K, int LW = 9>
 __device__ __forceinline__ void links_issue(const RowChunk& c, const typename S::word* __restrict__ U, int xm, int tid,
                                             int nth, u32x4 (&lr)[K + 1]) {
-  constexpr int LP = LinkPieces<S>::PER_SITE;
-  const u32x4* own = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + c.x0) * 36);
+  constexpr int LP = LinkPieces<S, LW>::PER_SITE;
+  const u32x4* own = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + c.x0) * 4 * LW);
   const int pieces = c.n * LP;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int i = tid + j * nth;
     lr[j] = own[i < pieces ? i : pieces - 1];
   }
-  const u32x4* halo = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + xm) * 36);
+  const u32x4* halo = reinterpret_cast<const u32x4*>(U + size_t(c.row_base + xm) * 4 * LW);
   lr[K] = halo[tid < LP ? tid : LP - 1];
 }
 
-template <class S, int K>
+template <class S, int K, int LW = 9>
 __device__ __forceinline__ void links_commit(const RowChunk& c, const u32x4 (&lr)[K + 1], typename S::word* lown,
                                              int tid, int nth) {
-  constexpr int LP = LinkPieces<S>::PER_SITE;
-  u32x4* own = reinterpret_cast<u32x4*>(lown + 36);
+  constexpr int LP = LinkPieces<S, LW>::PER_SITE;
+  u32x4* own = reinterpret_cast<u32x4*>(lown + 4 * LW);
   const int pieces = c.n * LP;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -430,7 +434,7 @@ __device__ __forceinline__ void hold_acc(cpx<T> (&acc)[4][3]) {
 // Two or three rows in flight fit the 168 VGPRs of three waves per SIMD.
 template <int DEPTH> struct MarchWaves { static constexpr int value = DEPTH <= 3 ? 3 : 2; };
 
-template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T>
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
 __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            const typename S::word* __restrict__ U,
                                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
@@ -439,18 +443,18 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            u32x4 (&r0)[RowPieces<S>::CH + 1], u32x4 (&r1)[RowPieces<S>::CH + 1],
                                            u32x4 (&r2)[RowPieces<S>::CH + 1], u32x4 (&r3)[RowPieces<S>::CH + 1],
                                            u32x4 (&r4)[RowPieces<S>::CH + 1], u32x4 (&r5)[RowPieces<S>::CH + 1],
-                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[LinkK<S, NV>::value + 1],
+                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[LinkK<S, NV, LW>::value + 1],
                                            cpx<T> (&carry)[2][3]) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
-  constexpr int LK = LinkK<S, NV>::value;
+  constexpr int LK = LinkK<S, NV, LW>::value;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
   constexpr int CF = ADJ ? +1 : -1, CB = -CF;
   // the first step's leading rows and links were requested by the caller; a
   // later step requests them here, after the previous step's last barrier
   if constexpr (!FIRST) {
-#define DSL_SISSUE(P) march_issue<Q::at(P), NV, S>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+#define DSL_SISSUE(P) march_issue<Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
     DSL_SISSUE(0);
     if constexpr (DEPTH > 1) DSL_SISSUE(1);
     if constexpr (DEPTH > 2) DSL_SISSUE(2);
@@ -458,9 +462,9 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
     if constexpr (DEPTH > 4) DSL_SISSUE(4);
     if constexpr (DEPTH > 5) DSL_SISSUE(5);
 #undef DSL_SISSUE
-    links_issue<S, LK>(c, U, xm, tid, nth, lr);
+    links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
   }
-  links_commit<S, LK>(c, lr, lown, tid, nth);
+  links_commit<S, LK, LW>(c, lr, lown, tid, nth);
 
   cpx<T> acc[4][3];
 #pragma unroll
@@ -470,13 +474,13 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
 
   W* const row = buf + SSW;
 #define DSL_MISSUE(P, CH_)                                                                             \
-  march_issue<Q::at(P), NV, S>(g, CH_, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+  march_issue<Q::at(P), NV, S, LW>(g, CH_, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
 #define DSL_MSTEP(P, MU, SGN, CUR)                                        \
   if constexpr (P < Q::N - 1) {                                           \
-    row_commit<SGN, NV, S>(c, CUR, row, lnb, xl, v, tid);                 \
+    row_commit<SGN, NV, S, LW>(c, CUR, row, lnb, xl, v, tid);                 \
     __syncthreads();                                                      \
     if constexpr (P + DEPTH < Q::N) DSL_MISSUE(P + DEPTH, c);             \
-    row_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);      \
+    row_compute<MU, SGN, ADJ, NV, S, T, LW>(row, lown, lnb, xl, v, acc);      \
     hold_acc<T>(acc);                                                     \
     __syncthreads();                                                      \
   }
@@ -493,8 +497,8 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
 #undef DSL_MISSUE
   cpx<T> res[4][3];
   {
-    lds_hop<0, CF, false, NV, S, T>(buf + (xl + 2) * SSW, lown + (xl + 1) * 36, v, acc);
-    lds_hop<0, CB, true, NV, S, T>(buf + xl * SSW, lown + xl * 36, v, acc);
+    lds_hop<0, CF, false, NV, S, T, LW>(buf + (xl + 2) * SSW, lown + (xl + 1) * 4 * LW, v, acc);
+    lds_hop<0, CB, true, NV, S, T, LW>(buf + xl * SSW, lown + xl * 4 * LW, v, acc);
     if constexpr (!FIRST) reconstruct_add<3, CB, T>(acc, carry);
     const W* self = buf + (xl + 1) * SSW;
     cpx<T> p[4][3];
@@ -510,11 +514,7 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
     cpx<T> h[2][3];
     project<3, CB, T>(p, h);
     cpx<T> u[3][3];
-    const W* lt = lown + (xl + 1) * 36 + 27;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(lt + a * 3 + b);
+    load_link_lw<LW, S, T>(lown + (xl + 1) * 4 * LW + 3 * LW, u);
     su3_mul2<true, T>(u, h, carry);
   }
   __syncthreads();
@@ -539,18 +539,18 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
   __syncthreads();
 }
 
-template <int DEPTH, bool ADJ, int NV, class S, class T>
+template <int DEPTH, bool ADJ, int NV, class S, class T, int LW>
 __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
   using W = typename S::word;
-  constexpr int CH = RowPieces<S>::CH, LK = LinkK<S, NV>::value;
+  constexpr int CH = RowPieces<S>::CH, LK = LinkK<S, NV, LW>::value;
   constexpr int SSW = SiteStride<NV, S>::WORDS;
   extern __shared__ uint4 smem_march[];
   const int R = int(m.sb);
   W* buf = reinterpret_cast<W*>(smem_march);
   W* lown = buf + (R + 2) * SSW;
-  W* lnb = lown + (R + 1) * 36;
+  W* lnb = lown + (R + 1) * 4 * LW;
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const uint32_t seg = m.d_rows.div(L);
@@ -566,40 +566,40 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
   u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
   using Q0 = MarchSeq<true>;
-#define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+#define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
   DSL_PISSUE(0);
   if constexpr (DEPTH > 1) DSL_PISSUE(1);
   if constexpr (DEPTH > 2) DSL_PISSUE(2);
   if constexpr (DEPTH > 3) DSL_PISSUE(3);
   if constexpr (DEPTH > 4) DSL_PISSUE(4);
 #undef DSL_PISSUE
-  links_issue<S, LK>(c, U, xm, tid, nth, lr);
-  march_step<true, DEPTH, ADJ, NV, S, T>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
+  links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
+  march_step<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
                                          r0, r1, r2, r3, r4, r5, r6, lr, carry);
 #pragma nounroll
   for (int k = 1; k < steps; ++k) {
     c.t += 1;
     c.row_base += uint32_t(g.stride[3]);
-    march_step<false, DEPTH, ADJ, NV, S, T>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
+    march_step<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
                                             diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
   }
 }
 
-template <int DEPTH, int NV, class S, class T>
+template <int DEPTH, int NV, class S, class T, int LW = 9>
 static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, bool xcd, const void* U, const void* in,
                                  void* out, double mass, hipStream_t st) {
   using W = typename S::word;
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
-  size_t lds = rows_lds_words<NV, S>(R) * sizeof(W);
+  size_t lds = rows_lds_words<NV, S, LW>(R) * sizeof(W);
   if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
   if (adj)
-    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, true, NV, S, T>), grid, block, lds, st, g, m, int(xcd),
+    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, true, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
                        (const W*)U, (const W*)in, (W*)out, diag);
   else
-    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, false, NV, S, T>), grid, block, lds, st, g, m, int(xcd),
+    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, false, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
                        (const W*)U, (const W*)in, (W*)out, diag);
   return hipGetLastError();
 }
@@ -802,7 +802,7 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
 // Returns hipErrorNotSupported when the configuration is not covered (the
 // caller then uses the direct-load kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st, const void* clover) {
+                              double mass, hipStream_t st, const void* clover, bool compressed) {
   if (const char* e = getenv("DSLASH_ROWS"))
     if (atoi(e) == 0) return hipErrorNotSupported;
   if (g.nv != 12) return hipErrorNotSupported;
@@ -824,16 +824,24 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   int tsteps = 8;
   if (const char* e = getenv("DSLASH_TSTEPS")) tsteps = atoi(e);
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
-  // the clover term is fused into the one-row-per-workgroup kernel only
+  // the clover term is fused into the one-row-per-workgroup kernel only;
+  // compressed links are read by the t-marching kernel only
+  if (compressed && (tsteps <= 0 || clover)) return hipErrorNotSupported;
   if (tsteps > 0 && !clover) {
     const int depth = depth_env ? atoi(depth_env) : 2;
-#define DSL_MT(D)                                                                                       \
-  switch (dtype) {                                                                                      \
-    case DT_C64: return wilson_march_t<D, 12, C64, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
-    case DT_BF16: return wilson_march_t<D, 12, BF16, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st); \
-    case DT_F16: return wilson_march_t<D, 12, F16, float>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
+#define DSL_MT(D, LW)                                                                                          \
+  switch (dtype) {                                                                                             \
+    case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
+    case DT_BF16: return wilson_march_t<D, 12, BF16, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st); \
+    case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
   }
-    if (depth <= 2) { DSL_MT(2) } else { DSL_MT(3) }
+    if (compressed) {
+      DSL_MT(2, 6)
+    } else if (depth <= 2) {
+      DSL_MT(2, 9)
+    } else {
+      DSL_MT(3, 9)
+    }
 #undef DSL_MT
     return hipErrorNotSupported;
   }

@@ -69,6 +69,40 @@ hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- gauge compression
+// Vc[l][a][b] = V[l][a][b] for rows a = 0, 1 of every 3x3 link l (6 of its 9
+// words); the third row is completed from them where the links are read.
+template <class W>
+__global__ void __launch_bounds__(256) compress_links_kernel(const W* __restrict__ src, W* __restrict__ dst,
+                                                             size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const size_t l = i / 6, e = i - l * 6;
+    dst[i] = src[l * 9 + e];
+  }
+}
+
+hipError_t launch_compress_links(int dtype, size_t links, const void* V, void* Vc, hipStream_t st) {
+  const size_t n = links * 6;
+  if (n == 0) return hipSuccess;
+  switch (dtype) {
+    case DT_C64:
+      hipLaunchKernelGGL((compress_links_kernel<C64::word>), stream_grid(n), dim3(256), 0, st,
+                         (const C64::word*)V, (C64::word*)Vc, n);
+      break;
+    case DT_C128:
+      hipLaunchKernelGGL((compress_links_kernel<C128::word>), stream_grid(n), dim3(256), 0, st,
+                         (const C128::word*)V, (C128::word*)Vc, n);
+      break;
+    case DT_BF16:
+    case DT_F16:
+      hipLaunchKernelGGL((compress_links_kernel<uint32_t>), stream_grid(n), dim3(256), 0, st, (const uint32_t*)V,
+                         (uint32_t*)Vc, n);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- reductions
 // Block (vc, ry): lane x = column, y = row within the block's stride.
 struct ColShape {

@@ -78,10 +78,11 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 102; }
+int dslash_version(void) { return 103; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
-                        int Nv, double mass, int dtype, void* stream, const void* C = nullptr) {
+                        int Nv, double mass, int dtype, void* stream, const void* C = nullptr,
+                        bool compressed = false) {
   g_err[0] = 0;
   if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
   if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
@@ -89,12 +90,12 @@ static int apply_common(bool adj, int op, const void* U, const void* in, void* o
   const uint64_t vol = volume(dims);
   const size_t eb = dsl::dtype_bytes(dtype);
   const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * eb;
-  const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * eb;
+  const size_t nlink = size_t(vol) * dsl::links_per_site(op) * (compressed ? 6 : 9) * eb;
   if (overlap(in, nspin, out, nspin)) return fail(DSLASH_E_ALIAS, "in and out overlap");
   if (overlap(U, nlink, out, nspin)) return fail(DSLASH_E_ALIAS, "U and out overlap");
   if (C && overlap(C, size_t(vol) * 36 * eb, out, nspin)) return fail(DSLASH_E_ALIAS, "C and out overlap");
   const dsl::Geom g = dsl::make_geom(dims, Nv);
-  hipError_t e = dsl::launch_apply(op, adj, dtype, g, U, in, out, mass, (hipStream_t)stream, C);
+  hipError_t e = dsl::launch_apply(op, adj, dtype, g, U, in, out, mass, (hipStream_t)stream, C, compressed);
   if (e != hipSuccess) return hip_fail(e, "dslash_apply launch");
   return DSLASH_OK;
 }
@@ -130,6 +131,27 @@ int dslash_apply_clover(int op, const void* U, const void* C, const void* in, vo
     return fail(DSLASH_E_ARG, "the clover term belongs to WILSON and BRILLOUIN (got op %d)", op);
   if (!C) return fail(DSLASH_E_ARG, "C is NULL");
   return apply_common(adjoint != 0, op, U, in, out, dims, Nc, Nv, mass, dtype, stream, C);
+}
+
+int dslash_compress_links(const void* V, void* Vc, const int dims[4], int Nc, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_WILSON, dims, Nc, 1)) return rc;
+  if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
+  if (!V || !Vc) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  if (overlap(V, size_t(vol) * 36 * eb, Vc, size_t(vol) * 24 * eb)) return fail(DSLASH_E_ALIAS, "V and Vc overlap");
+  hipError_t e = dsl::launch_compress_links(dtype, size_t(vol) * 4, V, Vc, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_compress_links launch");
+  return DSLASH_OK;
+}
+
+int dslash_apply_compressed(int op, const void* Vc, const void* in, void* out, const int dims[4], int Nc, int Nv,
+                            double mass, int adjoint, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (op != DSLASH_STAGGERED && op != DSLASH_WILSON)
+    return fail(DSLASH_E_ARG, "compressed links are built for STAGGERED and WILSON (got op %d)", op);
+  return apply_common(adjoint != 0, op, Vc, in, out, dims, Nc, Nv, mass, dtype, stream, nullptr, true);
 }
 
 int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U, void* grad_in,

@@ -25,13 +25,15 @@ struct Shape {
 Shape site_v_shape(uint32_t vol, int nv);
 
 // clover: packed site-local clover term (36 words per site) added to D_W or
-// D_B, or nullptr; STAGGERED takes none.
+// D_B, or nullptr; STAGGERED takes none.  compressed: U holds the first two
+// rows of every link (6 words per link; STAGGERED and WILSON, not with clover).
 hipError_t launch_apply(int op, bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                        double mass, hipStream_t st, const void* clover = nullptr);
+                        double mass, hipStream_t st, const void* clover = nullptr, bool compressed = false);
 hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st, const void* clover = nullptr);
+                              double mass, hipStream_t st, const void* clover = nullptr, bool compressed = false);
 hipError_t launch_staggered_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                                 double mass, hipStream_t st);
+                                 double mass, hipStream_t st, bool compressed = false);
+hipError_t launch_compress_links(int dtype, size_t links, const void* V, void* Vc, hipStream_t st);
 hipError_t launch_brillouin_rows(bool adjoint, int dtype, const Geom& g, const void* W, const void* in, void* out,
                                  double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);

@@ -28,6 +28,31 @@ DSL_HD void load_link(const typename S::word* __restrict__ U, size_t base, cpx<T
     for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(U + base + a * 3 + b);
 }
 
+// Third row of an SU(3) matrix from its first two (unitarity and det u = 1):
+// u_2j = conj(u_0k u_1l - u_0l u_1k), (j, k, l) a cyclic permutation of (0, 1, 2).
+template <class T>
+DSL_HD void complete_su3(cpx<T> (&u)[3][3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int k = (j + 1) % 3, l = (j + 2) % 3;
+    cpx<T> z = cmadd(zero<T>(), u[0][k], u[1][l]);
+    z = cmadd(z, -u[0][l], u[1][k]);
+    u[2][j] = conj(z);
+  }
+}
+
+// A link of LW storage words at p: 9 (the full matrix) or 6 (gauge
+// compression: its first two rows, the third completed as above).
+template <int LW, class S, class T>
+DSL_HD void load_link_lw(const typename S::word* p, cpx<T> (&u)[3][3]) {
+  static_assert(LW == 9 || LW == 6, "a link is stored in 9 or 6 words");
+#pragma unroll
+  for (int a = 0; a < LW / 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(p + a * 3 + b);
+  if constexpr (LW == 6) complete_su3(u);
+}
+
 template <class S, class T>
 DSL_HD void load_wspinor(const typename S::word* __restrict__ in, size_t base, int nv, cpx<T> (&p)[4][3]) {
 #pragma unroll
@@ -150,7 +175,7 @@ DSL_HD void su3_mul2(const cpx<T> (&u)[3][3], const cpx<T> (&h)[2][3], cpx<T> (&
 }
 
 // One Wilson hop: acc += (1 + c gamma_mu) U' psi(n), U' = U or U^dag.
-template <int MU, int C, bool DAG, class S, class T>
+template <int MU, int C, bool DAG, class S, class T, int LW = 9>
 DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S::word* __restrict__ in,
                        size_t link_base, size_t spin_base, int nv, cpx<T> (&acc)[4][3]) {
   cpx<T> p[4][3];
@@ -158,7 +183,7 @@ DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S:
   cpx<T> h[2][3];
   project<MU, C, T>(p, h);
   cpx<T> u[3][3];
-  load_link<S, T>(U, link_base, u);
+  load_link_lw<LW, S, T>(U + link_base, u);
   cpx<T> t[2][3];
   su3_mul2<DAG, T>(u, h, t);
   reconstruct_add<MU, C, T>(acc, t);
@@ -167,8 +192,9 @@ DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S:
 // D_W at c_SW = 0 (eq. def_wils) in hop form:
 //   out(x) = (4 + m0) in(x) - 1/2 sum_mu [(1 - gamma_mu) V_mu(x) in(x+mu)
 //                                       + (1 + gamma_mu) V_mu(x-mu)^dag in(x-mu)]
-// ADJ: gamma_5 D_W gamma_5, i.e. gamma_mu -> -gamma_mu.
-template <bool ADJ, class S, class T>
+// ADJ: gamma_5 D_W gamma_5, i.e. gamma_mu -> -gamma_mu.  LW: words per stored
+// link (9, or 6 for compressed links).
+template <bool ADJ, class S, class T, int LW = 9>
 DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                         const typename S::word* __restrict__ C, uint32_t s, const SiteNbr& nb, int v, T diag) {
@@ -186,21 +212,21 @@ DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
   const uint32_t sf1 = s + nb.fwd[1], sb1 = s + nb.bwd[1];
   const uint32_t sf2 = s + nb.fwd[2], sb2 = s + nb.bwd[2];
   const uint32_t sf3 = s + nb.fwd[3], sb3 = s + nb.bwd[3];
-  wilson_hop<0, CF, false, S, T>(U, in, (size_t(s) * 4 + 0) * 9, sf0 * sps + v, nv, acc);
-  wilson_hop<0, CB, true, S, T>(U, in, (size_t(sb0) * 4 + 0) * 9, sb0 * sps + v, nv, acc);
-  wilson_hop<1, CF, false, S, T>(U, in, (size_t(s) * 4 + 1) * 9, sf1 * sps + v, nv, acc);
-  wilson_hop<1, CB, true, S, T>(U, in, (size_t(sb1) * 4 + 1) * 9, sb1 * sps + v, nv, acc);
-  wilson_hop<2, CF, false, S, T>(U, in, (size_t(s) * 4 + 2) * 9, sf2 * sps + v, nv, acc);
-  wilson_hop<2, CB, true, S, T>(U, in, (size_t(sb2) * 4 + 2) * 9, sb2 * sps + v, nv, acc);
-  wilson_hop<3, CF, false, S, T>(U, in, (size_t(s) * 4 + 3) * 9, sf3 * sps + v, nv, acc);
-  wilson_hop<3, CB, true, S, T>(U, in, (size_t(sb3) * 4 + 3) * 9, sb3 * sps + v, nv, acc);
+  wilson_hop<0, CF, false, S, T, LW>(U, in, (size_t(s) * 4 + 0) * LW, sf0 * sps + v, nv, acc);
+  wilson_hop<0, CB, true, S, T, LW>(U, in, (size_t(sb0) * 4 + 0) * LW, sb0 * sps + v, nv, acc);
+  wilson_hop<1, CF, false, S, T, LW>(U, in, (size_t(s) * 4 + 1) * LW, sf1 * sps + v, nv, acc);
+  wilson_hop<1, CB, true, S, T, LW>(U, in, (size_t(sb1) * 4 + 1) * LW, sb1 * sps + v, nv, acc);
+  wilson_hop<2, CF, false, S, T, LW>(U, in, (size_t(s) * 4 + 2) * LW, sf2 * sps + v, nv, acc);
+  wilson_hop<2, CB, true, S, T, LW>(U, in, (size_t(sb2) * 4 + 2) * LW, sb2 * sps + v, nv, acc);
+  wilson_hop<3, CF, false, S, T, LW>(U, in, (size_t(s) * 4 + 3) * LW, sf3 * sps + v, nv, acc);
+  wilson_hop<3, CB, true, S, T, LW>(U, in, (size_t(sb3) * 4 + 3) * LW, sb3 * sps + v, nv, acc);
 
   site_finish<S, T>(in, out, C, s, size_t(s) * sps + v, nv, diag, T(-0.5), acc);
 }
 
 // D_S (Sec. 3): out(x) = m in(x) + sum_mu eta_mu(x)/2 [V_mu(x) in(x+mu) - V_mu(x-mu)^dag in(x-mu)],
 // eta_1 = 1, eta_2 = (-1)^x, eta_3 = (-1)^(x+y), eta_4 = (-1)^(x+y+z).  ADJ negates the hop term.
-template <bool ADJ, class S, class T>
+template <bool ADJ, class S, class T, int LW = 9>
 DSL_HD void staggered_site(const Geom& g, const typename S::word* __restrict__ U,
                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                            uint32_t s, const SiteNbr& nb, int v, T mass) {
@@ -214,8 +240,8 @@ DSL_HD void staggered_site(const Geom& g, const typename S::word* __restrict__ U
     par += nb.c[mu];
     const uint32_t sf = s + nb.fwd[mu], sb = s + nb.bwd[mu];
     cpx<T> u[3][3], ub[3][3], pf[3], pb[3];
-    load_link<S, T>(U, (size_t(s) * 4 + mu) * 9, u);
-    load_link<S, T>(U, (size_t(sb) * 4 + mu) * 9, ub);
+    load_link_lw<LW, S, T>(U + (size_t(s) * 4 + mu) * LW, u);
+    load_link_lw<LW, S, T>(U + (size_t(sb) * 4 + mu) * LW, ub);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       pf[c] = S::template load<T>(in + size_t(sf) * sps + size_t(c) * nv + v);

@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
     "backward", "brillouin_links", "convert", "solve", "dslash", "op_code", "clover_field", "eo_pack", "eo_unpack",
-    "eo_hop",
+    "eo_hop", "compress_links", "apply_compressed",
 ]
 
 STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
@@ -60,11 +60,14 @@ def _load():
                                     ctypes.POINTER(ctypes.c_double), ip, vp]
     lib.dslash_clover_field.argtypes = [vp, vp, ip, i, d, i, vp]
     lib.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
+    lib.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
+    lib.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
                  "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
-                 "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover"):
+                 "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
+                 "dslash_compress_links", "dslash_apply_compressed"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -179,6 +182,44 @@ def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bo
     fn = _lib.dslash_apply_adjoint if adjoint else _lib.dslash_apply
     _check(fn(op, _ptr(U), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass), _dtype_code(psi),
               _stream(psi)), "dslash_apply")
+    return out
+
+
+def compress_links(V: torch.Tensor) -> torch.Tensor:
+    """First two rows of every SU(3) link: [Nt,Nz,Ny,Nx,4,2,3] (gauge compression)."""
+    _require(V, "V")
+    vs = _core_shape(V)
+    if len(vs) != 7 or vs[4:] != (4, 3, 3):
+        raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
+    pair = _dtype_code(V) in (BF16, F16)
+    Vc = torch.empty(vs[:4] + (4, 2, 3) + ((2,) if pair else ()), dtype=V.dtype, device=V.device)
+    _check(_lib.dslash_compress_links(_ptr(V), _ptr(Vc), _dims_c(vs), 3, _dtype_code(V), _stream(V)),
+           "dslash_compress_links")
+    return Vc
+
+
+def apply_compressed(op, Vc: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """out = D psi (or D^dag psi) for D_S or D_W with compressed links from ``compress_links``."""
+    op = op_code(op)
+    _require(Vc, "Vc")
+    _require(psi, "psi")
+    if _dtype_code(Vc) != _dtype_code(psi):
+        raise ValueError("Vc and psi must have the same storage dtype")
+    vs, ps = _core_shape(Vc), _core_shape(psi)
+    if len(vs) != 7 or vs[4:] != (4, 2, 3):
+        raise ValueError(f"Vc must have shape [Nt,Nz,Ny,Nx,4,2,3], got {vs}")
+    nv = ps[-1]
+    if op == BRILLOUIN or ps != _spinor_shape(op, vs[:4], nv):
+        raise ValueError(f"psi shape {ps} does not match Vc {vs} for this operator")
+    if out is None:
+        out = torch.empty_like(psi)
+    else:
+        _require(out, "out")
+        if out.shape != psi.shape or out.dtype != psi.dtype:
+            raise ValueError("out must match psi in shape and dtype")
+    _check(_lib.dslash_apply_compressed(op, _ptr(Vc), _ptr(psi), _ptr(out), _dims_c(vs), 3, nv, float(mass),
+                                        int(bool(adjoint)), _dtype_code(psi), _stream(psi)), "dslash_apply_compressed")
     return out
 
 

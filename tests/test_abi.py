@@ -37,6 +37,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_double), ip, vp]
     l.dslash_clover_field.argtypes = [vp, vp, ip, i, d, i, vp]
     l.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
+    l.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
+    l.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     return l
 
 
@@ -47,10 +49,10 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 17
+    assert len(declared) == 19
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 102
+    assert lib.dslash_version() == 103
 
 
 def test_status_strings(lib):
@@ -160,3 +162,15 @@ def test_clover_validation(lib):
     assert lib.dslash_apply_clover(1, A, None, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # no C
     assert lib.dslash_apply_clover(1, A, B, C, C, dims, 3, 2, 0.1, 0, 0, None) == 3  # in == out
     assert lib.dslash_apply_clover(1, A, B, C, B, dims, 3, 2, 0.1, 0, 0, None) == 3  # out == C
+
+
+def test_compressed_validation(lib):
+    dims = _dims(4, 4, 4, 4)
+    D = 0x20000000
+    assert lib.dslash_compress_links(None, B, dims, 3, 0, None) == 1            # NULL V
+    assert lib.dslash_compress_links(A, A, dims, 3, 0, None) == 3               # V == Vc
+    assert lib.dslash_compress_links(A, B, dims, 2, 0, None) == 2               # Nc != 3
+    assert lib.dslash_apply_compressed(2, A, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # brillouin
+    assert lib.dslash_apply_compressed(1, A, C, C, dims, 3, 2, 0.1, 0, 0, None) == 3  # in == out
+    assert lib.dslash_apply_compressed(1, None, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # NULL Vc
+    assert lib.dslash_apply_compressed(0, A, C, D, _dims(4, 3, 4, 4), 3, 2, 0.0, 0, 0, None) == 1  # odd, staggered
