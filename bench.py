@@ -12,7 +12,8 @@ well above the 256 MB Infinity Cache.
 
 Further rows (``rows`` in the JSON line), each timed the same way:
 D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
-BF16 storage, D_W and D_B with the clover term (c_SW = 1), link gradients at
+BF16 storage, D_W and D_B with the clover term (c_SW = 1), D_W and D_S with
+compressed links (two stored rows per link) against full links, link gradients at
 24^3 x 48, and the mixed-precision solve at 32^3 x 64 (time to
 ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16 inner storage, on the
 full lattice and on the even-odd Schur complement).
@@ -44,9 +45,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def site_bytes(op: str, nv: int, eb: int) -> int:
-    """Compulsory bytes per site: links read once, input read once, output written once."""
-    links = {"staggered": 36, "wilson": 36, "brillouin": 360}[op]
+def site_bytes(op: str, nv: int, eb: int, compressed: bool = False) -> int:
+    """Compulsory bytes per site: links read once, input read once, output written once
+    (compressed links: two of the three rows of each)."""
+    links = {"staggered": 36, "wilson": 36, "brillouin": 360}[op] * (2 if compressed else 3) // 3
     comps = 3 if op == "staggered" else 12
     return eb * (links + 2 * comps * nv)
 
@@ -99,19 +101,22 @@ def rotated_sets(torch, U, P, count: int, C=None):
     return sets
 
 
-def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label, clover=None):
+def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label, clover=None, compressed=False):
     sets = rotated_sets(torch, U, P, rotate, clover)
     outs = [torch.empty_like(P) for _ in sets]
 
     def launch(i):
         u, p, c = sets[i % len(sets)]
-        D.apply(op, u, p, mass, out=outs[i % len(sets)], clover=c)
+        if compressed:
+            D.apply_compressed(op, u, p, mass, out=outs[i % len(sets)])
+        else:
+            D.apply(op, u, p, mass, out=outs[i % len(sets)], clover=c)
     t = timed(torch, launch, steps, warmup)
     nt, nz, ny, nx = P.shape[:4]
     vol = nt * nz * ny * nx
     nv = P.shape[-1] if P.dtype in (torch.complex64, torch.complex128) else P.shape[-2]
     flops = (FLOPS[op] + (CLOVER_FLOPS if clover is not None else 0)) * vol * nv
-    nbytes = (site_bytes(op, nv, dtype_bytes) + (36 * dtype_bytes if clover is not None else 0)) * vol
+    nbytes = (site_bytes(op, nv, dtype_bytes, compressed) + (36 * dtype_bytes if clover is not None else 0)) * vol
     row = {"us": t * 1e6, "gflops": flops / t / 1e9, "gbs": nbytes / t / 1e9,
            "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": flops,
            "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
@@ -210,7 +215,28 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     row, _ = bench_apply(torch, D, "wilson", U, P, 0.1, steps, warmup, 4, 8, "D_W + clover fp32", clover=C)
     row["c_sw"] = 1.0
     rows["wilson_clover_16^3x32_nv12_fp32"] = row
+    # the same D_W with compressed links (two stored rows per link)
+    rows["wilson_compressed_16^3x32_nv12_fp32"], _ = bench_apply(
+        torch, D, "wilson", D.compress_links(U), P, 0.1, steps, warmup, 4, 8, "D_W compressed fp32", compressed=True)
     del U, P, C
+    # link-dominated cases (N_v = 1) and D_S at N_v = 12, full and compressed links, 32^4
+    dims = (32, 32, 32, 32)
+    for op, gen, kind, seed in (("wilson", synthetic.wilson_spinor, "smooth", 1),
+                                ("staggered", synthetic.staggered_spinor, "haar", 0)):
+        U = up(synthetic.gauge_links(dims, kind, seed), np.complex64)
+        Uc = D.compress_links(U)
+        for nv in ((1, 12) if op == "staggered" else (1,)):
+            P = up(gen(dims, nv, 100), np.complex64)
+            mass = 0.1 if op == "wilson" else 0.0
+            r_full, _ = bench_apply(torch, D, op, U, P, mass, steps, warmup, 1, 8, f"{op} 32^4 nv{nv} fp32")
+            r_comp, _ = bench_apply(torch, D, op, Uc, P, mass, steps, warmup, 1, 8, f"{op} compressed 32^4 nv{nv}",
+                                    compressed=True)
+            r_comp["speedup_vs_full_links"] = r_full["us"] / r_comp["us"]
+            rows[f"{op}_32^4_nv{nv}_fp32"] = r_full
+            rows[f"{op}_compressed_32^4_nv{nv}_fp32"] = r_comp
+            del P
+        del U, Uc
+    torch.cuda.empty_cache()
     # link gradients at 24^3 x 48, N_v = 12
     dims = (24, 24, 24, 48)
     for op, kind, seed in (("staggered", "haar", 4), ("wilson", "smooth", 5)):
