@@ -23,14 +23,32 @@ depend on the links.
 
 L is affine in the real and imaginary part of every single link, so a central
 difference in one link component is exact for any step (``fd_link_grad``).
+
+Brillouin.  With the stored W taken as free matrices, W_d(x) (d stored) enters
+the hop term of d into out(x), factor S_d = -lambda_k/2 + rho_k d.gamma (the
+hop form of eqs. def_bril, def_der, def_lap), and, as W_{-d}(x + d) =
+W_d(x)^dag, the hop term of -d into out(x + d), factor S_{-d}:
+
+    G_{W_d}(x) = sum_v sum_s [ (S_d^dag chi(x))_s (x) conj(psi(x+d)_s)
+                             + psi(x)_s (x) conj((S_{-d}^dag chi(x+d))_s) ].
+
+Through the construction of W from V (Tab. 1) the chain rule runs over every
+path product M = A_1 ... A_k of every stored d: with P and Q the products
+before and after hop i, delta L = Re tr(G_M^dag P delta A_i Q) gives the
+gradient P^dag G_M Q^dag / k! for A_i, and its adjoint for the link V_mu(y)
+when the hop runs against it (A_i = V_mu(y)^dag).  L is then a polynomial of
+degree at most 4 along any line V + t Delta, so a five-point central
+difference is exact.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import staggered, wilson
+import itertools
+
+from . import brillouin, staggered, wilson
 from .gamma import GAMMA, IDENTITY, spin_mul
-from .lattice import dims_of, eta, shift
+from .lattice import dims_of, eta, shift, shift_by
 
 
 def loss(op: str, U: np.ndarray, chi: np.ndarray, psi: np.ndarray, mass: float = 0.0) -> float:
@@ -39,6 +57,8 @@ def loss(op: str, U: np.ndarray, chi: np.ndarray, psi: np.ndarray, mass: float =
         out = staggered.apply(U, psi, mass)
     elif op == "wilson":
         out = wilson.apply(U, psi, mass)
+    elif op == "brillouin":
+        out = brillouin.apply(U, psi, mass)
     else:
         raise ValueError(op)
     return float(np.real(np.vdot(chi, out)))
@@ -70,6 +90,68 @@ def link_grad_wilson(chi: np.ndarray, psi: np.ndarray) -> np.ndarray:
         t2 = np.einsum("...sav,...sbv->...ab", phi_b, np.conj(chi_f))
         G[..., mu, :, :] = t1 + t2
     return G
+
+
+def _dag(u: np.ndarray) -> np.ndarray:
+    return np.conj(np.swapaxes(u, -1, -2))
+
+
+def _spin_factor(d) -> np.ndarray:
+    k = brillouin.hops(d)
+    return -0.5 * brillouin.LAMBDA[k] * IDENTITY + brillouin.RHO[k] * sum(c * GAMMA[mu] for mu, c in enumerate(d))
+
+
+def link_grad_brillouin_W(chi: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """G [..][40][Nc][Nc] with respect to the stored W (free matrices); chi, psi [..][4][Nc][Nv]."""
+    nc = psi.shape[-2]
+    G = np.zeros(psi.shape[:4] + (40, nc, nc), dtype=np.complex128)
+    for j, d in enumerate(brillouin.STORED):
+        md = tuple(-c for c in d)
+        a_f = spin_mul(_dag(_spin_factor(d)), chi)
+        a_b = spin_mul(_dag(_spin_factor(md)), shift_by(chi, d))
+        t1 = np.einsum("...sav,...sbv->...ab", a_f, np.conj(shift_by(psi, d)))
+        t2 = np.einsum("...sav,...sbv->...ab", psi, np.conj(a_b))
+        G[..., j, :, :] = t1 + t2
+    return G
+
+
+def brillouin_links_backward(V: np.ndarray, G_W: np.ndarray) -> np.ndarray:
+    """Gradient with respect to V of Re sum conj(G_W) W[V] (the adjoint of the W construction)."""
+    nc = V.shape[-1]
+    G_V = np.zeros(V.shape, dtype=np.complex128)
+    eye = np.broadcast_to(np.eye(nc, dtype=np.complex128), V.shape[:4] + (nc, nc))
+    for j, d in enumerate(brillouin.STORED):
+        G = G_W[..., j, :, :]
+        steps = [(mu, c) for mu, c in enumerate(d) if c]
+        orders = list(itertools.permutations(steps))
+        for order in orders:
+            hops, offs = [], []
+            off = [0, 0, 0, 0]
+            for mu, sgn in order:
+                hops.append(shift_by(brillouin._hop_link(V, mu, sgn), off))
+                offs.append(tuple(off))
+                off[mu] += sgn
+            for i, (mu, sgn) in enumerate(order):
+                P, Q = eye, eye
+                for h in hops[:i]:
+                    P = P @ h
+                for h in hops[i + 1:]:
+                    Q = Q @ h
+                X = _dag(P) @ G @ _dag(Q) / len(orders)
+                if sgn > 0:
+                    # A_i(x) = V_mu(x + off_i): the gradient lands at y = x + off_i
+                    G_V[..., mu, :, :] += shift_by(X, tuple(-o for o in offs[i]))
+                else:
+                    # A_i(x) = V_mu(x + off_i - mu)^dag
+                    back = list(-o for o in offs[i])
+                    back[mu] += 1
+                    G_V[..., mu, :, :] += _dag(shift_by(X, tuple(back)))
+    return G_V
+
+
+def link_grad_brillouin(V: np.ndarray, chi: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """G [..][4][Nc][Nc] of L = Re<chi, D_B[W(V)] psi> with respect to the one-hop links V."""
+    return brillouin_links_backward(V, link_grad_brillouin_W(chi, psi))
 
 
 def link_grad(op: str, chi: np.ndarray, psi: np.ndarray) -> np.ndarray:
