@@ -136,6 +136,21 @@ int dslash_apply_clover(int op, const void* U, const void* C, const void* in, vo
                         int Nc, int Nv, double mass, int adjoint, int dtype, void* stream);
 
 /*
+ * Adjoint of dslash_brillouin_links (Tab. 1): grad_V = dR/dV for
+ * R = Re sum conj(grad_W) W[V], i.e. the chain rule through every path
+ * product of every stored W_d.  For a path product M = A_1 ... A_k in the
+ * mean over the k! hop orderings, hop i receives P^dag grad_W Q^dag / k!
+ * (P, Q the products before and after it), or the adjoint of that for a hop
+ * against the link (A_i = V_mu(y - mu)^dag).  Together with the BRILLOUIN
+ * branch of dslash_backward this is the link gradient of D_B with respect to
+ * V.  V: [..][4][3][3]; grad_W: [..][40][3][3]; grad_V: [..][4][3][3]
+ * (written, deterministic: no atomics).  C64 and C128 only.  grad_V must not
+ * overlap V or grad_W (E_ALIAS).  Asynchronous on `stream`.
+ */
+int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* grad_V, const int dims[4], int Nc,
+                                    int dtype, void* stream);
+
+/*
  * Gauge compression (Sec. 4 names storing N_c - 1 colour rows of V as a next
  * step; Sec. 5 notes that 36 of the 40 W are not special unitary, so it is
  * offered for V only).  An SU(3) link is fixed by its first two rows: the
@@ -168,9 +183,14 @@ int dslash_apply_compressed(int op, const void* Vc, const void* in, void* out, c
  * factors of the forward and backward hop: eta_mu(x)/2 and -eta_mu(x)/2 for
  * STAGGERED, -(1 - gamma_mu)/2 and -(1 + gamma_mu)/2 for WILSON.  This is the
  * link gradient of L = Re sum conj(grad_out) * (D in) with the links treated
- * as free complex matrices.  grad_U has the layout of V.  BRILLOUIN:
- * grad_U must be NULL (E_UNSUPPORTED otherwise).  Outputs may not alias
- * inputs (E_ALIAS).  Only C64 and C128 are accepted.
+ * as free complex matrices.  grad_U has the layout of V.  BRILLOUIN (U = the
+ * stored W, taken as free matrices): grad_U has the layout of W and
+ *   G_{W_d}(x) = sum_v sum_s [ (S_d g(x))_s (x) conj(in(x+d)_s)
+ *                            + in(x)_s (x) conj((S_{-d} g(x+d))_s) ]
+ * for every stored d, S_d = -lambda_k/2 + rho_k d.gamma the spin factor of the
+ * hop d (eqs. def_der, def_lap; W_d(x) also enters out(x+d) as W_{-d}(x+d)^dag).
+ * The gradient with respect to V follows from dslash_brillouin_links_backward.
+ * Outputs may not alias inputs (E_ALIAS).  Only C64 and C128 are accepted.
  */
 int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U,
                     void* grad_in, const int dims[4], int Nc, int Nv, double mass, int dtype,

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdslash.so")
 ARCH = "gfx950"
 
-SOURCES = ["apply.hip", "apply_rows.hip", "staggered_rows.hip", "brillouin_rows.hip", "grad_rows.hip", "links_grad.hip", "eo.hip", "clover.hip", "blas.hip", "capi.cpp", "solver.cpp"]
+SOURCES = ["apply.hip", "apply_rows.hip", "staggered_rows.hip", "brillouin_rows.hip", "grad_rows.hip", "links_grad.hip", "eo.hip", "clover.hip", "bri_grad.hip", "blas.hip", "capi.cpp", "solver.cpp"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,338 @@
+// Link gradients of the Brillouin operator.
+//
+// bri_wgrad_kernel: gradient of L = Re sum conj(chi) (D_B psi) with respect to
+// the 40 stored W, taken as free complex matrices.  W_d(x) (d stored) enters
+// the hop of d into out(x) with spin factor S_d = a_k + b_k d.gamma
+// (a_k = -lambda_k / 2, b_k = rho_k; eqs. def_der, def_lap) and, as
+// W_{-d}(x + d) = W_d(x)^dag (Tab. 1 caption), the hop of -d into out(x + d)
+// with S_{-d} = a_k - b_k d.gamma.  S_d is Hermitian, so
+//   G_{W_d}(x) = sum_v sum_s [ (S_d chi(x))_s (x) conj(psi(x+d)_s)
+//                            + psi(x)_s (x) conj((S_{-d} chi(x+d))_s) ].
+// One thread per (site, stored direction), the N_v right-hand sides in a loop.
+//
+// bri_links_backward_kernel: the adjoint of the construction of W from V
+// (Tab. 1).  W_d(x) is the mean over the k! hop orderings of the path product
+// M = A_1 ... A_k (A_i = V_mu(y) for a hop +mu from y, V_mu(y - mu)^dag for a
+// hop -mu); for the gradient G of a path product, hop i receives
+// P^dag G Q^dag with P, Q the products before and after it, or the adjoint of
+// that when the hop runs against the link.  One thread per link (y, mu) gathers
+// every (d, ordering, hop) that uses it, in a fixed order: the sum is
+// deterministic and needs no atomics.
+#include "launch.hpp"
+#include "stencils.hpp"
+
+namespace dsl {
+namespace {
+
+// out = (d.gamma) y in the chiral basis: d.gamma = [[0, S], [S^dag, 0]],
+// S = [[d4 - i d3, -d2 - i d1], [d2 - i d1, d4 + i d3]].
+template <class T>
+DSL_HD void dgamma(const int (&d)[4], const cpx<T> (&y)[4][3], cpx<T> (&out)[4][3]) {
+  const T d1 = T(d[0]), d2 = T(d[1]), d3 = T(d[2]), d4 = T(d[3]);
+  const cpx<T> s00 = mk(d4, -d3), s01 = mk(-d2, -d1), s10 = mk(d2, -d1), s11 = mk(d4, d3);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[0][c] = cmadd(cmadd(zero<T>(), s00, y[2][c]), s01, y[3][c]);
+    out[1][c] = cmadd(cmadd(zero<T>(), s10, y[2][c]), s11, y[3][c]);
+    // S^dag: rows (conj s00, conj s10), (conj s01, conj s11)
+    out[2][c] = cjmadd(cjmadd(zero<T>(), s00, y[0][c]), s10, y[1][c]);
+    out[3][c] = cjmadd(cjmadd(zero<T>(), s01, y[0][c]), s11, y[1][c]);
+  }
+}
+
+template <class T>
+DSL_HD void m3_mul(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cpx<T> z = zero<T>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) z = cmadd(z, a[i][k], b[k][j]);
+      r[i][j] = z;
+    }
+}
+
+// r = a^dag b
+template <class T>
+DSL_HD void m3_adj_mul(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cpx<T> z = zero<T>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) z = cjmadd(z, a[k][i], b[k][j]);
+      r[i][j] = z;
+    }
+}
+
+// r = a b^dag
+template <class T>
+DSL_HD void m3_mul_adj(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cpx<T> z = zero<T>();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) z = cmaddj(z, a[i][k], b[j][k]);
+      r[i][j] = z;
+    }
+}
+
+template <class T>
+DSL_HD void m3_identity(cpx<T> (&m)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m[i][j] = i == j ? mk(T(1), T(0)) : zero<T>();
+}
+
+DSL_HD uint32_t site_of(const Geom& g, const int (&p)[4]) {
+  return uint32_t(p[0] + g.stride[1] * p[1] + g.stride[2] * p[2] + g.stride[3] * p[3]);
+}
+
+DSL_HD int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+// Link of the hop sg * mu from pos (V_mu(pos), or V_mu(pos - mu)^dag); pos moves along.
+template <class S, class T>
+DSL_HD void walk_hop(const Geom& g, const typename S::word* __restrict__ V, int (&pos)[4], int mu, int sg,
+                     cpx<T> (&l)[3][3]) {
+  if (sg < 0) pos[mu] = wrap(pos[mu] - 1, g.n[mu]);
+  load_link<S, T>(V, (size_t(site_of(g, pos)) * 4 + mu) * 9, l);
+  if (sg < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) {
+        const cpx<T> x = l[a][b], y = l[b][a];
+        l[a][b] = conj(y);
+        l[b][a] = conj(x);
+      }
+  } else {
+    pos[mu] = wrap(pos[mu] + 1, g.n[mu]);
+  }
+}
+
+// Permutation `code` (0 .. 23, factorial number system) of {0, 1, 2, 3}.
+DSL_HD void decode_perm(int code, int (&perm)[4]) {
+  int avail[4] = {0, 1, 2, 3};
+  int rem = code;
+  const int fact[4] = {6, 2, 1, 1};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = rem / fact[i];
+    rem -= q * fact[i];
+    perm[i] = avail[q];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (t >= q) avail[t] = avail[t + 1];
+  }
+}
+
+}  // namespace
+
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_wgrad_kernel(Geom g, const typename S::word* __restrict__ chi,
+                                                       const typename S::word* __restrict__ psi,
+                                                       typename S::word* __restrict__ GW) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = int(blockIdx.y);  // stored slot, uniform over the block
+  if (s >= g.vol) return;
+  int d[4];
+  stored_direction(j, d);
+  const int k = (d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0);
+  const T a = T(-0.5) * bri_lambda<T>(k), b = bri_rho<T>(k);
+  const SiteNbr nb = site_nbr(g, s);
+  int q[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) q[mu] = wrap(q[mu] + d[mu], g.n[mu]);
+  const uint32_t sd = site_of(g, q);
+  const int nv = g.nv;
+  const size_t sps = size_t(12) * nv;
+
+  cpx<T> G[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) G[r][c] = zero<T>();
+#pragma unroll 1
+  for (int v = 0; v < nv; ++v) {
+    cpx<T> cx[4][3], cd[4][3], px[4][3], pd[4][3];
+    load_wspinor<S, T>(chi, size_t(s) * sps + v, nv, cx);
+    load_wspinor<S, T>(chi, size_t(sd) * sps + v, nv, cd);
+    load_wspinor<S, T>(psi, size_t(s) * sps + v, nv, px);
+    load_wspinor<S, T>(psi, size_t(sd) * sps + v, nv, pd);
+    // af = S_d chi(x) = a chi(x) + b (d.gamma) chi(x); ab = S_{-d} chi(x+d) = a chi(x+d) - b (d.gamma) chi(x+d)
+    cpx<T> af[4][3], ab[4][3];
+    dgamma<T>(d, cx, af);
+    dgamma<T>(d, cd, ab);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        af[sp][c] = rmadd(b * af[sp][c], a, cx[sp][c]);
+        ab[sp][c] = rmadd((-b) * ab[sp][c], a, cd[sp][c]);
+      }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          G[r][c] = cmaddj(G[r][c], af[sp][r], pd[sp][c]);
+          G[r][c] = cmaddj(G[r][c], px[sp][r], ab[sp][c]);
+        }
+  }
+  typename S::word* o = GW + (size_t(s) * 40 + j) * 9;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, G[r][c]);
+}
+
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_links_backward_kernel(Geom g, const typename S::word* __restrict__ V,
+                                                                const typename S::word* __restrict__ GW,
+                                                                typename S::word* __restrict__ GV) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = int(blockIdx.y);  // link direction, uniform over the block
+  if (y >= g.vol) return;
+  const SiteNbr nb = site_nbr(g, y);
+  cpx<T> acc[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = zero<T>();
+
+#pragma unroll 1
+  for (int j = 0; j < 40; ++j) {
+    int d[4];
+    stored_direction(j, d);
+    if (d[mu] == 0) continue;  // uniform: j and mu are the same for the whole wave
+    int axes[4], k = 0;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+      if (d[nu] != 0) axes[k++] = nu;
+    const int nperm = k == 1 ? 1 : (k == 2 ? 2 : (k == 3 ? 6 : 24));
+    const T inv = T(1) / T(nperm);
+    const int sg = d[mu];
+#pragma unroll 1
+    for (int code = 0; code < 24; ++code) {
+      int perm[4];
+      decode_perm(code, perm);
+      bool keep = true;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i >= k && perm[i] != i) keep = false;
+      if (!keep) continue;
+      // position of the mu hop in this ordering
+      int ih = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < k && axes[perm[i]] == mu) ih = i;
+      // the hop starts at y (forward) or at y + mu (backward); the path starts
+      // at x = start - (hops before it)
+      int x[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+      if (sg < 0) x[mu] = wrap(x[mu] + 1, g.n[mu]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < ih) {
+          const int nu = axes[perm[i]];
+          x[nu] = wrap(x[nu] - d[nu], g.n[nu]);
+        }
+      const uint32_t xs = site_of(g, x);
+      // P = product of the hops before ih, walked from x
+      int pos[4] = {x[0], x[1], x[2], x[3]};
+      cpx<T> P[3][3], L[3][3], Tm[3][3];
+      m3_identity(P);
+#pragma unroll 1
+      for (int i = 0; i < ih; ++i) {
+        const int nu = axes[perm[i]];
+        walk_hop<S, T>(g, V, pos, nu, d[nu], L);
+        m3_mul(P, L, Tm);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) P[r][c] = Tm[r][c];
+      }
+      // step over the mu hop itself
+      pos[mu] = wrap(pos[mu] + sg, g.n[mu]);
+      // Q = product of the hops after ih
+      cpx<T> Q[3][3];
+      m3_identity(Q);
+#pragma unroll 1
+      for (int i = ih + 1; i < k; ++i) {
+        const int nu = axes[perm[i]];
+        walk_hop<S, T>(g, V, pos, nu, d[nu], L);
+        m3_mul(Q, L, Tm);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Q[r][c] = Tm[r][c];
+      }
+      // X = P^dag G Q^dag
+      cpx<T> Gm[3][3];
+      load_link<S, T>(GW, (size_t(xs) * 40 + j) * 9, Gm);
+      m3_adj_mul(P, Gm, Tm);
+      m3_mul_adj(Tm, Q, L);
+      if (sg > 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][c] = rmadd(acc[r][c], inv, L[r][c]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][c] = rmadd(acc[r][c], inv, conj(L[c][r]));
+      }
+    }
+  }
+  typename S::word* o = GV + (size_t(y) * 4 + mu) * 9;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
+}
+
+namespace {
+
+template <class S, class T>
+hipError_t wgrad_t(const Geom& g, const void* chi, const void* psi, void* GW, hipStream_t st) {
+  using W = typename S::word;
+  const dim3 block(128), grid((g.vol + 127) / 128, 40);
+  hipLaunchKernelGGL((bri_wgrad_kernel<S, T>), grid, block, 0, st, g, (const W*)chi, (const W*)psi, (W*)GW);
+  return hipGetLastError();
+}
+
+template <class S, class T>
+hipError_t links_backward_t(const Geom& g, const void* V, const void* GW, void* GV, hipStream_t st) {
+  using W = typename S::word;
+  const dim3 block(128), grid((g.vol + 127) / 128, 4);
+  hipLaunchKernelGGL((bri_links_backward_kernel<S, T>), grid, block, 0, st, g, (const W*)V, (const W*)GW, (W*)GV);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
+                                  hipStream_t st) {
+  switch (dtype) {
+    case DT_C64: return wgrad_t<C64, float>(g, chi, psi, GW, st);
+    case DT_C128: return wgrad_t<C128, double>(g, chi, psi, GW, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* GW, void* GV,
+                                           hipStream_t st) {
+  switch (dtype) {
+    case DT_C64: return links_backward_t<C64, float>(g, V, GW, GV, st);
+    case DT_C128: return links_backward_t<C128, double>(g, V, GW, GV, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dsl

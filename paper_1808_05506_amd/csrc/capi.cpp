@@ -78,7 +78,7 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 103; }
+int dslash_version(void) { return 104; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
                         int Nv, double mass, int dtype, void* stream, const void* C = nullptr,
@@ -163,8 +163,6 @@ int dslash_backward(int op, const void* U, const void* grad_out, const void* in,
   if (!grad_out) return fail(DSLASH_E_ARG, "grad_out is NULL");
   if (grad_in && !U) return fail(DSLASH_E_ARG, "U is NULL but grad_in requested");
   if (grad_U && !in) return fail(DSLASH_E_ARG, "in is NULL but grad_U requested");
-  if (grad_U && op == DSLASH_BRILLOUIN)
-    return fail(DSLASH_E_UNSUPPORTED, "link gradient of the Brillouin operator is not built");
   const uint64_t vol = volume(dims);
   const size_t eb = dsl::dtype_bytes(dtype);
   const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * eb;
@@ -186,9 +184,28 @@ int dslash_backward(int op, const void* U, const void* grad_out, const void* in,
     if (e != hipSuccess) return hip_fail(e, "dslash_backward grad_in launch");
   }
   if (grad_U) {
-    hipError_t e = dsl::launch_link_grad(op, dtype, g, grad_out, in, grad_U, st);
+    hipError_t e = op == DSLASH_BRILLOUIN ? dsl::launch_brillouin_wgrad(dtype, g, grad_out, in, grad_U, st)
+                                          : dsl::launch_link_grad(op, dtype, g, grad_out, in, grad_U, st);
     if (e != hipSuccess) return hip_fail(e, "dslash_backward grad_U launch");
   }
+  return DSLASH_OK;
+}
+
+int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* grad_V, const int dims[4], int Nc,
+                                    int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return rc;
+  if (dtype != DSLASH_C64 && dtype != DSLASH_C128)
+    return fail(DSLASH_E_UNSUPPORTED, "W construction is built for C64 and C128 only (got dtype %d)", dtype);
+  if (!V || !grad_W || !grad_V) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t nv = size_t(vol) * 36 * eb, nw = size_t(vol) * 360 * eb;
+  if (overlap(grad_V, nv, V, nv) || overlap(grad_V, nv, grad_W, nw))
+    return fail(DSLASH_E_ALIAS, "grad_V overlaps an input");
+  const dsl::Geom g = dsl::make_geom(dims, 1);
+  hipError_t e = dsl::launch_brillouin_links_backward(dtype, g, V, grad_W, grad_V, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_brillouin_links_backward launch");
   return DSLASH_OK;
 }
 

@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
     "backward", "brillouin_links", "convert", "solve", "dslash", "op_code", "clover_field", "eo_pack", "eo_unpack",
-    "eo_hop", "compress_links", "apply_compressed",
+    "eo_hop", "compress_links", "apply_compressed", "brillouin_links_backward", "brillouin_links_autograd",
 ]
 
 STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
@@ -62,12 +62,13 @@ def _load():
     lib.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     lib.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
+    lib.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
                  "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
                  "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
-                 "dslash_compress_links", "dslash_apply_compressed"):
+                 "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -268,6 +269,38 @@ def brillouin_links(V: torch.Tensor) -> torch.Tensor:
     return W
 
 
+def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor) -> torch.Tensor:
+    """Gradient with respect to V of Re sum conj(grad_W) W[V] (adjoint of ``brillouin_links``)."""
+    _require(V, "V")
+    _require(grad_W, "grad_W")
+    vs = _core_shape(V)
+    if len(vs) != 7 or vs[4:] != (4, 3, 3):
+        raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
+    if tuple(grad_W.shape) != vs[:4] + (40, 3, 3) or grad_W.dtype != V.dtype:
+        raise ValueError("grad_W must be [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
+    gV = torch.empty_like(V)
+    _check(_lib.dslash_brillouin_links_backward(_ptr(V), _ptr(grad_W), _ptr(gV), _dims_c(vs), 3, _dtype_code(V),
+                                                _stream(V)), "dslash_brillouin_links_backward")
+    return gV
+
+
+class _BrillouinLinksFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V):
+        ctx.save_for_backward(V)
+        return brillouin_links(V)
+
+    @staticmethod
+    def backward(ctx, g):
+        (V,) = ctx.saved_tensors
+        return brillouin_links_backward(V, g.contiguous())
+
+
+def brillouin_links_autograd(V: torch.Tensor) -> torch.Tensor:
+    """Autograd-aware ``brillouin_links`` (complex64 / complex128)."""
+    return _BrillouinLinksFn.apply(V)
+
+
 _TORCH_OF = {C64: (torch.complex64, False), C128: (torch.complex128, False),
              BF16: (torch.bfloat16, True), F16: (torch.float16, True)}
 _NAMES = {"c64": C64, "c128": C128, "bf16": BF16, "f16": F16}
@@ -413,5 +446,6 @@ class _DslashFn(torch.autograd.Function):
 
 
 def dslash(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False) -> torch.Tensor:
-    """Autograd-aware D psi (complex64 / complex128; links: staggered and Wilson)."""
+    """Autograd-aware D psi (complex64 / complex128).  BRILLOUIN: U is the stored W;
+    combine with ``brillouin_links_autograd`` for the gradient with respect to V."""
     return _DslashFn.apply(op_code(op), U, psi, float(mass), bool(adjoint))

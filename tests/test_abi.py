@@ -39,6 +39,7 @@ def lib():
     l.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     l.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     l.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
+    l.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
     return l
 
 
@@ -49,10 +50,10 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 19
+    assert len(declared) == 20
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 103
+    assert lib.dslash_version() == 104
 
 
 def test_status_strings(lib):
@@ -87,7 +88,7 @@ def test_backward_validation(lib):
     d = _dims(4, 4, 4, 4)
     assert lib.dslash_backward(1, A, None, B, C, 0, d, 3, 2, 0.1, 0, None) == 1       # NULL grad_out
     assert lib.dslash_backward(1, A, B, C, 0x9000000, 0, d, 3, 2, 0.1, 2, None) == 2  # bf16 backward
-    assert lib.dslash_backward(2, A, B, C, 0x9000000, 0, d, 3, 2, 0.1, 0, None) == 2  # Brillouin grad_U
+    assert lib.dslash_backward(2, A, B, C, C + 0x100, 0, d, 3, 2, 0.1, 0, None) == 3  # Brillouin grad_U overlaps in
     assert lib.dslash_backward(1, A, B, C, None, B, d, 3, 2, 0.1, 0, None) == 3       # grad_in == grad_out
     assert lib.dslash_backward(1, A, B, C, C, None, d, 3, 2, 0.1, 0, None) == 3       # grad_U == in
 
@@ -174,3 +175,12 @@ def test_compressed_validation(lib):
     assert lib.dslash_apply_compressed(1, A, C, C, dims, 3, 2, 0.1, 0, 0, None) == 3  # in == out
     assert lib.dslash_apply_compressed(1, None, C, D, dims, 3, 2, 0.1, 0, 0, None) == 1  # NULL Vc
     assert lib.dslash_apply_compressed(0, A, C, D, _dims(4, 3, 4, 4), 3, 2, 0.0, 0, 0, None) == 1  # odd, staggered
+
+
+def test_brillouin_links_backward_validation(lib):
+    dims = _dims(4, 4, 4, 4)
+    assert lib.dslash_brillouin_links_backward(None, B, C, dims, 3, 0, None) == 1   # NULL V
+    assert lib.dslash_brillouin_links_backward(A, B, A, dims, 3, 0, None) == 3      # grad_V == V
+    assert lib.dslash_brillouin_links_backward(A, B, B, dims, 3, 0, None) == 3      # grad_V == grad_W
+    assert lib.dslash_brillouin_links_backward(A, B, C, dims, 3, 2, None) == 2      # BF16
+    assert lib.dslash_brillouin_links_backward(A, B, C, dims, 2, 0, None) == 2      # Nc != 3

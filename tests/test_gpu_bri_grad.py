@@ -1,0 +1,83 @@
+"""GPU parity of the Brillouin link gradients (with respect to the stored W,
+and through the W construction to V) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import brillouin, grad
+from tests.gpu_util import compare, down, say, up
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1808_05506_amd import dslash as D  # noqa: E402
+
+
+def _fields(dims, nv, seed):
+    v = synthetic.gauge_links(dims, "haar", seed)
+    chi = synthetic.wilson_spinor(dims, nv, seed + 1)
+    psi = synthetic.wilson_spinor(dims, nv, seed + 2)
+    return v, chi, psi
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("dims,nv", [((3, 3, 2, 3), 1), ((4, 3, 3, 4), 3), ((5, 2, 3, 3), 12)])
+def test_wgrad_matches_oracle(dt, dims, nv):
+    say(f"case brillouin W gradient {dims} nv={nv} {dt}")
+    v, chi, psi = _fields(dims, nv, 110)
+    w = brillouin.build(v)
+    W = up(w, dt)
+    gW, gi = D.backward("brillouin", W, up(chi, dt), up(psi, dt), 0.1)
+    ref = grad.link_grad_brillouin_W(down(up(chi, dt)), down(up(psi, dt)))
+    compare(down(gW), ref, dt, "G_W")
+    compare(down(gi), brillouin.apply(down(W), down(up(chi, dt)), 0.1, True), dt, "grad_in")
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("dims", [(3, 3, 2, 3), (4, 3, 3, 5)])
+def test_links_backward_matches_oracle(dt, dims):
+    say(f"case brillouin links backward {dims} {dt}")
+    v = synthetic.gauge_links(dims, "haar", 120)
+    gw = synthetic.gaussian(v.shape[:4] + (40, 3, 3), 121)
+    V, GW = up(v, dt), up(gw, dt)
+    gV = D.brillouin_links_backward(V, GW)
+    ref = grad.brillouin_links_backward(down(V), down(GW))
+    compare(down(gV), ref, dt, "G_V from G_W")
+
+
+def test_link_gradient_wrt_V_end_to_end():
+    dims, nv = (4, 3, 3, 3), 2
+    say("case brillouin link gradient end to end")
+    v, chi, psi = _fields(dims, nv, 130)
+    V = up(v, "c128").requires_grad_(True)
+    W = D.brillouin_links_autograd(V)
+    L = (up(chi, "c128").conj() * D.dslash("brillouin", W, up(psi, "c128"), 0.1)).real.sum()
+    L.backward()
+    compare(down(V.grad), grad.link_grad_brillouin(v, chi, psi), "c128", "autograd dL/dV")
+
+
+def test_gradcheck_through_links():
+    dims, nv = (3, 3, 2, 3), 1
+    say("case brillouin gradcheck")
+    v, _, psi = _fields(dims, nv, 140)
+    V = up(v, "c128").requires_grad_(True)
+    P = up(psi, "c128")
+    fn = lambda a: D.dslash("brillouin", D.brillouin_links_autograd(a), P, 0.2)  # noqa: E731
+    assert torch.autograd.gradcheck(fn, (V,), eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
+
+
+def test_brillouin_gradients_deterministic():
+    dims, nv = (6, 4, 4, 4), 12
+    say("case brillouin gradient determinism")
+    v, chi, psi = _fields(dims, nv, 150)
+    V = up(v, "c64")
+    W = D.brillouin_links(V)
+    a, _ = D.backward("brillouin", W, up(chi, "c64"), up(psi, "c64"), 0.1, need_grad_in=False)
+    b, _ = D.backward("brillouin", W, up(chi, "c64"), up(psi, "c64"), 0.1, need_grad_in=False)
+    assert torch.equal(a, b)
+    ga = D.brillouin_links_backward(V, a)
+    gb = D.brillouin_links_backward(V, a)
+    assert torch.equal(ga, gb)
