@@ -151,6 +151,17 @@ int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* gra
                                     int dtype, void* stream);
 
 /*
+ * out = D_B in (adjoint == 0) or D_B^dag in, with the off-axis links W_d(x)
+ * built from the one-hop links V inside the kernel for every hop (Tab. 1; the
+ * paper's variant without a precomputed W, Sec. 5): no W array is read or
+ * stored.  V: [..][4][3][3].  Built for N_v = 12, C64 storage and x-extents
+ * that give rows of at least 12 sites (the row-staged kernel);
+ * E_UNSUPPORTED otherwise.  Other arguments and errors as dslash_apply.
+ */
+int dslash_apply_brillouin_fly(const void* V, const void* in, void* out, const int dims[4], int Nc, int Nv,
+                               double mass, int adjoint, int dtype, void* stream);
+
+/*
  * Gauge compression (Sec. 4 names storing N_c - 1 colour rows of V as a next
  * step; Sec. 5 notes that 36 of the 40 W are not special unitary, so it is
  * offered for V only).  An SU(3) link is fixed by its first two rows: the

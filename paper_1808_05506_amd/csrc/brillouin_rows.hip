@@ -58,7 +58,7 @@ struct BriRowRegs {
   typename S::word w[BriStage<NV, S>::KW];
 };
 
-template <int NV, class S>
+template <bool FLY, int NV, class S>
 __device__ __forceinline__ void bri_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ Wl,
                                           const typename S::word* __restrict__ in, int r, int xm, int xp, int xl,
                                           int v, int tid, int nth, BriRowRegs<NV, S>& q) {
@@ -77,7 +77,9 @@ __device__ __forceinline__ void bri_issue(const Geom& g, const RowChunk& c, cons
     const int hs = h < St::SP ? xm : xp;
     q.halo[k] = reinterpret_cast<const u32x4*>(in + size_t(nb + hs) * St::SW)[h < St::SP ? h : h - St::SP];
   }
-  // link columns dx = -1, 0, 1: 9 words per site of the chunk
+  // link columns dx = -1, 0, 1: 9 words per site of the chunk (built from V
+  // in LDS instead when FLY)
+  if constexpr (FLY) return;
   const int nw = 27 * c.n;
 #pragma unroll
   for (int k = 0; k < St::KW; ++k) {
@@ -99,7 +101,7 @@ __device__ __forceinline__ void bri_issue(const Geom& g, const RowChunk& c, cons
   }
 }
 
-template <int NV, class S>
+template <bool FLY, int NV, class S>
 __device__ __forceinline__ void bri_commit(const RowChunk& c, const BriRowRegs<NV, S>& q, typename S::word* buf,
                                            typename S::word* wbuf, int R, int xl, int v, int tid, int nth) {
   using St = BriStage<NV, S>;
@@ -115,6 +117,7 @@ __device__ __forceinline__ void bri_commit(const RowChunk& c, const BriRowRegs<N
     u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < St::SP ? 0 : (c.n + 1) * SSP);
     hdst[h < St::SP ? h : h - St::SP] = q.halo[k];
   }
+  if constexpr (FLY) return;
   const int nw = 27 * c.n;
 #pragma unroll
   for (int k = 0; k < St::KW; ++k) {
@@ -189,9 +192,33 @@ __device__ __forceinline__ void bri_hop(const typename S::word* site, const type
     for (int cc = 0; cc < 3; ++cc) hold(acc[q][cc]);
 }
 
+// On-the-fly links: W_d(x) for the three hops (dx = -1, 0, 1; dy, dz, dt) of
+// row r and the chunk's sites, built from V (Tab. 1) straight into the link
+// columns, one (column, site) pair per thread.  Every W_d(x) of the 80
+// directions is built where it is used, so no adjoint relation is needed.
+template <class S, class T>
+__device__ __forceinline__ void bri_build(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ V,
+                                          int r, typename S::word* wbuf, int R, int tid) {
+  int dy, dz, dt;
+  bri_row_offset(r, dy, dz, dt);
+  if (tid >= 3 * c.n) return;
+  const int col = tid / c.n, site = tid - col * c.n;
+  const int d[4] = {col - 1, dy, dz, dt};
+  if ((d[0] | dy | dz | dt) == 0) return;  // no hop
+  const int x[4] = {c.x0 + site, c.y, c.z, c.t};
+  cpx<T> w[3][3];
+  brillouin_path_mean<S, T>(g, V, x, d, w);
+  typename S::word* o = wbuf + col * R * 9 + site * 9;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) S::template store<T>(o + a * 3 + b, w[a][b]);
+}
+
 // The three hops of staged row r (and the diagonal term, with the clover term
-// if CLOV, for the own row).
-template <bool ADJ, bool CLOV, int NV, class S, class T>
+// if CLOV, for the own row).  FLY: the link columns hold W_d(x) for all three
+// hops (built in place), never an adjoint.
+template <bool ADJ, bool CLOV, bool FLY, int NV, class S, class T>
 __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* buf, const typename S::word* wbuf,
                                                 const typename S::word* lcl, int R, int xl, int v, T diag,
                                                 cpx<T> (&acc)[4][3]) {
@@ -226,8 +253,8 @@ __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* b
     const T a = T(-0.5) * bri_lambda<T>(k);
     const T b = (ADJ ? T(-1) : T(1)) * bri_rho<T>(k);
     const typename S::word* link = wbuf + (dx + 1) * R * 9 + xl * 9;
-    bri_hop<NV, S, T>(site, link, bri_code(dx, dy, dz, dt) <= 40, v, a, b * T(dx), b * T(dy), b * T(dz), b * T(dt),
-                      dx, dy, dz, dt, acc);
+    bri_hop<NV, S, T>(site, link, !FLY && bri_code(dx, dy, dz, dt) <= 40, v, a, b * T(dx), b * T(dy), b * T(dz),
+                      b * T(dt), dx, dy, dz, dt, acc);
   }
 }
 
@@ -235,8 +262,9 @@ __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* b
 }  // namespace
 
 // CLOV: adds the site-local clover term (packed, 36 words per site, staged
-// in LDS after the link columns).
-template <bool ADJ, bool CLOV, int NV, class S, class T>
+// in LDS after the link columns).  FLY: Wl holds the one-hop links V and the
+// off-axis links are built on the fly for every row.
+template <bool ADJ, bool CLOV, bool FLY, int NV, class S, class T>
 __global__ void __launch_bounds__(256, 3)
     brillouin_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ Wl,
                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
@@ -269,13 +297,14 @@ __global__ void __launch_bounds__(256, 3)
   if constexpr (CLOV)
     copy_pieces<3>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * (36 * int(sizeof(W)) / 16), tid, nth);
   BriRowRegs<NV, S> q;
-  bri_issue<NV, S>(g, c, Wl, in, 0, xm, xp, xl, v, tid, nth, q);
+  bri_issue<FLY, NV, S>(g, c, Wl, in, 0, xm, xp, xl, v, tid, nth, q);
 #pragma nounroll
   for (int r = 0; r < kBriRows; ++r) {
-    bri_commit<NV, S>(c, q, buf, wbuf, R, xl, v, tid, nth);
+    bri_commit<FLY, NV, S>(c, q, buf, wbuf, R, xl, v, tid, nth);
+    if constexpr (FLY) bri_build<S, T>(g, c, Wl, r, wbuf, R, tid);
     __syncthreads();
-    bri_issue<NV, S>(g, c, Wl, in, r + 1 < kBriRows ? r + 1 : kBriRows - 1, xm, xp, xl, v, tid, nth, q);
-    bri_row_compute<ADJ, CLOV, NV, S, T>(r, buf, wbuf, lcl, R, xl, v, diag, acc);
+    bri_issue<FLY, NV, S>(g, c, Wl, in, r + 1 < kBriRows ? r + 1 : kBriRows - 1, xm, xp, xl, v, tid, nth, q);
+    bri_row_compute<ADJ, CLOV, FLY, NV, S, T>(r, buf, wbuf, lcl, R, xl, v, diag, acc);
     __syncthreads();
   }
   // output through LDS, coalesced 16-byte stores
@@ -299,7 +328,7 @@ __global__ void __launch_bounds__(256, 3)
   }
 }
 
-template <int NV, class S, class T>
+template <int NV, class S, class T, bool FLY>
 static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* Wl, const void* in,
                                    void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
@@ -309,7 +338,7 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
       (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(3 * R) * 9 + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   const T diag = T(mass) + T(15.0 / 8.0);
 #define DSL_BK(A, CL)                                                                                        \
-  hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl, \
+  hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, FLY, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl, \
                      (const W*)in, (W*)out, (const W*)C, diag)
   if (C) {
     if (adj) DSL_BK(true, true); else DSL_BK(false, true);
@@ -320,6 +349,20 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
   return hipGetLastError();
 }
 
+// Chunk length of the row-staged D_B for N_v = 12 in C64, or 0 when the
+// configuration is not covered.
+static int brillouin_rows_sites(int dtype, const Geom& g) {
+  // FP32 only: the FP64 variant would not fit in registers
+  if (g.nv != 12 || dtype != DT_C64) return 0;
+  int R = row_sites_default(g.n[0], g.nv);
+  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  if (R > g.n[0]) R = g.n[0];
+  // at least 12 sites: the halo sites (2 * 12 N_v words) take at most one
+  // 16-byte piece per thread
+  if (R < 12 || R * g.nv > 256) return 0;
+  return R;
+}
+
 // Row-staged D_B for N_v = 12 in C64.  Returns hipErrorNotSupported
 // when the configuration is not covered (the caller then uses the direct
 // kernel).  DSLASH_ROWS=0 disables it.
@@ -327,19 +370,27 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
                                  double mass, hipStream_t st, const void* clover) {
   if (const char* e = getenv("DSLASH_ROWS"))
     if (atoi(e) == 0) return hipErrorNotSupported;
-  // FP32 only: the FP64 variant would not fit in registers
-  if (g.nv != 12 || dtype != DT_C64) return hipErrorNotSupported;
-  int R = row_sites_default(g.n[0], g.nv);
-  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
-  if (R > g.n[0]) R = g.n[0];
-  // at least 12 sites: the halo sites (2 * 12 N_v words) take at most one
-  // 16-byte piece per thread
-  if (R < 12 || R * g.nv > 256) return hipErrorNotSupported;
+  const int R = brillouin_rows_sites(dtype, g);
+  if (R == 0) return hipErrorNotSupported;
   int bt = 2;
   if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
   bool xcd = true;
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
-  return brillouin_rows_t<12, C64, float>(adj, g, R, bt, xcd, Wl, in, out, clover, mass, st);
+  return brillouin_rows_t<12, C64, float, false>(adj, g, R, bt, xcd, Wl, in, out, clover, mass, st);
+}
+
+// D_B with the off-axis links built from V inside the row-staged kernel (no W
+// array).  Same configurations as launch_brillouin_rows; hipErrorNotSupported
+// otherwise.
+hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* V, const void* in, void* out,
+                                double mass, hipStream_t st, const void* clover) {
+  const int R = brillouin_rows_sites(dtype, g);
+  if (R == 0) return hipErrorNotSupported;
+  int bt = 2;
+  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bool xcd = true;
+  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  return brillouin_rows_t<12, C64, float, true>(adj, g, R, bt, xcd, V, in, out, clover, mass, st);
 }
 
 }  // namespace dsl

@@ -78,7 +78,7 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 104; }
+int dslash_version(void) { return 105; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
                         int Nv, double mass, int dtype, void* stream, const void* C = nullptr,
@@ -152,6 +152,27 @@ int dslash_apply_compressed(int op, const void* Vc, const void* in, void* out, c
   if (op != DSLASH_STAGGERED && op != DSLASH_WILSON)
     return fail(DSLASH_E_ARG, "compressed links are built for STAGGERED and WILSON (got op %d)", op);
   return apply_common(adjoint != 0, op, Vc, in, out, dims, Nc, Nv, mass, dtype, stream, nullptr, true);
+}
+
+int dslash_apply_brillouin_fly(const void* V, const void* in, void* out, const int dims[4], int Nc, int Nv,
+                               double mass, int adjoint, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, Nv)) return rc;
+  if (!valid_dtype(dtype)) return fail(DSLASH_E_ARG, "unknown dtype %d", dtype);
+  if (!V || !in || !out) return fail(DSLASH_E_ARG, "NULL field pointer");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t nspin = size_t(vol) * 12 * Nv * eb, nlink = size_t(vol) * 36 * eb;
+  if (overlap(in, nspin, out, nspin)) return fail(DSLASH_E_ALIAS, "in and out overlap");
+  if (overlap(V, nlink, out, nspin)) return fail(DSLASH_E_ALIAS, "V and out overlap");
+  const dsl::Geom g = dsl::make_geom(dims, Nv);
+  hipError_t e = dsl::launch_brillouin_fly(adjoint != 0, dtype, g, V, in, out, mass, (hipStream_t)stream);
+  if (e == hipErrorNotSupported)
+    return fail(DSLASH_E_UNSUPPORTED,
+                "on-the-fly links are built for N_v = 12, C64 and rows of at least 12 sites (got N_v = %d, dtype %d, "
+                "Nx = %d)", Nv, dtype, dims[0]);
+  if (e != hipSuccess) return hip_fail(e, "dslash_apply_brillouin_fly launch");
+  return DSLASH_OK;
 }
 
 int dslash_backward(int op, const void* U, const void* grad_out, const void* in, void* grad_U, void* grad_in,

@@ -37,6 +37,8 @@ hipError_t launch_compress_links(int dtype, size_t links, const void* V, void* V
 hipError_t launch_brillouin_rows(bool adjoint, int dtype, const Geom& g, const void* W, const void* in, void* out,
                                  double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
+hipError_t launch_brillouin_fly(bool adjoint, int dtype, const Geom& g, const void* V, const void* in, void* out,
+                                double mass, hipStream_t st, const void* clover = nullptr);
 hipError_t launch_clover_field(int dtype, const Geom& g, const void* V, void* C, double c_sw, hipStream_t st);
 hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
                                   hipStream_t st);

@@ -422,13 +422,11 @@ DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W
 }
 
 // ---------------------------------------------------------------- W build
-// W_d(x) for stored slot j (Tab. 1): mean over the k! orderings of the hops of
-// d of the ordered product V_{e1}(x) V_{e2}(x+e1) ..., V_{-mu}(y) = V_mu(y-mu)^dag.
+// W_d(x) (Tab. 1): the mean over the k! orderings of the hops of d of the
+// ordered product V_{e1}(x) V_{e2}(x+e1) ..., V_{-mu}(y) = V_mu(y-mu)^dag.
 template <class S, class T>
-DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restrict__ V,
-                                typename S::word* __restrict__ Wout, uint32_t s, int j) {
-  int d[4];
-  stored_direction(j, d);
+DSL_HD void brillouin_path_mean(const Geom& g, const typename S::word* __restrict__ V, const int (&x)[4],
+                                const int (&d)[4], cpx<T> (&acc)[3][3]) {
   int mus[4], sgn[4], k = 0;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
@@ -437,8 +435,6 @@ DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restric
       sgn[k] = d[mu];
       ++k;
     }
-  const SiteNbr nb = site_nbr(g, s);
-  cpx<T> acc[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -470,7 +466,7 @@ DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restric
       if (i >= k && perm[i] != i) keep = false;
     if (!keep) continue;
     ++nperm;
-    int pos[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+    int pos[4] = {x[0], x[1], x[2], x[3]};
     cpx<T> m[3][3];
 #pragma unroll 1
     for (int i = 0; i < k; ++i) {
@@ -485,9 +481,9 @@ DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restric
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int b = a; b < 3; ++b) {
-            cpx<T> x = l[a][b], y = l[b][a];
-            l[a][b] = conj(y);
-            l[b][a] = conj(x);
+            cpx<T> x1 = l[a][b], y1 = l[b][a];
+            l[a][b] = conj(y1);
+            l[b][a] = conj(x1);
           }
       }
       if (i == 0) {
@@ -519,11 +515,27 @@ DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restric
       for (int b = 0; b < 3; ++b) acc[a][b] += m[a][b];
   }
   const T inv = T(1) / T(nperm);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = inv * acc[a][b];
+}
+
+// Stored W for slot j (direction n(d) = j + 41) at site s.
+template <class S, class T>
+DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restrict__ V,
+                                typename S::word* __restrict__ Wout, uint32_t s, int j) {
+  int d[4];
+  stored_direction(j, d);
+  const SiteNbr nb = site_nbr(g, s);
+  const int x[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+  cpx<T> w[3][3];
+  brillouin_path_mean<S, T>(g, V, x, d, w);
   const size_t base = (size_t(s) * 40 + j) * 9;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) S::template store<T>(Wout + base + a * 3 + b, inv * acc[a][b]);
+    for (int b = 0; b < 3; ++b) S::template store<T>(Wout + base + a * 3 + b, w[a][b]);
 }
 
 }  // namespace dsl

@@ -24,6 +24,7 @@ __all__ = [
     "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
     "backward", "brillouin_links", "convert", "solve", "dslash", "op_code", "clover_field", "eo_pack", "eo_unpack",
     "eo_hop", "compress_links", "apply_compressed", "brillouin_links_backward", "brillouin_links_autograd",
+    "apply_brillouin_fly",
 ]
 
 STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
@@ -63,12 +64,13 @@ def _load():
     lib.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     lib.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
+    lib.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
                  "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
                  "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
-                 "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward"):
+                 "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward", "dslash_apply_brillouin_fly"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -183,6 +185,22 @@ def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bo
     fn = _lib.dslash_apply_adjoint if adjoint else _lib.dslash_apply
     _check(fn(op, _ptr(U), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass), _dtype_code(psi),
               _stream(psi)), "dslash_apply")
+    return out
+
+
+def apply_brillouin_fly(V: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """D_B psi (or D_B^dag psi) with the off-axis links built from V inside the kernel."""
+    lat, nv = _validate(WILSON, V, psi)   # V and psi have the shapes of the Wilson operator
+    if out is None:
+        out = torch.empty_like(psi)
+    else:
+        _require(out, "out")
+        if out.shape != psi.shape or out.dtype != psi.dtype:
+            raise ValueError("out must match psi in shape and dtype")
+    _check(_lib.dslash_apply_brillouin_fly(_ptr(V), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass),
+                                           int(bool(adjoint)), _dtype_code(psi), _stream(psi)),
+           "dslash_apply_brillouin_fly")
     return out
 
 

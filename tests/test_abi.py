@@ -40,6 +40,7 @@ def lib():
     l.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     l.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     l.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
+    l.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     return l
 
 
@@ -50,10 +51,10 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 20
+    assert len(declared) == 21
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 104
+    assert lib.dslash_version() == 105
 
 
 def test_status_strings(lib):
@@ -184,3 +185,13 @@ def test_brillouin_links_backward_validation(lib):
     assert lib.dslash_brillouin_links_backward(A, B, B, dims, 3, 0, None) == 3      # grad_V == grad_W
     assert lib.dslash_brillouin_links_backward(A, B, C, dims, 3, 2, None) == 2      # BF16
     assert lib.dslash_brillouin_links_backward(A, B, C, dims, 2, 0, None) == 2      # Nc != 3
+
+
+def test_brillouin_fly_validation(lib):
+    dims = _dims(16, 4, 4, 4)
+    D = 0x20000000
+    assert lib.dslash_apply_brillouin_fly(None, C, D, dims, 3, 12, 0.1, 0, 0, None) == 1   # NULL V
+    assert lib.dslash_apply_brillouin_fly(A, C, C, dims, 3, 12, 0.1, 0, 0, None) == 3      # in == out
+    assert lib.dslash_apply_brillouin_fly(A, C, D, dims, 3, 4, 0.1, 0, 0, None) == 2       # N_v = 4
+    assert lib.dslash_apply_brillouin_fly(A, C, D, dims, 3, 12, 0.1, 0, 1, None) == 2      # C128
+    assert lib.dslash_apply_brillouin_fly(A, C, D, _dims(8, 4, 4, 4), 3, 12, 0.1, 0, 0, None) == 2  # rows of 8
