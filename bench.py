@@ -13,8 +13,9 @@ well above the 256 MB Infinity Cache.
 Further rows (``rows`` in the JSON line), each timed the same way:
 D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
 BF16 storage, D_W and D_B with the clover term (c_SW = 1), D_W and D_S with
-compressed links (two stored rows per link) against full links, link gradients at
-24^3 x 48, and the mixed-precision solve at 32^3 x 64 (time to
+compressed links (two stored rows per link) against full links, D_B with W built
+on the fly from V inside the kernel, link gradients at
+24^3 x 48 (D_S, D_W, and D_B with respect to W and through W to V), and the mixed-precision solve at 32^3 x 64 (time to
 ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16 inner storage, on the
 full lattice and on the even-odd Schur complement).
 
@@ -198,6 +199,24 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
             row["c_sw"] = 1.0
             rows["brillouin_clover_32^4_nv12_fp32"] = row
             del C
+            # the same operator with W built on the fly from V inside the kernel (no W array)
+            V = up(v, cdt)
+            sets_v = [V]
+
+            def fly(i):
+                D.apply_brillouin_fly(sets_v[0], P, 0.1, out=out_fly)
+            out_fly = torch.empty_like(P)
+            nfly = max(3, steps // 10)
+            tf = timed(torch, fly, nfly, 2)
+            vol = int(np.prod(dims))
+            fbytes = (36 + 2 * 12 * 12) * eb * vol
+            rows["brillouin_fly_32^4_nv12_fp32"] = {
+                "us": tf * 1e6, "gflops": FLOPS["brillouin"] * vol * 12 / tf / 1e9,
+                "valu_frac": FLOPS["brillouin"] * vol * 12 / tf / peak, "gbs": fbytes / tf / 1e9,
+                "bytes_per_launch": fbytes, "vs_stored_w": rows["brillouin_32^4_nv12_fp32"]["us"] / (tf * 1e6),
+                "note": "apply flops only (the W construction inside the kernel is not counted)"}
+            log(f"D_B fly 32^4 fp32: {tf * 1e6:.1f} us")
+            del V, out_fly
         del W, P
         torch.cuda.empty_cache()
     # D_W with BF16 storage (FP32 arithmetic) on the headline workload
@@ -265,6 +284,40 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
                                                      "bytes_per_launch": nbytes}
         log(f"link grad {op}: {t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
         del U, C, P, gU
+    torch.cuda.empty_cache()
+    # Brillouin link gradient at 24^3 x 48, N_v = 12, FP32: with respect to the stored W
+    # (dslash_backward), then through the W construction to V (dslash_brillouin_links_backward)
+    V = up(synthetic.gauge_links(dims, "haar", 6), np.complex64)
+    W = D.brillouin_links(V)
+    C = up(synthetic.wilson_spinor(dims, 12, 104), np.complex64)
+    P = up(synthetic.wilson_spinor(dims, 12, 105), np.complex64)
+    gW = torch.empty_like(W)
+    gV = torch.empty_like(V)
+    import ctypes
+    lib = D._lib
+    dims_c = (ctypes.c_int * 4)(*dims)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+
+    def wgrad(i):
+        if lib.dslash_backward(2, vp(W), vp(C), vp(P), vp(gW), None, dims_c, 3, 12, 0.0, 0, stream):
+            raise RuntimeError("dslash_backward failed")
+
+    def vgrad(i):
+        if lib.dslash_brillouin_links_backward(vp(V), vp(gW), vp(gV), dims_c, 3, 0, stream):
+            raise RuntimeError("dslash_brillouin_links_backward failed")
+    vol = int(np.prod(dims))
+    nsteps = max(3, steps // 20)
+    tw = timed(torch, wgrad, nsteps, 1)
+    tv = timed(torch, vgrad, nsteps, 1)
+    bw = (2 * 12 * 12 * 8 + 360 * 8) * vol   # chi and psi read, G_W written
+    bv = (36 * 8 + 360 * 8 + 36 * 8) * vol   # V and G_W read, G_V written
+    rows["link_grad_brillouin_W_24^3x48_nv12_fp32"] = {"us": tw * 1e6, "gbs": bw / tw / 1e9,
+                                                       "hbm_frac": bw / tw / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bw}
+    rows["brillouin_links_backward_24^3x48_fp32"] = {"us": tv * 1e6, "gbs": bv / tv / 1e9,
+                                                     "hbm_frac": bv / tv / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bv}
+    log(f"Brillouin link grad: W {tw * 1e6:.1f} us, through W to V {tv * 1e6:.1f} us")
+    del V, W, C, P, gW, gV
     torch.cuda.empty_cache()
     # mixed-precision solve, 32^3 x 64, N_v = 12, m0 = 0.05, smooth links
     dims = (32, 32, 32, 64)

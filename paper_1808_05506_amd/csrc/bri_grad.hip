@@ -8,7 +8,8 @@
 // with S_{-d} = a_k - b_k d.gamma.  S_d is Hermitian, so
 //   G_{W_d}(x) = sum_v sum_s [ (S_d chi(x))_s (x) conj(psi(x+d)_s)
 //                            + psi(x)_s (x) conj((S_{-d} chi(x+d))_s) ].
-// One thread per (site, stored direction), the N_v right-hand sides in a loop.
+// A block handles one stored direction for a run of sites; the N_v lanes of a
+// site each take their right-hand sides and the shares are summed through LDS.
 //
 // bri_links_backward_kernel: the adjoint of the construction of W from V
 // (Tab. 1).  W_d(x) is the mean over the k! hop orderings of the path product
@@ -133,22 +134,25 @@ DSL_HD void decode_perm(int code, int (&perm)[4]) {
 
 }  // namespace
 
+// Block (VB, SB): lane x takes the right-hand sides v = x, x + VB, ... of
+// site y (so the VB lanes of a site read consecutive words of every spinor
+// component), accumulates its share of G_{W_d}, and the shares are summed over
+// the lanes through LDS in a fixed order.  blockIdx.y = stored slot.
 template <class S, class T>
-__global__ void __launch_bounds__(128) bri_wgrad_kernel(Geom g, const typename S::word* __restrict__ chi,
+__global__ void __launch_bounds__(256) bri_wgrad_kernel(Geom g, const typename S::word* __restrict__ chi,
                                                        const typename S::word* __restrict__ psi,
                                                        typename S::word* __restrict__ GW) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ unsigned char smem_wgrad[];
+  T* red = reinterpret_cast<T*>(smem_wgrad);  // [SB][18][VB]
+  const int VB = int(blockDim.x), SB = int(blockDim.y);
+  const int lane = int(threadIdx.x), sl = int(threadIdx.y);
+  const uint32_t s0 = blockIdx.x * uint32_t(SB);
+  const uint32_t s = s0 + uint32_t(sl);
   const int j = int(blockIdx.y);  // stored slot, uniform over the block
-  if (s >= g.vol) return;
   int d[4];
   stored_direction(j, d);
   const int k = (d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0);
   const T a = T(-0.5) * bri_lambda<T>(k), b = bri_rho<T>(k);
-  const SiteNbr nb = site_nbr(g, s);
-  int q[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) q[mu] = wrap(q[mu] + d[mu], g.n[mu]);
-  const uint32_t sd = site_of(g, q);
   const int nv = g.nv;
   const size_t sps = size_t(12) * nv;
 
@@ -157,39 +161,63 @@ __global__ void __launch_bounds__(128) bri_wgrad_kernel(Geom g, const typename S
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) G[r][c] = zero<T>();
+  if (s < g.vol) {
+    const SiteNbr nb = site_nbr(g, s);
+    int q[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) q[mu] = wrap(q[mu] + d[mu], g.n[mu]);
+    const uint32_t sd = site_of(g, q);
 #pragma unroll 1
-  for (int v = 0; v < nv; ++v) {
-    cpx<T> cx[4][3], cd[4][3], px[4][3], pd[4][3];
-    load_wspinor<S, T>(chi, size_t(s) * sps + v, nv, cx);
-    load_wspinor<S, T>(chi, size_t(sd) * sps + v, nv, cd);
-    load_wspinor<S, T>(psi, size_t(s) * sps + v, nv, px);
-    load_wspinor<S, T>(psi, size_t(sd) * sps + v, nv, pd);
-    // af = S_d chi(x) = a chi(x) + b (d.gamma) chi(x); ab = S_{-d} chi(x+d) = a chi(x+d) - b (d.gamma) chi(x+d)
-    cpx<T> af[4][3], ab[4][3];
-    dgamma<T>(d, cx, af);
-    dgamma<T>(d, cd, ab);
+    for (int v = lane; v < nv; v += VB) {
+      cpx<T> cx[4][3], cd[4][3], px[4][3], pd[4][3];
+      load_wspinor<S, T>(chi, size_t(s) * sps + v, nv, cx);
+      load_wspinor<S, T>(chi, size_t(sd) * sps + v, nv, cd);
+      load_wspinor<S, T>(psi, size_t(s) * sps + v, nv, px);
+      load_wspinor<S, T>(psi, size_t(sd) * sps + v, nv, pd);
+      // af = S_d chi(x) = a chi(x) + b (d.gamma) chi(x); ab = S_{-d} chi(x+d) = a chi(x+d) - b (d.gamma) chi(x+d)
+      cpx<T> af[4][3], ab[4][3];
+      dgamma<T>(d, cx, af);
+      dgamma<T>(d, cd, ab);
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        af[sp][c] = rmadd(b * af[sp][c], a, cx[sp][c]);
-        ab[sp][c] = rmadd((-b) * ab[sp][c], a, cd[sp][c]);
-      }
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          G[r][c] = cmaddj(G[r][c], af[sp][r], pd[sp][c]);
-          G[r][c] = cmaddj(G[r][c], px[sp][r], ab[sp][c]);
+          af[sp][c] = rmadd(b * af[sp][c], a, cx[sp][c]);
+          ab[sp][c] = rmadd((-b) * ab[sp][c], a, cd[sp][c]);
         }
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            G[r][c] = cmaddj(G[r][c], af[sp][r], pd[sp][c]);
+            G[r][c] = cmaddj(G[r][c], px[sp][r], ab[sp][c]);
+          }
+    }
   }
-  typename S::word* o = GW + (size_t(s) * 40 + j) * 9;
+  // shares of the VB lanes of each site, summed in lane order
+  T* mine = red + size_t(sl) * 18 * VB + lane;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, G[r][c]);
+    for (int c = 0; c < 3; ++c) {
+      mine[(2 * (r * 3 + c)) * VB] = G[r][c].r;
+      mine[(2 * (r * 3 + c) + 1) * VB] = G[r][c].i;
+    }
+  __syncthreads();
+  const int nthr = VB * SB;
+  for (int t = sl * VB + lane; t < SB * 9; t += nthr) {
+    const int site = t / 9, e = t - site * 9;
+    if (s0 + uint32_t(site) >= g.vol) continue;
+    const T* src = red + size_t(site) * 18 * VB;
+    T re = T(0), im = T(0);
+    for (int l = 0; l < VB; ++l) {
+      re += src[(2 * e) * VB + l];
+      im += src[(2 * e + 1) * VB + l];
+    }
+    S::template store<T>(GW + ((size_t(s0) + site) * 40 + j) * 9 + e, mk(re, im));
+  }
 }
 
 template <class S, class T>
@@ -302,8 +330,11 @@ namespace {
 template <class S, class T>
 hipError_t wgrad_t(const Geom& g, const void* chi, const void* psi, void* GW, hipStream_t st) {
   using W = typename S::word;
-  const dim3 block(128), grid((g.vol + 127) / 128, 40);
-  hipLaunchKernelGGL((bri_wgrad_kernel<S, T>), grid, block, 0, st, g, (const W*)chi, (const W*)psi, (W*)GW);
+  const int vb = g.nv < 16 ? g.nv : 16;
+  const int sb = 256 / vb;
+  const dim3 block(vb, sb), grid((g.vol + sb - 1) / sb, 40);
+  const size_t lds = size_t(sb) * 18 * vb * sizeof(T);
+  hipLaunchKernelGGL((bri_wgrad_kernel<S, T>), grid, block, lds, st, g, (const W*)chi, (const W*)psi, (W*)GW);
   return hipGetLastError();
 }
 
