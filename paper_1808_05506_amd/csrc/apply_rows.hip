@@ -539,8 +539,124 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
   __syncthreads();
 }
 
-template <int DEPTH, bool ADJ, int NV, class S, class T, int LW>
-__global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
+// The same step with two row buffers used in turn: row k + 1 is written to
+// one buffer while row k is applied from the other, so each staged row costs
+// one barrier instead of two.  LDS: buf0, buf1 [(R + 2) SSW], lown, lnb0, lnb1.
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
+__device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
+                                              const typename S::word* __restrict__ U,
+                                              const typename S::word* __restrict__ in,
+                                              typename S::word* __restrict__ out, typename S::word* buf0,
+                                              typename S::word* buf1, typename S::word* lown, typename S::word* lnb0,
+                                              typename S::word* lnb1, int xm, int xp, int xl, int v, int tid, int nth,
+                                              T diag, u32x4 (&r0)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
+                                              u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3]) {
+  using W = typename S::word;
+  using Q = MarchSeq<FIRST>;
+  constexpr int LK = LinkK<S, NV, LW>::value;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
+  constexpr int CF = ADJ ? +1 : -1, CB = -CF;
+  if constexpr (!FIRST) {
+#define DSL_SISSUE(P) march_issue<Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+    DSL_SISSUE(0);
+    if constexpr (DEPTH > 1) DSL_SISSUE(1);
+    if constexpr (DEPTH > 2) DSL_SISSUE(2);
+#undef DSL_SISSUE
+    links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
+  }
+  links_commit<S, LK, LW>(c, lr, lown, tid, nth);
+
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
+
+#define DSL_MISSUE(P) march_issue<Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+  // row P of the sequence goes to buffer P % 2
+#define DSL_BUF(P) ((P) % 2 == 0 ? buf0 : buf1)
+#define DSL_LNB(P) ((P) % 2 == 0 ? lnb0 : lnb1)
+#define DSL_COMMIT(P, SGN, CUR) row_commit<SGN, NV, S, LW>(c, CUR, DSL_BUF(P) + SSW, DSL_LNB(P), xl, v, tid)
+  DSL_COMMIT(0, +1, r0);
+  __syncthreads();
+  // P: the row applied now; then P + 1 is written into the other buffer
+#define DSL_PSTEP(P, MU, SGN, NSGN, NCUR)                                             \
+  if constexpr (P + DEPTH < Q::N) DSL_MISSUE(P + DEPTH);                              \
+  row_compute<MU, SGN, ADJ, NV, S, T, LW>(DSL_BUF(P) + SSW, lown, DSL_LNB(P), xl, v, acc); \
+  hold_acc<T>(acc);                                                                   \
+  if constexpr (P + 1 < Q::N - 1) DSL_COMMIT(P + 1, NSGN, NCUR);                      \
+  if constexpr (P + 1 == Q::N - 1) own_commit<NV, S>(c, r6, DSL_BUF(P + 1), xl, v, tid); \
+  __syncthreads();
+  if constexpr (FIRST) {
+    DSL_PSTEP(0, 1, +1, -1, r1)
+    DSL_PSTEP(1, 1, -1, +1, r2)
+    DSL_PSTEP(2, 2, +1, -1, r3)
+    DSL_PSTEP(3, 2, -1, +1, r4)
+    DSL_PSTEP(4, 3, +1, -1, r5)
+    DSL_PSTEP(5, 3, -1, +1, r0)
+  } else {
+    DSL_PSTEP(0, 1, +1, -1, r1)
+    DSL_PSTEP(1, 1, -1, +1, r2)
+    DSL_PSTEP(2, 2, +1, -1, r3)
+    DSL_PSTEP(3, 2, -1, +1, r4)
+    DSL_PSTEP(4, 3, +1, +1, r0)
+  }
+#undef DSL_PSTEP
+#undef DSL_COMMIT
+#undef DSL_MISSUE
+  W* const own = DSL_BUF(Q::N - 1);
+#undef DSL_BUF
+#undef DSL_LNB
+  cpx<T> res[4][3];
+  {
+    lds_hop<0, CF, false, NV, S, T, LW>(own + (xl + 2) * SSW, lown + (xl + 1) * 4 * LW, v, acc);
+    lds_hop<0, CB, true, NV, S, T, LW>(own + xl * SSW, lown + xl * 4 * LW, v, acc);
+    if constexpr (!FIRST) reconstruct_add<3, CB, T>(acc, carry);
+    cpx<T> p[4][3];
+    lds_spinor<S, T, NV>(own + (xl + 1) * SSW, v, p);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        res[sp][cc].r = fma(diag, p[sp][cc].r, T(-0.5) * acc[sp][cc].r);
+        res[sp][cc].i = fma(diag, p[sp][cc].i, T(-0.5) * acc[sp][cc].i);
+      }
+    cpx<T> h[2][3];
+    project<3, CB, T>(p, h);
+    cpx<T> u[3][3];
+    load_link_lw<LW, S, T>(lown + (xl + 1) * 4 * LW + 3 * LW, u);
+    su3_mul2<true, T>(u, h, carry);
+  }
+  // the output leaves through the other buffer (free since the last barrier)
+  W* const ob = own == buf0 ? buf1 : buf0;
+  {
+    W* o = ob + xl * SSW;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) S::template store<T>(o + (sp * 3 + cc) * NV + v, res[sp][cc]);
+  }
+  __syncthreads();
+  {
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
+    u32x4 r[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(r[j], &dst[j * NV + v]);
+  }
+  __syncthreads();
+}
+
+// PP: the two-buffer step (march_step_pp).
+template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, bool PP = false>
+__global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
   using W = typename S::word;
@@ -549,8 +665,10 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
   extern __shared__ uint4 smem_march[];
   const int R = int(m.sb);
   W* buf = reinterpret_cast<W*>(smem_march);
-  W* lown = buf + (R + 2) * SSW;
+  W* buf1 = buf + (R + 2) * SSW;  // PP only
+  W* lown = PP ? buf1 + (R + 2) * SSW : buf + (R + 2) * SSW;
   W* lnb = lown + (R + 1) * 4 * LW;
+  W* lnb1 = lnb + R * LW;  // PP only
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const uint32_t seg = m.d_rows.div(L);
@@ -574,33 +692,45 @@ __global__ void __launch_bounds__(256, MarchWaves<DEPTH>::value)
   if constexpr (DEPTH > 4) DSL_PISSUE(4);
 #undef DSL_PISSUE
   links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
-  march_step<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
-                                         r0, r1, r2, r3, r4, r5, r6, lr, carry);
+  if constexpr (PP)
+    march_step_pp<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v, tid,
+                                                  nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+  else
+    march_step<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
+                                               r0, r1, r2, r3, r4, r5, r6, lr, carry);
 #pragma nounroll
   for (int k = 1; k < steps; ++k) {
     c.t += 1;
     c.row_base += uint32_t(g.stride[3]);
-    march_step<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
-                                            diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    if constexpr (PP)
+      march_step_pp<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v,
+                                                     tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    else
+      march_step<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
+                                                  diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
   }
 }
 
 template <int DEPTH, int NV, class S, class T, int LW = 9>
-static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, bool xcd, const void* U, const void* in,
-                                 void* out, double mass, hipStream_t st) {
+static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, bool pp, bool xcd, const void* U,
+                                 const void* in, void* out, double mass, hipStream_t st) {
   using W = typename S::word;
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
   size_t lds = rows_lds_words<NV, S, LW>(R) * sizeof(W);
+  if (pp) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
-  if (adj)
-    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, true, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
-                       (const W*)U, (const W*)in, (W*)out, diag);
-  else
-    hipLaunchKernelGGL((wilson_march_kernel<DEPTH, false, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
-                       (const W*)U, (const W*)in, (W*)out, diag);
+#define DSL_MK(A, P)                                                                                        \
+  hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
+                     (const W*)U, (const W*)in, (W*)out, diag)
+  if (pp) {
+    if (adj) DSL_MK(true, true); else DSL_MK(false, true);
+  } else {
+    if (adj) DSL_MK(true, false); else DSL_MK(false, false);
+  }
+#undef DSL_MK
   return hipGetLastError();
 }
 
@@ -801,6 +931,19 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
 // Row-staged D_W for N_v = 12 with FP32 arithmetic (C64, BF16, F16 storage).
 // Returns hipErrorNotSupported when the configuration is not covered (the
 // caller then uses the direct-load kernel).  DSLASH_ROWS=0 disables it.
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                               double mass, hipStream_t st, const void* clover, bool compressed) {
   if (const char* e = getenv("DSLASH_ROWS"))
@@ -821,8 +964,24 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
   // 0 selects the kernel with one output row per workgroup).
   // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 2 marching, 3 otherwise).
+  // DSLASH_MARCH_PP: 1 = two row buffers (one barrier per staged row), 0 = one.
+  // Default: with FP32 storage, a lattice whose 16-step grid fits at two
+  // workgroups per CU (then all its workgroups are resident at once) marches
+  // 16 steps with two buffers; otherwise 8 steps with one.
   int tsteps = 8;
-  if (const char* e = getenv("DSLASH_TSTEPS")) tsteps = atoi(e);
+  bool pp = false;
+  if (const char* e = getenv("DSLASH_TSTEPS")) {
+    tsteps = atoi(e);
+  } else if (dtype == DT_C64 && !compressed && !clover && g.n[3] >= 16) {
+    const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
+    const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
+    if (wgs <= 2u * uint32_t(device_cus())) {
+      tsteps = 16;
+      pp = true;
+    }
+  }
+  if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e) != 0;
+  if (compressed) pp = false;
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
   // the clover term is fused into the one-row-per-workgroup kernel only;
   // compressed links are read by the t-marching kernel only
@@ -831,9 +990,9 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
     const int depth = depth_env ? atoi(depth_env) : 2;
 #define DSL_MT(D, LW)                                                                                          \
   switch (dtype) {                                                                                             \
-    case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
-    case DT_BF16: return wilson_march_t<D, 12, BF16, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st); \
-    case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st);   \
+    case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
+    case DT_BF16: return wilson_march_t<D, 12, BF16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st); \
+    case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
   }
     if (compressed) {
       DSL_MT(2, 6)

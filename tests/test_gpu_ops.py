@@ -210,17 +210,37 @@ def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
 
 
 @pytest.mark.parametrize("dims,tsteps", [((16, 2, 2, 11), "8"), ((12, 3, 2, 17), "8"), ((16, 2, 3, 7), "3"),
-                                         ((16, 2, 2, 5), "1"), ((16, 2, 2, 4), "64")])
+                                         ((16, 2, 2, 5), "1"), ((16, 2, 2, 4), "64"), ((13, 2, 2, 35), "16")])
 @pytest.mark.parametrize("adj", [False, True])
-def test_wilson_march_segments(dims, tsteps, adj, monkeypatch):
+@pytest.mark.parametrize("pp", ["0", "1"])
+def test_wilson_march_segments(dims, tsteps, adj, pp, monkeypatch):
     # t-marching workgroups over several t segments, a partial last one, one
-    # step per workgroup (no carried -t hop) and a segment longer than N_t
+    # step per workgroup (no carried -t hop) and a segment longer than N_t,
+    # with one row buffer and with two used in turn
     nv, dt = 12, "c64"
     monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
-    say(f"case wilson march segments {dims} T={tsteps} adj={adj}")
+    monkeypatch.setenv("DSLASH_MARCH_PP", pp)
+    say(f"case wilson march segments {dims} T={tsteps} pp={pp} adj={adj}")
     u, p = _wil_fields(dims, nv, 83, 84, dt, "haar")
     out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
     compare(down(out), wilson.apply(u, p, 0.1, adj), dt, "D_W march segments")
+
+
+def test_march_two_buffers_bitwise_equal_one_buffer(monkeypatch):
+    # 16^3 x 32, N_v = 12, FP32: the default launch marches 16 steps with two
+    # row buffers; the arithmetic is the single-buffer kernel's, so at the same
+    # segment length the results agree bit for bit, and both match the oracle
+    dims, nv, dt = (16, 16, 16, 32), 12, "c64"
+    say("case wilson march two buffers vs one")
+    u, p = _wil_fields(dims, nv, 85, 86, dt, "smooth")
+    U, P = up(u, dt), up(p, dt)
+    default = D.apply("wilson", U, P, 0.1)
+    monkeypatch.setenv("DSLASH_TSTEPS", "16")
+    monkeypatch.setenv("DSLASH_MARCH_PP", "0")
+    one = D.apply("wilson", U, P, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(default, one)
+    compare(down(default), wilson.apply(u, p, 0.1), dt, "D_W 16^3x32 default launch")
 
 
 @pytest.mark.parametrize("kernel", ["march", "rows"])
