@@ -8,14 +8,18 @@ kernel's share of the HBM bandwidth roofline.  A step is one application of
 D_W to the 12-vector block (site indexing, 8 hops with spin projection,
 single write of every output).  Inputs are resident in HBM before timing;
 R rotating (U, in, out) sets (default 4, about 1.4 GB) keep the working set
-well above the 256 MB Infinity Cache.
+well above the 256 MB Infinity Cache.  Each operator row is launched through
+the C ABI with its arguments marshalled once, and runs untimed for 0.1 s
+before its W warmup and K timed launches (the first tens of milliseconds of
+back-to-back launches are slower while the clocks settle).
 
 Further rows (``rows`` in the JSON line), each timed the same way:
 D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
 BF16 storage, D_W and D_B with the clover term (c_SW = 1), D_W and D_S with
-compressed links (two stored rows per link) against full links, D_B with W built
-on the fly from V inside the kernel, link gradients at
-24^3 x 48 (D_S, D_W, and D_B with respect to W and through W to V), and the mixed-precision solve at 32^3 x 64 (time to
+compressed links (two stored rows per link) against full links, D_B with W
+built on the fly from V inside the kernel, link gradients at 24^3 x 48 (D_S,
+D_W, and D_B with respect to W and through W to V), and the mixed-precision
+solve at 32^3 x 64 (time to
 ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and FP16 inner storage, on the
 full lattice and on the even-odd Schur complement).
 
@@ -77,6 +81,24 @@ def measured_traffic(name: str):
     return ent.get("bytes_per_launch")
 
 
+SETTLE_SECONDS = 0.1
+
+
+def settle(torch, launch, seconds: float = SETTLE_SECONDS) -> int:
+    """Untimed launches for ``seconds`` of wall time before the warmup steps: the
+    first tens of milliseconds of back-to-back launches run measurably slower
+    (clock and power ramp), which a short warmup does not cover.  Returns the
+    number of launches."""
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            launch(n)
+            n += 1
+        torch.cuda.synchronize()
+    return n
+
+
 def timed(torch, launch, steps: int, warmup: int) -> float:
     """Mean seconds per launch over ``steps`` launches on the current stream."""
     for i in range(warmup):
@@ -102,16 +124,43 @@ def rotated_sets(torch, U, P, count: int, C=None):
     return sets
 
 
+def abi_launcher(torch, D, op, U, P, out, mass, clover=None, compressed=False):
+    """A closure that enqueues one application through the C ABI with its
+    arguments marshalled once (the Python binding's per-call checks cost about
+    as much host time as the kernel takes on the GPU, which would leave the
+    GPU idle between back-to-back launches)."""
+    import ctypes
+    D.apply(op, U, P, mass, out=out, clover=clover) if not compressed else D.apply_compressed(op, U, P, mass, out=out)
+    lib = D._lib
+    code = D.op_code(op)
+    nt, nz, ny, nx = P.shape[:4]
+    dims = (ctypes.c_int * 4)(nx, ny, nz, nt)
+    nv = P.shape[-1] if P.dtype in (torch.complex64, torch.complex128) else P.shape[-2]
+    dt = D._dtype_code(P)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    vu, vp, vo = ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(out.data_ptr())
+    m = ctypes.c_double(mass)
+    if compressed:
+        fn, args = lib.dslash_apply_compressed, (code, vu, vp, vo, dims, 3, nv, m, 0, dt, stream)
+    elif clover is not None:
+        fn, args = lib.dslash_apply_clover, (code, vu, ctypes.c_void_p(clover.data_ptr()), vp, vo, dims, 3, nv, m, 0,
+                                             dt, stream)
+    else:
+        fn, args = lib.dslash_apply, (code, vu, vp, vo, dims, 3, nv, m, dt, stream)
+
+    def launch():
+        rc = fn(*args)
+        if rc:
+            raise RuntimeError(f"{fn.__name__} failed: {rc}")
+    return launch
+
+
 def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, label, clover=None, compressed=False):
     sets = rotated_sets(torch, U, P, rotate, clover)
     outs = [torch.empty_like(P) for _ in sets]
-
-    def launch(i):
-        u, p, c = sets[i % len(sets)]
-        if compressed:
-            D.apply_compressed(op, u, p, mass, out=outs[i % len(sets)])
-        else:
-            D.apply(op, u, p, mass, out=outs[i % len(sets)], clover=c)
+    launchers = [abi_launcher(torch, D, op, u, p, o, mass, c, compressed) for (u, p, c), o in zip(sets, outs)]
+    launch = lambda i: launchers[i % len(launchers)]()  # noqa: E731
+    settle(torch, launch)
     t = timed(torch, launch, steps, warmup)
     nt, nz, ny, nx = P.shape[:4]
     vol = nt * nz * ny * nx
@@ -424,6 +473,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_seconds": SETTLE_SECONDS,
         "ms_per_step": t * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
