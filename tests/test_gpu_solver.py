@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synthetic
-from oracle import dense, solver, staggered, wilson
+from oracle import dense, local, solver, staggered, wilson
 from tests.gpu_util import down, say, up
 
 pytestmark = pytest.mark.gpu
@@ -92,3 +92,33 @@ def test_wilson_solve_nv12_row_kernels(inner, itol):
     say(f"oracle residuals {res}")
     assert np.all(res <= 1e-10)
     assert np.allclose(info["relres"], res, rtol=1e-3, atol=1e-13)
+
+
+def test_wilson_solve_32cube64_nv12_sampled():
+    # the solver workload: 32^3 x 64, N_v = 12, m0 = 0.05, smooth links (seed 3),
+    # rhs seed 103; BF16 inner storage on the full lattice and FP16 on the
+    # even-odd Schur complement.  ||b - D x||_2 <= 1e-10 ||b||_2 per column
+    # bounds every single element of the residual, which the oracle evaluates
+    # in FP64 at sampled sites.
+    dims, nv, m0 = (32, 32, 32, 64), 12, 0.05
+    say(f"case solve wilson {dims} nv={nv} sampled")
+    u = synthetic.gauge_links(dims, "smooth", 3)
+    b = synthetic.wilson_spinor(dims, nv, 103)
+    U, B = up(u, "c128"), up(b, "c128")
+    bnorm = np.linalg.norm(b.reshape(-1, nv), axis=0)
+    sites = local.sample_sites(dims, 48, 11)
+    bs = local._at(b, sites)
+    for inner, itol, eo in (("bf16", 0.05, False), ("f16", 5e-3, True)):
+        x, info = D.solve("wilson", U, B, m0, inner=inner, tol=1e-10, inner_tol=itol, eo=eo)
+        say(f"inner={inner} eo={eo}: {info['inner_iters']} inner / {info['outer_iters']} outer, "
+            f"max relres {max(info['relres']):.2e}")
+        assert info["status"] == 0
+        assert max(info["relres"]) <= 1e-10
+        xh = down(x)
+        del x
+        torch.cuda.empty_cache()
+        r = bs - local.wilson_at(u, xh, m0, sites)
+        worst = np.abs(r).reshape(len(sites), -1, nv).max(axis=(0, 1))
+        say(f"sampled |b - D x| max per column / ||b||: {(worst / bnorm).max():.2e}")
+        assert np.all(worst <= 1e-10 * bnorm)
+        del xh
