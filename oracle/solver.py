@@ -8,7 +8,7 @@ checked against:
   axis of every field), stopping each column when ||r||/||b|| <= tol;
 * ``cgnr``: CG on the normal equations D^dag D x = D^dag b;
 * ``relative_residual``: ||b - D x||_2 / ||b||_2 per right-hand side, the
-  certificate every solve is judged by (several x meet a tolerance, so
+  certificate every solve is checked by (several x meet a tolerance, so
   residuals, not solutions, are compared).
 """
 from __future__ import annotations

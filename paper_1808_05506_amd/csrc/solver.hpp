@@ -1,4 +1,4 @@
-// Mixed-precision solver driver (host side of dslash_solve).
+// Mixed-precision solver: host-side sequencing of dslash_solve and dslash_solve_eo.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -40,7 +40,7 @@ def library_path() -> str:
 def _load():
     path = library_path()
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1808_05506_amd.build`")
     lib = ctypes.CDLL(path)
     vp, ip, i, d, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     lib.dslash_apply.argtypes = [i, vp, vp, vp, ip, i, i, d, i, vp]
