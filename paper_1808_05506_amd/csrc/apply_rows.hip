@@ -6,6 +6,8 @@
 // steps one workgroup through several consecutive t of the same (y, z).
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "rows.hpp"
 
@@ -161,6 +163,30 @@ __device__ __forceinline__ void own_commit(const RowChunk& c, const u32x4 (&r)[R
   u32x4* dst = reinterpret_cast<u32x4*>(buf) + (xc + 1) * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
+  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
+  u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
+  hdst[h < SP ? h : h - SP] = r[CH];
+}
+
+// Only the halo sites x0 - 1, x0 + n of the own row (its interior is already
+// in LDS), in slot CH; the other slots are cleared so that every call site
+// writes the whole register array.
+template <int NV, class S>
+__device__ __forceinline__ void own_halo_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm,
+                                               int xp, int tid, u32x4 (&r)[RowPieces<S>::CH + 1]) {
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(typename S::word)) / 16;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) r[j] = u32x4{0u, 0u, 0u, 0u};
+  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
+  const int hs = h < SP ? xm : xp;
+  r[CH] = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+}
+
+template <int NV, class S>
+__device__ __forceinline__ void own_halo_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+                                                typename S::word* buf, int tid) {
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(typename S::word)) / 16;
+  constexpr int SSP = SiteStride<NV, S>::PIECES;
   const int h = tid < 2 * SP ? tid : 2 * SP - 1;
   u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
   hdst[h < SP ? h : h - SP] = r[CH];
@@ -356,8 +382,8 @@ DSL_HD RowChunk march_chunk(const Geom& g, const MarchTraversal& m, uint32_t id,
   return c;
 }
 
-// Row K of a step's sequence (0 +y, 1 -y, 2 +z, 3 -z, 4 +t, 5 -t, 6 own) into
-// its register array.
+// Row K of a step's sequence (0 +y, 1 -y, 2 +z, 3 -z, 4 +t, 5 -t, 6 own, 7 the
+// own row's halo sites only) into its register array.
 template <int K, int NV, class S, int LW = 9>
 __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                             const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
@@ -372,6 +398,7 @@ __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, co
   if constexpr (K == 4) row_issue<3, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r4);
   if constexpr (K == 5) row_issue<3, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r5);
   if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);
+  if constexpr (K == 7) own_halo_issue<NV, S>(c, in, xm, xp, tid, r6);
 }
 
 // Sequence of staged rows in a step: all seven in the first step of a
@@ -379,6 +406,17 @@ __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, co
 template <bool FIRST> struct MarchSeq {
   static constexpr int N = FIRST ? 7 : 6;
   static constexpr int at(int p) { return FIRST ? p : (p < 5 ? p : 6); }
+};
+
+// Sequence of the own-buffer step: the own row first and the +t row last, into
+// the same buffer, so the +t row of step t is the own row of step t + 1 and a
+// later step stages only its two halo sites (K = 7).
+//   first step: own, +y, -y, +z, -z, -t, +t     later steps: halo, +y, -y, +z, -z, +t
+template <bool FIRST> struct MarchSeqO {
+  static constexpr int N = FIRST ? 7 : 6;
+  static constexpr int at(int p) {
+    return p == 0 ? (FIRST ? 6 : 7) : (p <= 4 ? p - 1 : (FIRST ? (p == 5 ? 5 : 4) : 4));
+  }
 };
 
 // Links of sites x0 - 1 .. x0 + n - 1 of a row (36 words each): up to 3
@@ -654,8 +692,131 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
   __syncthreads();
 }
 
-// PP: the two-buffer step (march_step_pp).
-template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, bool PP = false>
+// The step with three buffers: bo holds the own row (with its halo sites)
+// and receives the +t row at the end of the step, which is then the next
+// step's own row; ba and bb take the other rows in turn (one barrier per staged
+// row) and the output.  The diagonal term is folded into acc as -2 diag psi at
+// the start, since the own row is gone from bo when the output is formed.
+// LDS: bo [(R + 2) SSW], ba, bb [R SSW], lown, lnba, lnbb [R LW].
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
+__device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
+                                             const typename S::word* __restrict__ in,
+                                             typename S::word* __restrict__ out, typename S::word* bo,
+                                             typename S::word* ba, typename S::word* bb, typename S::word* lown,
+                                             typename S::word* lnba, typename S::word* lnbb, int xm, int xp, int xl,
+                                             int v, int tid, int nth, T diag, u32x4 (&r0)[RowPieces<S>::CH + 1],
+                                             u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
+                                             u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
+                                             u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
+                                             u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3]) {
+  using W = typename S::word;
+  using Q = MarchSeqO<FIRST>;
+  constexpr int LK = LinkK<S, NV, LW>::value;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
+  constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
+  constexpr int CF = ADJ ? +1 : -1, CB = -CF;
+#define DSL_OISSUE(P) march_issue<Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+  if constexpr (!FIRST) {
+    DSL_OISSUE(0);
+    if constexpr (DEPTH > 1) DSL_OISSUE(1);
+    if constexpr (DEPTH > 2) DSL_OISSUE(2);
+    links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
+  }
+  links_commit<S, LK, LW>(c, lr, lown, tid, nth);
+  if constexpr (FIRST)
+    own_commit<NV, S>(c, r6, bo, xl, v, tid);
+  else
+    own_halo_commit<NV, S>(c, r6, bo, tid);
+  __syncthreads();
+  if constexpr (DEPTH < Q::N) DSL_OISSUE(DEPTH);
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
+  {
+    if constexpr (!FIRST) reconstruct_add<3, CB, T>(acc, carry);
+    cpx<T> p[4][3];
+    lds_spinor<S, T, NV>(bo + (xl + 1) * SSW, v, p);
+    const T m2d = T(-2) * diag;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = rmadd(acc[sp][cc], m2d, p[sp][cc]);
+    // carry for the next step: U_t(x, t)^dag (1 + CB gamma_t) psi(x, t), projected
+    cpx<T> h[2][3];
+    project<3, CB, T>(p, h);
+    cpx<T> u[3][3];
+    load_link_lw<LW, S, T>(lown + (xl + 1) * 4 * LW + 3 * LW, u);
+    su3_mul2<true, T>(u, h, carry);
+  }
+  hold_acc<T>(acc);
+  lds_hop<0, CF, false, NV, S, T, LW>(bo + (xl + 2) * SSW, lown + (xl + 1) * 4 * LW, v, acc);
+  lds_hop<0, CB, true, NV, S, T, LW>(bo + xl * SSW, lown + xl * 4 * LW, v, acc);
+  hold_acc<T>(acc);
+  row_commit<+1, NV, S, LW>(c, r0, ba, lnba, xl, v, tid);
+  __syncthreads();
+  // row P (in buffer BUF) applied, then row P + 1 written to NBUF
+#define DSL_OSTEP(P, MU, SGN, BUF, LNB)                                  \
+  if constexpr (P + DEPTH < Q::N) DSL_OISSUE(P + DEPTH);                 \
+  row_compute<MU, SGN, ADJ, NV, S, T, LW>(BUF, lown, LNB, xl, v, acc);   \
+  hold_acc<T>(acc);
+#define DSL_OCOMMIT(SGN, CUR, BUF, LNB)                   \
+  row_commit<SGN, NV, S, LW>(c, CUR, BUF, LNB, xl, v, tid); \
+  __syncthreads();
+  DSL_OSTEP(1, 1, +1, ba, lnba)
+  DSL_OCOMMIT(-1, r1, bb, lnbb)
+  DSL_OSTEP(2, 1, -1, bb, lnbb)
+  DSL_OCOMMIT(+1, r2, ba, lnba)
+  DSL_OSTEP(3, 2, +1, ba, lnba)
+  DSL_OCOMMIT(-1, r3, bb, lnbb)
+  W* ob;
+  if constexpr (FIRST) {
+    DSL_OSTEP(4, 2, -1, bb, lnbb)
+    DSL_OCOMMIT(-1, r5, ba, lnba)
+    DSL_OSTEP(5, 3, -1, ba, lnba)
+    DSL_OCOMMIT(+1, r4, bo + SSW, lnbb)
+    DSL_OSTEP(6, 3, +1, bo + SSW, lnbb)
+    ob = bb;
+  } else {
+    DSL_OSTEP(4, 2, -1, bb, lnbb)
+    DSL_OCOMMIT(+1, r4, bo + SSW, lnba)
+    DSL_OSTEP(5, 3, +1, bo + SSW, lnba)
+    ob = ba;
+  }
+#undef DSL_OSTEP
+#undef DSL_OCOMMIT
+#undef DSL_OISSUE
+  // out = diag psi - 1/2 (hops) = -1/2 acc, through a free buffer
+  {
+    W* o = ob + xl * SSW;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        cpx<T> r;
+        r.r = T(-0.5) * acc[sp][cc].r;
+        r.i = T(-0.5) * acc[sp][cc].i;
+        S::template store<T>(o + (sp * 3 + cc) * NV + v, r);
+      }
+  }
+  __syncthreads();
+  {
+    const int xc = xl < c.n ? xl : c.n - 1;
+    const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * SSP;
+    u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
+    u32x4 rr[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) rr[j] = src[j * NV + v];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(rr[j], &dst[j * NV + v]);
+  }
+  __syncthreads();
+}
+
+// PP: 0 the one-buffer step (march_step), 1 two buffers in turn
+// (march_step_pp), 2 an own-row buffer plus two in turn (march_step_o).
+template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, int PP = 0>
 __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
@@ -665,8 +826,9 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   extern __shared__ uint4 smem_march[];
   const int R = int(m.sb);
   W* buf = reinterpret_cast<W*>(smem_march);
-  W* buf1 = buf + (R + 2) * SSW;  // PP only
-  W* lown = PP ? buf1 + (R + 2) * SSW : buf + (R + 2) * SSW;
+  W* buf1 = buf + (R + 2) * SSW;  // PP 1: the second buffer; PP 2: ba
+  W* buf2 = buf1 + R * SSW;       // PP 2: bb
+  W* lown = PP == 1 ? buf1 + (R + 2) * SSW : (PP == 2 ? buf2 + R * SSW : buf + (R + 2) * SSW);
   W* lnb = lown + (R + 1) * 4 * LW;
   W* lnb1 = lnb + R * LW;  // PP only
 
@@ -683,7 +845,7 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
   u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
-  using Q0 = MarchSeq<true>;
+  using Q0 = typename std::conditional<PP == 2, MarchSeqO<true>, MarchSeq<true>>::type;
 #define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
   DSL_PISSUE(0);
   if constexpr (DEPTH > 1) DSL_PISSUE(1);
@@ -692,7 +854,10 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   if constexpr (DEPTH > 4) DSL_PISSUE(4);
 #undef DSL_PISSUE
   links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
-  if constexpr (PP)
+  if constexpr (PP == 2)
+    march_step_o<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp, xl, v,
+                                                 tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+  else if constexpr (PP == 1)
     march_step_pp<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v, tid,
                                                   nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
   else
@@ -702,7 +867,10 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   for (int k = 1; k < steps; ++k) {
     c.t += 1;
     c.row_base += uint32_t(g.stride[3]);
-    if constexpr (PP)
+    if constexpr (PP == 2)
+      march_step_o<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp, xl, v,
+                                                    tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    else if constexpr (PP == 1)
       march_step_pp<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v,
                                                      tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
     else
@@ -712,23 +880,26 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
 }
 
 template <int DEPTH, int NV, class S, class T, int LW = 9>
-static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, bool pp, bool xcd, const void* U,
+static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int pp, bool xcd, const void* U,
                                  const void* in, void* out, double mass, hipStream_t st) {
   using W = typename S::word;
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
   size_t lds = rows_lds_words<NV, S, LW>(R) * sizeof(W);
-  if (pp) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
+  if (pp == 1) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
+  if (pp == 2) lds += (size_t(2 * R) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
 #define DSL_MK(A, P)                                                                                        \
   hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
                      (const W*)U, (const W*)in, (W*)out, diag)
-  if (pp) {
-    if (adj) DSL_MK(true, true); else DSL_MK(false, true);
+  if (pp == 2) {
+    if (adj) DSL_MK(true, 2); else DSL_MK(false, 2);
+  } else if (pp == 1) {
+    if (adj) DSL_MK(true, 1); else DSL_MK(false, 1);
   } else {
-    if (adj) DSL_MK(true, false); else DSL_MK(false, false);
+    if (adj) DSL_MK(true, 0); else DSL_MK(false, 0);
   }
 #undef DSL_MK
   return hipGetLastError();
@@ -964,24 +1135,26 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
   // 0 selects the kernel with one output row per workgroup).
   // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 2 marching, 3 otherwise).
-  // DSLASH_MARCH_PP: 1 = two row buffers (one barrier per staged row), 0 = one.
-  // Default: with FP32 storage, a lattice whose 16-step grid fits at two
-  // workgroups per CU (then all its workgroups are resident at once) marches
-  // 16 steps with two buffers; otherwise 8 steps with one.
+  // DSLASH_MARCH_PP: 0 = one row buffer, 1 = two used in turn (one barrier per
+  // staged row), 2 = an own-row buffer that keeps the +t row for the next step
+  // plus two used in turn.
+  // Default: FP32 and BF16 storage take the own-row buffer (FP16 one buffer);
+  // with FP32 storage, a lattice whose 16-step grid fits at two workgroups per
+  // CU (all its workgroups resident at once) marches 16 steps, otherwise 8.
   int tsteps = 8;
-  bool pp = false;
+  int pp = 0;
   if (const char* e = getenv("DSLASH_TSTEPS")) {
     tsteps = atoi(e);
-  } else if (dtype == DT_C64 && !compressed && !clover && g.n[3] >= 16) {
-    const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
-    const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
-    if (wgs <= 2u * uint32_t(device_cus())) {
-      tsteps = 16;
-      pp = true;
+  } else if (!compressed && !clover) {
+    if (dtype == DT_C64 || dtype == DT_BF16) pp = 2;
+    if (dtype == DT_C64 && g.n[3] >= 16) {
+      const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
+      const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
+      if (wgs <= 2u * uint32_t(device_cus())) tsteps = 16;
     }
   }
-  if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e) != 0;
-  if (compressed) pp = false;
+  if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e);
+  if (compressed || pp < 0 || pp > 2) pp = 0;
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
   // the clover term is fused into the one-row-per-workgroup kernel only;
   // compressed links are read by the t-marching kernel only

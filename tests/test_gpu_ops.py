@@ -212,11 +212,11 @@ def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
 @pytest.mark.parametrize("dims,tsteps", [((16, 2, 2, 11), "8"), ((12, 3, 2, 17), "8"), ((16, 2, 3, 7), "3"),
                                          ((16, 2, 2, 5), "1"), ((16, 2, 2, 4), "64"), ((13, 2, 2, 35), "16")])
 @pytest.mark.parametrize("adj", [False, True])
-@pytest.mark.parametrize("pp", ["0", "1"])
+@pytest.mark.parametrize("pp", ["0", "1", "2"])
 def test_wilson_march_segments(dims, tsteps, adj, pp, monkeypatch):
     # t-marching workgroups over several t segments, a partial last one, one
     # step per workgroup (no carried -t hop) and a segment longer than N_t,
-    # with one row buffer and with two used in turn
+    # with one row buffer, two used in turn, and an own-row buffer plus two
     nv, dt = 12, "c64"
     monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
     monkeypatch.setenv("DSLASH_MARCH_PP", pp)
@@ -226,21 +226,27 @@ def test_wilson_march_segments(dims, tsteps, adj, pp, monkeypatch):
     compare(down(out), wilson.apply(u, p, 0.1, adj), dt, "D_W march segments")
 
 
-def test_march_two_buffers_bitwise_equal_one_buffer(monkeypatch):
-    # 16^3 x 32, N_v = 12, FP32: the default launch marches 16 steps with two
-    # row buffers; the arithmetic is the single-buffer kernel's, so at the same
-    # segment length the results agree bit for bit, and both match the oracle
+def test_march_buffer_modes_on_the_headline_lattice(monkeypatch):
+    # 16^3 x 32, N_v = 12, FP32: the default launch marches 16 steps with the
+    # own-row buffer.  Two buffers in turn do the one-buffer kernel's arithmetic
+    # (bitwise equal at the same segment length); the own-row buffer folds the
+    # diagonal term into the accumulator (equal to rounding).  All match the oracle.
     dims, nv, dt = (16, 16, 16, 32), 12, "c64"
-    say("case wilson march two buffers vs one")
+    say("case wilson march buffer modes")
     u, p = _wil_fields(dims, nv, 85, 86, dt, "smooth")
     U, P = up(u, dt), up(p, dt)
+    ref = wilson.apply(u, p, 0.1)
     default = D.apply("wilson", U, P, 0.1)
+    compare(down(default), ref, dt, "D_W 16^3x32 default launch")
     monkeypatch.setenv("DSLASH_TSTEPS", "16")
-    monkeypatch.setenv("DSLASH_MARCH_PP", "0")
-    one = D.apply("wilson", U, P, 0.1)
+    outs = {}
+    for mode in ("0", "1", "2"):
+        monkeypatch.setenv("DSLASH_MARCH_PP", mode)
+        outs[mode] = D.apply("wilson", U, P, 0.1)
+        compare(down(outs[mode]), ref, dt, f"D_W 16^3x32 buffers mode {mode}")
     torch.cuda.synchronize()
-    assert torch.equal(default, one)
-    compare(down(default), wilson.apply(u, p, 0.1), dt, "D_W 16^3x32 default launch")
+    assert torch.equal(outs["0"], outs["1"])
+    assert torch.equal(outs["2"], default)
 
 
 @pytest.mark.parametrize("kernel", ["march", "rows"])
