@@ -11,7 +11,9 @@ R rotating (U, in, out) sets (default 4, about 1.4 GB) keep the working set
 well above the 256 MB Infinity Cache.  Each operator row is launched through
 the C ABI with its arguments marshalled once, and runs untimed for 0.1 s
 before its W warmup and K timed launches (the first tens of milliseconds of
-back-to-back launches are slower while the clocks settle).
+back-to-back launches are slower while the clocks settle).  ``us`` is the mean
+over the K launches between two events; ``us_median_single`` the median of 50
+further launches, each between its own pair of events.
 
 Further rows (``rows`` in the JSON line), each timed the same way:
 D_S 32^4 and 8^4, D_B 32^4 (FP32, FP64) with its W construction, D_W in
@@ -24,7 +26,8 @@ solve at 32^3 x 64 (time to
 full lattice and on the even-odd Schur complement).
 
 cpu_baseline: the FP64 numpy oracle applying the same operator on the host
-cores (BLAS pinned to one thread), on the full headline workload.
+cores (BLAS pinned to one thread), on the full headline workload, with the
+host's CPU model and thread environment variables.
 """
 from __future__ import annotations
 
@@ -34,6 +37,7 @@ import json
 import math
 import os
 import sys
+import statistics
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -115,6 +119,19 @@ def timed(torch, launch, steps: int, warmup: int) -> float:
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def median_single(torch, launch, count: int = 50) -> float:
+    """Median seconds of ``count`` launches, each between its own pair of events
+    on the current stream (enqueued back to back, so the GPU does not idle)."""
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    for i, (a, b) in enumerate(ev):
+        a.record(st)
+        launch(i)
+        b.record(st)
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in ev) / 1e3
+
+
 def rotated_sets(torch, U, P, count: int, C=None):
     """``count`` distinct input sets: lattice translations of (U, P[, C]) along t."""
     roll = lambda x, k: None if x is None else torch.roll(x, shifts=k, dims=0).contiguous()  # noqa: E731
@@ -162,12 +179,13 @@ def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, la
     launch = lambda i: launchers[i % len(launchers)]()  # noqa: E731
     settle(torch, launch)
     t = timed(torch, launch, steps, warmup)
+    t_med = median_single(torch, launch)
     nt, nz, ny, nx = P.shape[:4]
     vol = nt * nz * ny * nx
     nv = P.shape[-1] if P.dtype in (torch.complex64, torch.complex128) else P.shape[-2]
     flops = (FLOPS[op] + (CLOVER_FLOPS if clover is not None else 0)) * vol * nv
     nbytes = (site_bytes(op, nv, dtype_bytes, compressed) + (36 * dtype_bytes if clover is not None else 0)) * vol
-    row = {"us": t * 1e6, "gflops": flops / t / 1e9, "gbs": nbytes / t / 1e9,
+    row = {"us": t * 1e6, "us_median_single": t_med * 1e6, "gflops": flops / t / 1e9, "gbs": nbytes / t / 1e9,
            "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": flops,
            "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
     log(f"{label}: {t * 1e6:.1f} us  {row['gflops']:.0f} Gflop/s  {row['gbs']:.0f} GB/s")
@@ -191,7 +209,19 @@ def cpu_baseline(dims, nv, m0, min_seconds: float = 10.0):
             t_total += time.perf_counter() - t0
             reps += 1
     gflops = FLOPS["wilson"] * vol * nv * reps / t_total / 1e9
-    return {"value": gflops, "unit": "Gflop/s", "cores": 1, "kind": "oracle",
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads_env = {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+                   if k in os.environ}
+    return {"value": gflops, "unit": "Gflop/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model,
+            "threads_env": threads_env,
             "sample": f"{reps} full FP64 numpy applications of D_W (eq. def_wils, literal form) to the same "
                       f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} N_v={nv} workload, {t_total:.1f} s, BLAS pinned to 1 thread",
             "host_cpus": len(os.sched_getaffinity(0))}
@@ -475,6 +505,7 @@ def main():
         "warmup": args.warmup,
         "settle_seconds": SETTLE_SECONDS,
         "ms_per_step": t * 1e3,
+        "ms_median_single_launch": row["us_median_single"] / 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -165,7 +165,17 @@ def _validate(op: int, U: torch.Tensor, psi: torch.Tensor):
 def apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
           out: torch.Tensor | None = None, clover: torch.Tensor | None = None) -> torch.Tensor:
     """out = D psi (or D^dag psi), plus C psi for a clover field C from
-    ``clover_field`` (WILSON, BRILLOUIN); no autograd (see ``dslash``)."""
+    ``clover_field`` (WILSON, BRILLOUIN).  With gradients enabled and U or psi
+    requiring them (and no ``out`` or ``clover``), this is the autograd
+    operation ``dslash``: its backward returns (grad_U, grad_psi)."""
+    if (out is None and clover is None and torch.is_grad_enabled()
+            and (getattr(U, "requires_grad", False) or getattr(psi, "requires_grad", False))):
+        return _DslashFn.apply(op_code(op), U, psi, float(mass), bool(adjoint))
+    return _apply(op, U, psi, mass, adjoint, out, clover)
+
+
+def _apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: bool = False,
+           out: torch.Tensor | None = None, clover: torch.Tensor | None = None) -> torch.Tensor:
     op = op_code(op)
     lat, nv = _validate(op, U, psi)
     if out is None:
@@ -445,7 +455,7 @@ class _DslashFn(torch.autograd.Function):
     def forward(ctx, op, U, psi, mass, adjoint):
         ctx.op, ctx.mass, ctx.adjoint = op, mass, adjoint
         ctx.save_for_backward(U, psi)
-        return apply(op, U, psi, mass, adjoint)
+        return _apply(op, U, psi, mass, adjoint)
 
     @staticmethod
     def backward(ctx, g):
@@ -459,7 +469,7 @@ class _DslashFn(torch.autograd.Function):
             if need_u:
                 gU, _ = backward(ctx.op, U, psi, g, ctx.mass, True, False)
             if need_psi:
-                gpsi = apply(ctx.op, U, g, ctx.mass, adjoint=False)
+                gpsi = _apply(ctx.op, U, g, ctx.mass, adjoint=False)
         return None, gU, gpsi, None, None
 
 

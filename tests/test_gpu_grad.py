@@ -48,15 +48,18 @@ def test_autograd_gradcheck(op, adjoint):
     assert torch.autograd.gradcheck(fn, (U, P), eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
 
 
+@pytest.mark.parametrize("entry", ["dslash", "apply"])
 @pytest.mark.parametrize("op", ["staggered", "wilson"])
-def test_autograd_loss_gradient(op):
-    # L = Re sum conj(chi) (D psi): torch's gradient equals the oracle's link gradient
+def test_autograd_loss_gradient(op, entry):
+    # L = Re sum conj(chi) (D psi): torch's gradient equals the oracle's link
+    # gradient, through dslash and through apply on inputs that require grad
+    say(f"case autograd loss {op} via {entry}")
     dims, nv = (4, 4, 2, 2), 3
     u, chi, psi = _fields(op, dims, nv, 300, "c128")
     U = up(u, "c128").requires_grad_(True)
     P = up(psi, "c128").requires_grad_(True)
     C = up(chi, "c128")
-    L = (C.conj() * D.dslash(op, U, P, 0.1)).real.sum()
+    L = (C.conj() * getattr(D, entry)(op, U, P, 0.1)).real.sum()
     L.backward()
     compare(down(U.grad), grad.link_grad(op, chi, psi), "c128", f"autograd grad_U {op}")
     adj = staggered.apply(u, chi, 0.1, True) if op == "staggered" else wilson.apply(u, chi, 0.1, True)
