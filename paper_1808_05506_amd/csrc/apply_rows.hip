@@ -202,6 +202,126 @@ __device__ __forceinline__ void row_compute(const typename S::word* nbr, const t
     lds_hop<MU, (ADJ ? -1 : 1), true, NV, S, T, LW>(nbr + xl * SSW, lnb + xl * LW, v, acc);
 }
 
+// ---------------------------------------------------------------- half-spinor
+// rows (FP32 complex storage).  A hop reads its neighbour only through the
+// projection (1 + C gamma_mu) psi, two spin components per colour (eq. def_wils
+// with the chiral gamma matrices).  Lane (x, v) of a site loads, for the
+// right-hand-side pair q = v mod N_v/2, the two spins that form half-spin
+// component s = v div N_v/2 of that projection (spin s and its partner under
+// gamma_mu) in all three colours, projects them, and writes the half spinor
+// [s][c][N_v] of the site to LDS: half the LDS writes, reads and space of a full
+// row.  The projection is the same sum as in project(), so the results are
+// bit-identical to staging the full spinor.
+
+// Partner of spin 0 under gamma_mu (spin 1's partner is 5 minus it).
+template <int MU> struct HalfPartner { static constexpr int value = MU <= 1 ? 3 : 2; };
+
+// Site stride of a half-spinor row in LDS, padded like SiteStride.
+template <int NV, class S>
+struct HalfStride {
+  static constexpr int WB = int(sizeof(typename S::word));
+  static constexpr int SWD = 6 * NV * WB / 4;
+  static constexpr int WIN = NV * WB / 4;
+  static constexpr int PAD = (((WIN - SWD) % 64) + 64) % 64;
+  static constexpr int DW = (PAD <= SWD / 4 && (PAD * 4) % 16 == 0) ? SWD + PAD : SWD;
+  static constexpr int WORDS = DW * 4 / WB;
+  static constexpr int PIECES = DW * 4 / 16;
+};
+
+template <int MU, int SGN, int NV, class S, int LW = 9>
+__device__ __forceinline__ void half_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
+                                           const typename S::word* __restrict__ in, int xl, int v, int tid,
+                                           u32x4 (&r)[RowPieces<S>::CH + 1]) {
+  static_assert(sizeof(typename S::word) == 8 && NV % 2 == 0 && RowPieces<S>::CH == 6,
+                "half-spinor rows take FP32 complex storage and an even N_v");
+  constexpr int SW = 12 * NV, HP = NV / 2, P0 = HalfPartner<MU>::value;
+  const uint32_t nrow = row_base_shift(g, c, MU, SGN) + uint32_t(c.x0);
+  const int xc = xl < c.n ? xl : c.n - 1;
+  const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(nrow + xc) * SW);
+  const int hs = v >= HP ? 1 : 0, q = v - hs * HP;
+  const int sa = hs, sb = hs ? 5 - P0 : P0;
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    r[cc] = src[(sa * 3 + cc) * HP + q];
+    r[3 + cc] = src[(sb * 3 + cc) * HP + q];
+  }
+  if (SGN < 0) {
+    const int w = tid < c.n * LW ? tid : c.n * LW - 1;
+    const int k = w / LW, e = w - k * LW;
+    r[6] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * LW + e]);
+  } else {
+    r[6] = u32x4{0u, 0u, 0u, 0u};
+  }
+}
+
+template <int MU, int SGN, bool ADJ, int NV, class S, int LW = 9>
+__device__ __forceinline__ void half_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+                                            typename S::word* hrow, typename S::word* lnb, int xl, int v, int tid) {
+  using W = typename S::word;
+  constexpr int HP = NV / 2, HSP = HalfStride<NV, S>::PIECES;
+  constexpr int C = SGN > 0 ? (ADJ ? 1 : -1) : (ADJ ? -1 : 1);
+  const int xc = xl < c.n ? xl : c.n - 1;
+  const int hs = v >= HP ? 1 : 0, q = v - hs * HP;
+  // h_s = psi_s + sg X(psi_partner), X = C i (MU = 0, 2) or C (MU = 1, 3)
+  const float sg = MU == 0 ? -1.f : (MU == 3 ? 1.f : (hs ? 1.f : -1.f));
+  u32x4* dst = reinterpret_cast<u32x4*>(hrow) + xc * HSP + hs * 3 * HP + q;
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    // whole-vector bit casts (a bit cast of a vector element is miscompiled)
+    const f32x4 a = __builtin_bit_cast(f32x4, r[cc]), b = __builtin_bit_cast(f32x4, r[3 + cc]);
+    f32x4 x;
+    if constexpr (MU == 0 || MU == 2) {
+      x = f32x4{float(-C) * b.y, float(C) * b.x, float(-C) * b.w, float(C) * b.z};
+    } else {
+      x = f32x4{float(C) * b.x, float(C) * b.y, float(C) * b.z, float(C) * b.w};
+    }
+    const f32x4 h = f32x4{a.x + sg * x.x, a.y + sg * x.y, a.z + sg * x.z, a.w + sg * x.w};
+    dst[cc * HP] = __builtin_bit_cast(u32x4, h);
+  }
+  if (SGN < 0) lnb[tid < c.n * LW ? tid : c.n * LW - 1] = piece_to_word<W>(r[6]);
+}
+
+template <int MU, int SGN, bool ADJ, int NV, class S, class T>
+__device__ __forceinline__ void half_compute(const typename S::word* hrow, const typename S::word* lown,
+                                             const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
+  constexpr int HSW = HalfStride<NV, S>::WORDS;
+  constexpr int C = SGN > 0 ? (ADJ ? 1 : -1) : (ADJ ? -1 : 1);
+  const typename S::word* site = hrow + xl * HSW;
+  cpx<T> h[2][3];
+#pragma unroll
+  for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) h[hs][cc] = S::template load<T>(site + (hs * 3 + cc) * NV + v);
+  const typename S::word* link = SGN > 0 ? lown + (xl + 1) * 36 + MU * 9 : lnb + xl * 9;
+  cpx<T> u[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(link + a * 3 + b);
+  cpx<T> t[2][3];
+  su3_mul2<(SGN < 0), T>(u, h, t);
+  reconstruct_add<MU, C, T>(acc, t);
+}
+
+// Full or half-spinor staging of a neighbour row, by HALF.
+template <bool HALF, int MU, int SGN, bool ADJ, int NV, class S, int LW>
+__device__ __forceinline__ void o_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+                                         typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
+  if constexpr (HALF)
+    half_commit<MU, SGN, ADJ, NV, S, LW>(c, r, row, lnb, xl, v, tid);
+  else
+    row_commit<SGN, NV, S, LW>(c, r, row, lnb, xl, v, tid);
+}
+
+template <bool HALF, int MU, int SGN, bool ADJ, int NV, class S, class T, int LW>
+__device__ __forceinline__ void o_compute(const typename S::word* row, const typename S::word* lown,
+                                          const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
+  if constexpr (HALF)
+    half_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);
+  else
+    row_compute<MU, SGN, ADJ, NV, S, T, LW>(row, lown, lnb, xl, v, acc);
+}
+
 // Occupancy hint per prefetch depth: deeper prefetch holds more rows in
 // registers (about 28 VGPRs per FP32 row) and runs fewer waves per SIMD.
 template <int DEPTH> struct RowsWaves { static constexpr int value = DEPTH <= 2 ? 4 : (DEPTH <= 4 ? 3 : 2); };
@@ -399,6 +519,22 @@ __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, co
   if constexpr (K == 5) row_issue<3, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r5);
   if constexpr (K == 6) own_issue<NV, S>(c, in, xm, xp, xl, v, tid, r6);
   if constexpr (K == 7) own_halo_issue<NV, S>(c, in, xm, xp, tid, r6);
+}
+
+// march_issue with the neighbour rows (K = 0 .. 3 and 5) as half spinors.
+template <bool HALF, int K, int NV, class S, int LW = 9>
+__device__ __forceinline__ void march_issue_o(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
+                                              const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
+                                              int tid, u32x4 (&r0)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
+                                              u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1]) {
+  if constexpr (HALF && K == 0) half_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);
+  else if constexpr (HALF && K == 1) half_issue<1, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r1);
+  else if constexpr (HALF && K == 2) half_issue<2, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r2);
+  else if constexpr (HALF && K == 3) half_issue<2, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r3);
+  else if constexpr (HALF && K == 5) half_issue<3, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r5);
+  else march_issue<K, NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6);
 }
 
 // Sequence of staged rows in a step: all seven in the first step of a
@@ -698,7 +834,9 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
 // row) and the output.  The diagonal term is folded into acc as -2 diag psi at
 // the start, since the own row is gone from bo when the output is formed.
 // LDS: bo [(R + 2) SSW], ba, bb [R SSW], lown, lnba, lnbb [R LW].
-template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
+// HALF: the +-y, +-z and first -t rows go through ba and bb as half spinors
+// (ba, bb [R HSW], adjacent), and the output through ba and bb together.
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW, bool HALF = false>
 __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                              const typename S::word* __restrict__ in,
                                              typename S::word* __restrict__ out, typename S::word* bo,
@@ -715,7 +853,8 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
   constexpr int CF = ADJ ? +1 : -1, CB = -CF;
-#define DSL_OISSUE(P) march_issue<Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+#define DSL_OISSUE(P) \
+  march_issue_o<HALF, Q::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
   if constexpr (!FIRST) {
     DSL_OISSUE(0);
     if constexpr (DEPTH > 1) DSL_OISSUE(1);
@@ -754,42 +893,46 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
   lds_hop<0, CF, false, NV, S, T, LW>(bo + (xl + 2) * SSW, lown + (xl + 1) * 4 * LW, v, acc);
   lds_hop<0, CB, true, NV, S, T, LW>(bo + xl * SSW, lown + xl * 4 * LW, v, acc);
   hold_acc<T>(acc);
-  row_commit<+1, NV, S, LW>(c, r0, ba, lnba, xl, v, tid);
+  o_commit<HALF, 1, +1, ADJ, NV, S, LW>(c, r0, ba, lnba, xl, v, tid);
   __syncthreads();
   // row P (in buffer BUF) applied, then row P + 1 written to NBUF
-#define DSL_OSTEP(P, MU, SGN, BUF, LNB)                                  \
-  if constexpr (P + DEPTH < Q::N) DSL_OISSUE(P + DEPTH);                 \
-  row_compute<MU, SGN, ADJ, NV, S, T, LW>(BUF, lown, LNB, xl, v, acc);   \
+#define DSL_OSTEP(P, MU, SGN, H, BUF, LNB)                                     \
+  if constexpr (P + DEPTH < Q::N) DSL_OISSUE(P + DEPTH);                       \
+  o_compute<H, MU, SGN, ADJ, NV, S, T, LW>(BUF, lown, LNB, xl, v, acc);        \
   hold_acc<T>(acc);
-#define DSL_OCOMMIT(SGN, CUR, BUF, LNB)                   \
-  row_commit<SGN, NV, S, LW>(c, CUR, BUF, LNB, xl, v, tid); \
+#define DSL_OCOMMIT(MU, SGN, H, CUR, BUF, LNB)                  \
+  o_commit<H, MU, SGN, ADJ, NV, S, LW>(c, CUR, BUF, LNB, xl, v, tid); \
   __syncthreads();
-  DSL_OSTEP(1, 1, +1, ba, lnba)
-  DSL_OCOMMIT(-1, r1, bb, lnbb)
-  DSL_OSTEP(2, 1, -1, bb, lnbb)
-  DSL_OCOMMIT(+1, r2, ba, lnba)
-  DSL_OSTEP(3, 2, +1, ba, lnba)
-  DSL_OCOMMIT(-1, r3, bb, lnbb)
+  DSL_OSTEP(1, 1, +1, HALF, ba, lnba)
+  DSL_OCOMMIT(1, -1, HALF, r1, bb, lnbb)
+  DSL_OSTEP(2, 1, -1, HALF, bb, lnbb)
+  DSL_OCOMMIT(2, +1, HALF, r2, ba, lnba)
+  DSL_OSTEP(3, 2, +1, HALF, ba, lnba)
+  DSL_OCOMMIT(2, -1, HALF, r3, bb, lnbb)
   W* ob;
   if constexpr (FIRST) {
-    DSL_OSTEP(4, 2, -1, bb, lnbb)
-    DSL_OCOMMIT(-1, r5, ba, lnba)
-    DSL_OSTEP(5, 3, -1, ba, lnba)
-    DSL_OCOMMIT(+1, r4, bo + SSW, lnbb)
-    DSL_OSTEP(6, 3, +1, bo + SSW, lnbb)
-    ob = bb;
+    DSL_OSTEP(4, 2, -1, HALF, bb, lnbb)
+    DSL_OCOMMIT(3, -1, HALF, r5, ba, lnba)
+    DSL_OSTEP(5, 3, -1, HALF, ba, lnba)
+    DSL_OCOMMIT(3, +1, false, r4, bo + SSW, lnbb)
+    DSL_OSTEP(6, 3, +1, false, bo + SSW, lnbb)
+    ob = HALF ? ba : bb;
   } else {
-    DSL_OSTEP(4, 2, -1, bb, lnbb)
-    DSL_OCOMMIT(+1, r4, bo + SSW, lnba)
-    DSL_OSTEP(5, 3, +1, bo + SSW, lnba)
+    DSL_OSTEP(4, 2, -1, HALF, bb, lnbb)
+    DSL_OCOMMIT(3, +1, false, r4, bo + SSW, lnba)
+    DSL_OSTEP(5, 3, +1, false, bo + SSW, lnba)
     ob = ba;
   }
 #undef DSL_OSTEP
 #undef DSL_OCOMMIT
 #undef DSL_OISSUE
-  // out = diag psi - 1/2 (hops) = -1/2 acc, through a free buffer
+  // out = diag psi - 1/2 (hops) = -1/2 acc, through a free buffer (HALF: ba
+  // and bb together, with a site stride of 12 N_v + 4 words)
+  constexpr int OSW = HALF ? 12 * NV + 4 : SSW;
+  constexpr int OSP = OSW * int(sizeof(W)) / 16;
+  static_assert(!HALF || OSW <= 2 * HalfStride<NV, S>::WORDS, "the output fits ba and bb");
   {
-    W* o = ob + xl * SSW;
+    W* o = ob + xl * OSW;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -803,7 +946,7 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
   __syncthreads();
   {
     const int xc = xl < c.n ? xl : c.n - 1;
-    const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * SSP;
+    const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * OSP;
     u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
     u32x4 rr[CH];
 #pragma unroll
@@ -815,9 +958,12 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
 }
 
 // PP: 0 the one-buffer step (march_step), 1 two buffers in turn
-// (march_step_pp), 2 an own-row buffer plus two in turn (march_step_o).
+// (march_step_pp), 2 an own-row buffer plus two in turn (march_step_o), 3 the
+// same with half-spinor neighbour rows (FP32 storage).
+template <int PP, int DEPTH> struct MarchOcc { static constexpr int value = PP ? 2 : MarchWaves<DEPTH>::value; };
+
 template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, int PP = 0>
-__global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
+__global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
   using W = typename S::word;
@@ -826,9 +972,10 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   extern __shared__ uint4 smem_march[];
   const int R = int(m.sb);
   W* buf = reinterpret_cast<W*>(smem_march);
-  W* buf1 = buf + (R + 2) * SSW;  // PP 1: the second buffer; PP 2: ba
-  W* buf2 = buf1 + R * SSW;       // PP 2: bb
-  W* lown = PP == 1 ? buf1 + (R + 2) * SSW : (PP == 2 ? buf2 + R * SSW : buf + (R + 2) * SSW);
+  constexpr int BSW = PP == 3 ? HalfStride<NV, S>::WORDS : SSW;  // ba, bb site stride
+  W* buf1 = buf + (R + 2) * SSW;  // PP 1: the second buffer; PP 2, 3: ba
+  W* buf2 = buf1 + R * BSW;       // PP 2, 3: bb
+  W* lown = PP == 1 ? buf1 + (R + 2) * SSW : (PP >= 2 ? buf2 + R * BSW : buf + (R + 2) * SSW);
   W* lnb = lown + (R + 1) * 4 * LW;
   W* lnb1 = lnb + R * LW;  // PP only
 
@@ -845,8 +992,9 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
   u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
-  using Q0 = typename std::conditional<PP == 2, MarchSeqO<true>, MarchSeq<true>>::type;
-#define DSL_PISSUE(P) march_issue<Q0::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
+  using Q0 = typename std::conditional<PP >= 2, MarchSeqO<true>, MarchSeq<true>>::type;
+#define DSL_PISSUE(P) \
+  march_issue_o<PP == 3, Q0::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
   DSL_PISSUE(0);
   if constexpr (DEPTH > 1) DSL_PISSUE(1);
   if constexpr (DEPTH > 2) DSL_PISSUE(2);
@@ -854,9 +1002,10 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   if constexpr (DEPTH > 4) DSL_PISSUE(4);
 #undef DSL_PISSUE
   links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
-  if constexpr (PP == 2)
-    march_step_o<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp, xl, v,
-                                                 tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+  if constexpr (PP >= 2)
+    march_step_o<true, DEPTH, ADJ, NV, S, T, LW, PP == 3>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp,
+                                                          xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr,
+                                                          carry);
   else if constexpr (PP == 1)
     march_step_pp<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v, tid,
                                                   nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
@@ -867,9 +1016,10 @@ __global__ void __launch_bounds__(256, PP ? 2 : MarchWaves<DEPTH>::value)
   for (int k = 1; k < steps; ++k) {
     c.t += 1;
     c.row_base += uint32_t(g.stride[3]);
-    if constexpr (PP == 2)
-      march_step_o<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp, xl, v,
-                                                    tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    if constexpr (PP >= 2)
+      march_step_o<false, DEPTH, ADJ, NV, S, T, LW, PP == 3>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm,
+                                                             xp, xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr,
+                                                             carry);
     else if constexpr (PP == 1)
       march_step_pp<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v,
                                                      tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
@@ -889,12 +1039,19 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
   size_t lds = rows_lds_words<NV, S, LW>(R) * sizeof(W);
   if (pp == 1) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (pp == 2) lds += (size_t(2 * R) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
+  if (pp == 3) lds += (size_t(2 * R) * HalfStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   const T diag = T(4) + T(mass);
 #define DSL_MK(A, P)                                                                                        \
   hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
                      (const W*)U, (const W*)in, (W*)out, diag)
-  if (pp == 2) {
+  if (pp == 3) {
+    if constexpr (sizeof(W) == 8 && NV % 2 == 0 && LW == 9) {
+      if (adj) DSL_MK(true, 3); else DSL_MK(false, 3);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (pp == 2) {
     if (adj) DSL_MK(true, 2); else DSL_MK(false, 2);
   } else if (pp == 1) {
     if (adj) DSL_MK(true, 1); else DSL_MK(false, 1);
@@ -1134,11 +1291,13 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
   // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
   // 0 selects the kernel with one output row per workgroup).
-  // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 2 marching, 3 otherwise).
+  // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 3 with half-spinor
+  // rows, 2 otherwise when marching, 3 for the one-row kernel).
   // DSLASH_MARCH_PP: 0 = one row buffer, 1 = two used in turn (one barrier per
   // staged row), 2 = an own-row buffer that keeps the +t row for the next step
-  // plus two used in turn.
-  // Default: FP32 and BF16 storage take the own-row buffer (FP16 one buffer);
+  // plus two used in turn, 3 = the same with half-spinor neighbour rows (FP32
+  // storage only; others fall back to 2).
+  // Default: FP32 storage takes 3, BF16 storage 2, FP16 storage one buffer;
   // with FP32 storage, a lattice whose 16-step grid fits at two workgroups per
   // CU (all its workgroups resident at once) marches 16 steps, otherwise 8.
   int tsteps = 8;
@@ -1146,7 +1305,8 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (const char* e = getenv("DSLASH_TSTEPS")) {
     tsteps = atoi(e);
   } else if (!compressed && !clover) {
-    if (dtype == DT_C64 || dtype == DT_BF16) pp = 2;
+    if (dtype == DT_C64) pp = 3;
+    if (dtype == DT_BF16) pp = 2;
     if (dtype == DT_C64 && g.n[3] >= 16) {
       const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
       const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
@@ -1154,13 +1314,14 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
     }
   }
   if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e);
-  if (compressed || pp < 0 || pp > 2) pp = 0;
+  if (pp == 3 && dtype != DT_C64) pp = 2;
+  if (compressed || pp < 0 || pp > 3) pp = 0;
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
   // the clover term is fused into the one-row-per-workgroup kernel only;
   // compressed links are read by the t-marching kernel only
   if (compressed && (tsteps <= 0 || clover)) return hipErrorNotSupported;
   if (tsteps > 0 && !clover) {
-    const int depth = depth_env ? atoi(depth_env) : 2;
+    const int depth = depth_env ? atoi(depth_env) : (pp == 3 ? 3 : 2);
 #define DSL_MT(D, LW)                                                                                          \
   switch (dtype) {                                                                                             \
     case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \

@@ -24,6 +24,7 @@ namespace dsl {
 // which keeps arrays of it in scratch memory instead of registers).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <class T>
 struct cpx {

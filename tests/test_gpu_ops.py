@@ -212,11 +212,12 @@ def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
 @pytest.mark.parametrize("dims,tsteps", [((16, 2, 2, 11), "8"), ((12, 3, 2, 17), "8"), ((16, 2, 3, 7), "3"),
                                          ((16, 2, 2, 5), "1"), ((16, 2, 2, 4), "64"), ((13, 2, 2, 35), "16")])
 @pytest.mark.parametrize("adj", [False, True])
-@pytest.mark.parametrize("pp", ["0", "1", "2"])
+@pytest.mark.parametrize("pp", ["0", "1", "2", "3"])
 def test_wilson_march_segments(dims, tsteps, adj, pp, monkeypatch):
     # t-marching workgroups over several t segments, a partial last one, one
     # step per workgroup (no carried -t hop) and a segment longer than N_t,
-    # with one row buffer, two used in turn, and an own-row buffer plus two
+    # with one row buffer, two used in turn, an own-row buffer plus two, and
+    # the same with half-spinor neighbour rows
     nv, dt = 12, "c64"
     monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
     monkeypatch.setenv("DSLASH_MARCH_PP", pp)
@@ -230,7 +231,9 @@ def test_march_buffer_modes_on_the_headline_lattice(monkeypatch):
     # 16^3 x 32, N_v = 12, FP32: the default launch marches 16 steps with the
     # own-row buffer.  Two buffers in turn do the one-buffer kernel's arithmetic
     # (bitwise equal at the same segment length); the own-row buffer folds the
-    # diagonal term into the accumulator (equal to rounding).  All match the oracle.
+    # diagonal term into the accumulator (equal to rounding); staging the
+    # neighbour rows as half spinors does the same arithmetic as staging them
+    # whole (bitwise equal).  All match the oracle.
     dims, nv, dt = (16, 16, 16, 32), 12, "c64"
     say("case wilson march buffer modes")
     u, p = _wil_fields(dims, nv, 85, 86, dt, "smooth")
@@ -240,13 +243,14 @@ def test_march_buffer_modes_on_the_headline_lattice(monkeypatch):
     compare(down(default), ref, dt, "D_W 16^3x32 default launch")
     monkeypatch.setenv("DSLASH_TSTEPS", "16")
     outs = {}
-    for mode in ("0", "1", "2"):
+    for mode in ("0", "1", "2", "3"):
         monkeypatch.setenv("DSLASH_MARCH_PP", mode)
         outs[mode] = D.apply("wilson", U, P, 0.1)
         compare(down(outs[mode]), ref, dt, f"D_W 16^3x32 buffers mode {mode}")
     torch.cuda.synchronize()
     assert torch.equal(outs["0"], outs["1"])
     assert torch.equal(outs["2"], default)
+    assert torch.equal(outs["3"], outs["2"])
 
 
 @pytest.mark.parametrize("kernel", ["march", "rows"])
