@@ -466,41 +466,7 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
 // spinor per lane), so after the first step only six rows are staged per
 // output row: +y, -y, +z, -z, +t and the own row, and the +t row of one step
 // is the own row of the next, read again while it is still in L2.
-struct MarchTraversal {
-  uint32_t sb, chunks, rows;  // sites per chunk, chunks per x-row, chunks per t-plane
-  uint32_t T;                 // t steps per workgroup
-  FastDiv d_chunks, d_ny, d_rows;
-};
-
-inline MarchTraversal make_march_traversal(const Geom& g, uint32_t sb, uint32_t T) {
-  MarchTraversal m;
-  m.sb = sb;
-  m.chunks = (uint32_t(g.n[0]) + sb - 1) / sb;
-  m.rows = m.chunks * uint32_t(g.n[1]) * uint32_t(g.n[2]);
-  if (T < 1) T = 1;
-  if (T > uint32_t(g.n[3])) T = uint32_t(g.n[3]);
-  m.T = T;
-  m.d_chunks = FastDiv::make(m.chunks);
-  m.d_ny = FastDiv::make(uint32_t(g.n[1]));
-  m.d_rows = FastDiv::make(m.rows);
-  return m;
-}
-
-// Chunk `id` = (z Ny + y) chunks + chunk of t-plane t.
-DSL_HD RowChunk march_chunk(const Geom& g, const MarchTraversal& m, uint32_t id, int t) {
-  const uint32_t yz = m.d_chunks.div(id);
-  const uint32_t chunk = id - yz * m.chunks;
-  const uint32_t z = m.d_ny.div(yz);
-  const uint32_t y = yz - z * uint32_t(g.n[1]);
-  RowChunk c;
-  c.x0 = int(chunk * m.sb);
-  c.n = g.n[0] - c.x0 < int(m.sb) ? g.n[0] - c.x0 : int(m.sb);
-  c.y = int(y);
-  c.z = int(z);
-  c.t = t;
-  c.row_base = uint32_t(g.stride[1] * c.y + g.stride[2] * c.z + g.stride[3] * t);
-  return c;
-}
+// (MarchTraversal, make_march_traversal and march_chunk are in rows.hpp.)
 
 // Row K of a step's sequence (0 +y, 1 -y, 2 +z, 3 -z, 4 +t, 5 -t, 6 own, 7 the
 // own row's halo sites only) into its register array.

@@ -59,6 +59,44 @@ inline int row_sites_default(int nx, int nv) {
   return r;
 }
 
+// Traversal of the t-marching kernels: a workgroup owns the x-row chunk at
+// (y, z) for T consecutive t and steps through them.
+struct MarchTraversal {
+  uint32_t sb, chunks, rows;  // sites per chunk, chunks per x-row, chunks per t-plane
+  uint32_t T;                 // t steps per workgroup
+  FastDiv d_chunks, d_ny, d_rows;
+};
+
+inline MarchTraversal make_march_traversal(const Geom& g, uint32_t sb, uint32_t T) {
+  MarchTraversal m;
+  m.sb = sb;
+  m.chunks = (uint32_t(g.n[0]) + sb - 1) / sb;
+  m.rows = m.chunks * uint32_t(g.n[1]) * uint32_t(g.n[2]);
+  if (T < 1) T = 1;
+  if (T > uint32_t(g.n[3])) T = uint32_t(g.n[3]);
+  m.T = T;
+  m.d_chunks = FastDiv::make(m.chunks);
+  m.d_ny = FastDiv::make(uint32_t(g.n[1]));
+  m.d_rows = FastDiv::make(m.rows);
+  return m;
+}
+
+// Chunk `id` = (z Ny + y) chunks + chunk of t-plane t.
+DSL_HD RowChunk march_chunk(const Geom& g, const MarchTraversal& m, uint32_t id, int t) {
+  const uint32_t yz = m.d_chunks.div(id);
+  const uint32_t chunk = id - yz * m.chunks;
+  const uint32_t z = m.d_ny.div(yz);
+  const uint32_t y = yz - z * uint32_t(g.n[1]);
+  RowChunk c;
+  c.x0 = int(chunk * m.sb);
+  c.n = g.n[0] - c.x0 < int(m.sb) ? g.n[0] - c.x0 : int(m.sb);
+  c.y = int(y);
+  c.z = int(z);
+  c.t = t;
+  c.row_base = uint32_t(g.stride[1] * c.y + g.stride[2] * c.z + g.stride[3] * t);
+  return c;
+}
+
 DSL_HD int wrap_x(const Geom& g, int x) { return x < 0 ? x + g.n[0] : (x >= g.n[0] ? x - g.n[0] : x); }
 
 // LDS stride of one site in the row buffer, in storage words.  For a fixed

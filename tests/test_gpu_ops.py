@@ -272,36 +272,56 @@ def test_row_staged_determinism_across_chunk_sizes(kernel, monkeypatch):
 _SROW_DIMS = [(16, 4, 2, 6), (20, 2, 4, 6), (12, 2, 2, 4), (14, 2, 2, 2), (32, 2, 2, 2), (24, 4, 2, 2)]
 
 
-@pytest.mark.parametrize("kernel", ["rows", "direct"])
+@pytest.mark.parametrize("kernel", ["march", "rows", "direct"])
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("dims", _SROW_DIMS)
 def test_staggered_row_staged_path(kernel, dt, adj, dims, monkeypatch):
-    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged D_S kernel
+    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged D_S kernels:
+    # t-marching by default, one output row per workgroup with DSLASH_TSTEPS=0
     # (DSLASH_ROWS=0 forces the direct kernel); 20 sites split into 11 + 9,
     # 24 into 12 + 12, 32 into 16 + 16, 12 to 16 fill one chunk
     nv = 12
-    monkeypatch.setenv("DSLASH_ROWS", "1" if kernel == "rows" else "0")
+    monkeypatch.setenv("DSLASH_ROWS", "0" if kernel == "direct" else "1")
+    if kernel == "rows":
+        monkeypatch.setenv("DSLASH_TSTEPS", "0")
     say(f"case staggered {kernel} {dims} nv={nv} {dt} adj={adj}")
     u, p = _stag_fields(dims, nv, 71, 72, dt)
     out = D.apply("staggered", up(u, dt), up(p, dt), 0.15, adjoint=adj)
     compare(down(out), staggered.apply(u, p, 0.15, adj), dt, f"D_S {kernel}")
 
 
-@pytest.mark.parametrize("depth", ["3", "7"])
-def test_staggered_rows_determinism_across_chunk_sizes(depth, monkeypatch):
+@pytest.mark.parametrize("kernel,depth", [("rows", "3"), ("rows", "7"), ("march", "2"), ("march", "3"), ("march", "4")])
+def test_staggered_rows_determinism_across_chunk_sizes(kernel, depth, monkeypatch):
     dims, nv = (22, 4, 2, 4), 12
     monkeypatch.setenv("DSLASH_ROW_DEPTH", depth)
+    monkeypatch.setenv("DSLASH_TSTEPS", "0" if kernel == "rows" else "3")
     u, p = _stag_fields(dims, nv, 73, 74, "c64")
     U, P = up(u, "c64"), up(p, "c64")
     outs = []
     for r in ("12", "16", "21"):
         monkeypatch.setenv("DSLASH_ROW_SITES", r)
-        say(f"case staggered rows determinism R={r} depth={depth}")
+        say(f"case staggered {kernel} determinism R={r} depth={depth}")
         outs.append(D.apply("staggered", U, P, 0.0).cpu())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), staggered.apply(u, p, 0.0), "c64", "D_S rows R sweep")
+
+
+@pytest.mark.parametrize("dims,tsteps", [((16, 2, 2, 12), "8"), ((12, 4, 2, 18), "8"), ((16, 2, 4, 6), "4"),
+                                         ((16, 2, 2, 6), "1"), ((16, 2, 2, 4), "64"), ((20, 2, 2, 34), "16")])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_staggered_march_segments(dims, tsteps, adj, dt, monkeypatch):
+    # t-marching D_S (even extents, as the operator requires) over several t
+    # segments, a partial last one, one step per workgroup (no carried -t hop),
+    # a segment longer than N_t, and chunks of 11 + 9 sites
+    nv = 12
+    monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
+    say(f"case staggered march segments {dims} T={tsteps} {dt} adj={adj}")
+    u, p = _stag_fields(dims, nv, 75, 76, dt)
+    out = D.apply("staggered", up(u, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), staggered.apply(u, p, 0.1, adj), dt, "D_S march segments")
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
