@@ -281,7 +281,7 @@ __device__ __forceinline__ void half_commit(const RowChunk& c, const u32x4 (&r)[
   if (SGN < 0) lnb[tid < c.n * LW ? tid : c.n * LW - 1] = piece_to_word<W>(r[6]);
 }
 
-template <int MU, int SGN, bool ADJ, int NV, class S, class T>
+template <int MU, int SGN, bool ADJ, int NV, class S, class T, int LW = 9>
 __device__ __forceinline__ void half_compute(const typename S::word* hrow, const typename S::word* lown,
                                              const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
   constexpr int HSW = HalfStride<NV, S>::WORDS;
@@ -292,12 +292,16 @@ __device__ __forceinline__ void half_compute(const typename S::word* hrow, const
   for (int hs = 0; hs < 2; ++hs)
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) h[hs][cc] = S::template load<T>(site + (hs * 3 + cc) * NV + v);
-  const typename S::word* link = SGN > 0 ? lown + (xl + 1) * 36 + MU * 9 : lnb + xl * 9;
+  const typename S::word* link = SGN > 0 ? lown + (xl + 1) * 4 * LW + MU * LW : lnb + xl * LW;
   cpx<T> u[3][3];
+  if constexpr (LW == 9) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(link + a * 3 + b);
+      for (int b = 0; b < 3; ++b) u[a][b] = S::template load<T>(link + a * 3 + b);
+  } else {
+    load_link_lw<LW, S, T>(link, u);
+  }
   cpx<T> t[2][3];
   su3_mul2<(SGN < 0), T>(u, h, t);
   reconstruct_add<MU, C, T>(acc, t);
@@ -317,7 +321,7 @@ template <bool HALF, int MU, int SGN, bool ADJ, int NV, class S, class T, int LW
 __device__ __forceinline__ void o_compute(const typename S::word* row, const typename S::word* lown,
                                           const typename S::word* lnb, int xl, int v, cpx<T> (&acc)[4][3]) {
   if constexpr (HALF)
-    half_compute<MU, SGN, ADJ, NV, S, T>(row, lown, lnb, xl, v, acc);
+    half_compute<MU, SGN, ADJ, NV, S, T, LW>(row, lown, lnb, xl, v, acc);
   else
     row_compute<MU, SGN, ADJ, NV, S, T, LW>(row, lown, lnb, xl, v, acc);
 }
@@ -1012,7 +1016,7 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
   hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
                      (const W*)U, (const W*)in, (W*)out, diag)
   if (pp == 3) {
-    if constexpr (sizeof(W) == 8 && NV % 2 == 0 && LW == 9) {
+    if constexpr (sizeof(W) == 8 && NV % 2 == 0) {
       if (adj) DSL_MK(true, 3); else DSL_MK(false, 3);
     } else {
       return hipErrorInvalidValue;
@@ -1263,16 +1267,17 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // staged row), 2 = an own-row buffer that keeps the +t row for the next step
   // plus two used in turn, 3 = the same with half-spinor neighbour rows (FP32
   // storage only; others fall back to 2).
-  // Default: FP32 storage takes 3, BF16 storage 2, FP16 storage one buffer;
-  // with FP32 storage, a lattice whose 16-step grid fits at two workgroups per
-  // CU (all its workgroups resident at once) marches 16 steps, otherwise 8.
+  // Default: FP32 storage takes 3 (full or compressed links), BF16 storage 2,
+  // FP16 storage and other compressed links one buffer; with FP32 storage, a
+  // lattice whose 16-step grid fits at two workgroups per CU (all its
+  // workgroups resident at once) marches 16 steps, otherwise 8.
   int tsteps = 8;
   int pp = 0;
   if (const char* e = getenv("DSLASH_TSTEPS")) {
     tsteps = atoi(e);
-  } else if (!compressed && !clover) {
+  } else if (!clover) {
     if (dtype == DT_C64) pp = 3;
-    if (dtype == DT_BF16) pp = 2;
+    if (dtype == DT_BF16 && !compressed) pp = 2;
     if (dtype == DT_C64 && g.n[3] >= 16) {
       const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
       const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
@@ -1281,7 +1286,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   }
   if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e);
   if (pp == 3 && dtype != DT_C64) pp = 2;
-  if (compressed || pp < 0 || pp > 3) pp = 0;
+  if (pp < 0 || pp > 3 || (compressed && pp != 3)) pp = 0;
   const char* depth_env = getenv("DSLASH_ROW_DEPTH");
   // the clover term is fused into the one-row-per-workgroup kernel only;
   // compressed links are read by the t-marching kernel only
@@ -1295,7 +1300,11 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
     case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
   }
     if (compressed) {
-      DSL_MT(2, 6)
+      if (depth <= 2) {
+        DSL_MT(2, 6)
+      } else {
+        DSL_MT(3, 6)
+      }
     } else if (depth <= 2) {
       DSL_MT(2, 9)
     } else {

@@ -25,8 +25,8 @@ def test_compress_links_bit_exact(dt):
 
 
 # N_v = 12 at rows of 16 sites (and two chunks of 13) runs the row-staged
-# kernels (D_W: t-marching, FP32 arithmetic; D_S: C64, C128); the rest the
-# direct kernels.
+# kernels (D_W: t-marching, FP32 arithmetic, half-spinor rows for FP32
+# storage; D_S: C64, C128); the rest the direct kernels.
 @pytest.mark.parametrize("dt", ["c64", "c128", "bf16", "f16"])
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("dims,nv", [((4, 3, 2, 5), 1), ((6, 4, 2, 4), 3), ((16, 4, 2, 8), 12), ((26, 2, 2, 4), 12)])
@@ -36,6 +36,21 @@ def test_wilson_compressed_matches_oracle(dt, adj, dims, nv):
     p = rounded(synthetic.wilson_spinor(dims, nv, 73), dt)
     out = D.apply_compressed("wilson", up(vc, dt), up(p, dt), 0.1, adjoint=adj)
     compare(down(out), compress.apply("wilson", vc, p, 0.1, adj), dt, "D_W compressed")
+
+
+@pytest.mark.parametrize("pp", ["0", "3"])
+@pytest.mark.parametrize("adj", [False, True])
+def test_wilson_compressed_march_modes(pp, adj, monkeypatch):
+    # FP32 D_W on compressed links through the t-marching kernel over three
+    # t segments (8 + 8 + 4) with one row buffer and with half-spinor rows
+    dims, nv, dt = (16, 2, 4, 20), 12, "c64"
+    monkeypatch.setenv("DSLASH_TSTEPS", "8")
+    monkeypatch.setenv("DSLASH_MARCH_PP", pp)
+    say(f"case wilson compressed march pp={pp} adj={adj}")
+    vc = rounded(compress.compress(synthetic.gauge_links(dims, "haar", 80)), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 81), dt)
+    out = D.apply_compressed("wilson", up(vc, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), compress.apply("wilson", vc, p, 0.1, adj), dt, "D_W compressed march")
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128", "bf16"])
