@@ -27,7 +27,9 @@ full lattice and on the even-odd Schur complement).
 
 cpu_baseline: the FP64 numpy oracle applying the same operator on the host
 cores (BLAS pinned to one thread), on the full headline workload, with the
-host's CPU model and thread environment variables.
+host's CPU model and thread environment variables.  With the rows, the
+oracle's CGNR on an 8^4 lattice (two right-hand sides) is timed beside the GPU
+solve of the same system.
 """
 from __future__ import annotations
 
@@ -190,6 +192,39 @@ def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, la
            "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
     log(f"{label}: {t * 1e6:.1f} us  {row['gflops']:.0f} Gflop/s  {row['gbs']:.0f} GB/s")
     return row, t
+
+
+def solve_oracle_baseline(torch, D, np, synthetic, nv: int = 2):
+    """The oracle's FP64 CGNR for D_W x = b on 8^4, m0 = 0.05, smooth links
+    (seed 3), b the first nv of the 12 right-hand sides of seed 103 (a bounded
+    sample: all 12 take over a minute on one core), to a normal-equation
+    residual of 1e-10 with BLAS on one thread, beside the GPU solve of the same
+    system (FP32 inner CG, FP64 defect correction to ||b - D x|| / ||b|| <= 1e-10)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import solver, wilson
+    dims, m0 = (8, 8, 8, 8), 0.05
+    u = synthetic.gauge_links(dims, "smooth", 3)
+    b = np.ascontiguousarray(synthetic.wilson_spinor(dims, 12, 103)[..., :nv])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        x, iters, _ = solver.cgnr(lambda v: wilson.apply(u, v, m0), lambda v: wilson.apply(u, v, m0, True), b,
+                                  tol=1e-10)
+        t_oracle = time.perf_counter() - t0
+    true_res = float(np.max(solver.relative_residual(lambda v: wilson.apply(u, v, m0), b, x)))
+    U = torch.from_numpy(u).cuda()
+    B = torch.from_numpy(b).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg, info = D.solve("wilson", U, B, m0, inner="c64", tol=1e-10, inner_tol=1e-5)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    log(f"solve 8^4 N_v={nv}: oracle CGNR {t_oracle:.1f} s ({int(np.max(iters))} iterations, relres {true_res:.1e}), "
+        f"GPU {t_gpu:.3f} s")
+    return {"oracle_seconds": t_oracle, "oracle_iters": int(np.max(iters)), "oracle_relres": true_res,
+            "oracle_cores": 1, "gpu_seconds": t_gpu, "gpu_inner_iters": info["inner_iters"],
+            "gpu_max_relres": max(info["relres"]), "dims": list(dims), "nv": nv, "m0": m0,
+            "sample": f"the first {nv} of the 12 right-hand sides"}
 
 
 def cpu_baseline(dims, nv, m0, min_seconds: float = 10.0):
@@ -495,6 +530,8 @@ def main():
         rows = rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
 
     cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
+    if args.rows == "all" and not args.no_cpu:
+        rows["solve_wilson_8^4_oracle_vs_gpu"] = solve_oracle_baseline(torch, D, np, synthetic)
 
     out = {
         "metric": "Dslash Gflop/s + % HBM roofline (N_v=12, FP32); mixed-prec solve speedup",
