@@ -262,6 +262,28 @@ def cpu_baseline(dims, nv, m0, min_seconds: float = 10.0):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def staggered_rows_bench(torch, D, np, synthetic, steps, warmup):
+    """The D_S rows: 8^4, N_v = 4 (cache-resident, launch-bound) and 32^4, N_v = 12."""
+    rows = {}
+    dev = torch.device("cuda:0")
+
+    def up(a, dt):
+        return torch.from_numpy(a.astype(dt)).to(dev)
+
+    u = synthetic.gauge_links((8, 8, 8, 8), "haar", 0)
+    p = synthetic.staggered_spinor((8, 8, 8, 8), 4, 100)
+    rows["staggered_8^4_nv4_fp32"], _ = bench_apply(torch, D, "staggered", up(u, np.complex64), up(p, np.complex64),
+                                                    0.0, steps, warmup, 1, 8, "D_S 8^4 nv4")
+    dims = (32, 32, 32, 32)
+    U = up(synthetic.gauge_links(dims, "haar", 0), np.complex64)
+    P = up(synthetic.staggered_spinor(dims, 12, 100), np.complex64)
+    rows["staggered_32^4_nv12_fp32"], _ = bench_apply(torch, D, "staggered", U, P, 0.0, steps, warmup, 1, 8,
+                                                      "D_S 32^4 nv12")
+    del U, P
+    torch.cuda.empty_cache()
+    return rows
+
+
 def rows_bench(torch, D, np, synthetic, steps, warmup):
     rows = {}
     dev = torch.device("cuda:0")
@@ -269,18 +291,8 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     def up(a, dt):
         return torch.from_numpy(a.astype(dt)).to(dev)
 
-    # D_S 8^4, N_v = 4 (cache-resident, launch-bound)
-    u = synthetic.gauge_links((8, 8, 8, 8), "haar", 0)
-    p = synthetic.staggered_spinor((8, 8, 8, 8), 4, 100)
-    rows["staggered_8^4_nv4_fp32"], _ = bench_apply(torch, D, "staggered", up(u, np.complex64), up(p, np.complex64),
-                                                    0.0, steps, warmup, 1, 8, "D_S 8^4 nv4")
-    # D_S 32^4, N_v = 12
+    rows.update(staggered_rows_bench(torch, D, np, synthetic, steps, warmup))
     dims = (32, 32, 32, 32)
-    U = up(synthetic.gauge_links(dims, "haar", 0), np.complex64)
-    P = up(synthetic.staggered_spinor(dims, 12, 100), np.complex64)
-    rows["staggered_32^4_nv12_fp32"], _ = bench_apply(torch, D, "staggered", U, P, 0.0, steps, warmup, 1, 8,
-                                                      "D_S 32^4 nv12")
-    del U, P
     # D_B 32^4, N_v = 12, FP32 and FP64 (W built on the GPU, untimed setup)
     v = synthetic.gauge_links(dims, "haar", 2)
     p = synthetic.wilson_spinor(dims, 12, 102)
@@ -479,7 +491,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=4)
-    ap.add_argument("--rows", choices=["all", "none"], default="all")
+    ap.add_argument("--rows", choices=["all", "none", "staggered"], default="all",
+                    help="the other rows: all, none, or only the D_S ones")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain FP32 complex copy of this many MiB (counter calibration)")
@@ -529,6 +542,8 @@ def main():
     rows = {}
     if args.rows == "all":
         rows = rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
+    elif args.rows == "staggered":
+        rows = staggered_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
 
     cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
     if args.rows == "all" and not args.no_cpu:
