@@ -513,7 +513,8 @@ static hipError_t staggered_march_t(bool adj, const Geom& g, int R, int tsteps, 
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
-  const size_t lds = smarch_lds_words<NV, S, LW>(R) * sizeof(W);
+  size_t lds = smarch_lds_words<NV, S, LW>(R) * sizeof(W);
+  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
   if (adj)
     hipLaunchKernelGGL((staggered_march_kernel<DEPTH, true, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
                        (const W*)U, (const W*)in, (W*)out, T(mass));
