@@ -9,11 +9,17 @@ checked against:
 * ``cgnr``: CG on the normal equations D^dag D x = D^dag b;
 * ``relative_residual``: ||b - D x||_2 / ||b||_2 per right-hand side, the
   certificate every solve is checked by (several x meet a tolerance, so
-  residuals, not solutions, are compared).
+  residuals, not solutions, are compared);
+* ``wilson_residual_slab``: the squared norms that certificate needs for D_W
+  (Sec. 4, eq. def_wils), restricted to the time slices t0 <= t < t1, so a
+  lattice whose FP64 oracle application does not fit at once can be
+  certified slab by slab (the stencil reaches one slice in t).
 """
 from __future__ import annotations
 
 import numpy as np
+
+from . import wilson
 
 
 def _dot(a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -60,3 +66,24 @@ def cg(apply_a, b: np.ndarray, tol: float = 1e-12, maxiter: int = 10000, x0=None
 def cgnr(apply_d, apply_ddag, b: np.ndarray, tol: float = 1e-12, maxiter: int = 10000, x0=None):
     """CG on D^dag D x = D^dag b; tol applies to the normal-equation residual."""
     return cg(lambda v: apply_ddag(apply_d(v)), apply_ddag(b), tol, maxiter, x0)
+
+
+def wilson_residual_slab(V: np.ndarray, b: np.ndarray, x: np.ndarray, m0: float, t0: int, t1: int):
+    """(||r_v||^2, ||b_v||^2) per right-hand side v over the sites with
+    t0 <= t < t1, r = b - D_W x.
+
+    D_W x on those slices needs x and V on the slices t0 - 1 .. t1 only (one hop
+    in t; the backward link V_t(x - t) sits on slice t - 1).  The oracle's D_W
+    is applied to that periodic window of t1 - t0 + 2 slices and its two outer
+    slices, the only ones the window's own wrap reaches, are dropped.  Fields
+    are [Nt][Nz][Ny][Nx][...] arrays (memory maps work: only the window is
+    read).
+    """
+    nt = V.shape[0]
+    if not 0 <= t0 < t1 <= nt:
+        raise ValueError(f"need 0 <= t0 < t1 <= Nt, got {t0}, {t1}, {nt}")
+    rows = [(t0 - 1 + k) % nt for k in range(t1 - t0 + 2)]
+    dx = wilson.apply_hop(np.asarray(V[rows], dtype=np.complex128), np.asarray(x[rows], dtype=np.complex128),
+                          m0)[1:-1]
+    bs = np.asarray(b[t0:t1], dtype=np.complex128)
+    return norm2(bs - dx), norm2(bs)
