@@ -51,6 +51,16 @@ FP64_VALU_PEAK = 78.6e12
 FLOPS = {"staggered": 570, "wilson": 1320, "brillouin": 28224}   # per site and right-hand side
 CLOVER_FLOPS = 576             # two 6x6 complex matrix-vector products and their addition, per site and rhs
 
+# The mixed-precision solve of D_W x = b on 32^3 x 64, N_v = 12, m0 = 0.05 to
+# ||b - D x|| / ||b|| <= 1e-10: inner storage and inner tolerance of each timed
+# solve, full lattice and even-odd (the fastest setting of a sweep over the
+# inner tolerance on this system for each storage).
+SOLVE_DIMS, SOLVE_NV, SOLVE_M0, SOLVE_TOL = (32, 32, 32, 64), 12, 0.05, 1e-10
+SOLVE_SETTINGS = {
+    "full": (("c64", 1e-5), ("bf16", 0.02), ("f16", 2e-3)),
+    "eo": (("c64", 1e-5), ("bf16", 0.01), ("f16", 5e-3)),
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -192,6 +202,17 @@ def bench_apply(torch, D, op, U, P, mass, steps, warmup, rotate, dtype_bytes, la
            "dims": [nx, ny, nz, nt], "nv": nv, "rotate": rotate}
     log(f"{label}: {t * 1e6:.1f} us  {row['gflops']:.0f} Gflop/s  {row['gbs']:.0f} GB/s")
     return row, t
+
+
+def launch_row(torch, launch, steps, warmup, nbytes, rotate, label, single=50):
+    """Time ``launch`` as the operator rows are timed: settle, warmup, mean over
+    ``steps`` launches, median of ``single`` single launches."""
+    settle(torch, launch)
+    t = timed(torch, launch, steps, warmup)
+    t_med = median_single(torch, launch, single)
+    log(f"{label}: {t * 1e6:.1f} us (median single {t_med * 1e6:.1f} us), {nbytes / t / 1e9:.0f} GB/s")
+    return {"us": t * 1e6, "us_median_single": t_med * 1e6, "gbs": nbytes / t / 1e9,
+            "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "rotate": rotate}
 
 
 def solve_oracle_baseline(torch, D, np, synthetic, nv: int = 2):
@@ -382,34 +403,34 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
             del P
         del U, Uc
     torch.cuda.empty_cache()
-    # link gradients at 24^3 x 48, N_v = 12
+    # link gradients at 24^3 x 48, N_v = 12, timed like the operator rows
+    # (settle, warmup, mean over the timed launches, median single launch);
+    # D_S rotates two translated (chi, psi, G) sets so the footprint exceeds 1 GB
+    import ctypes
+    lib = D._lib
     dims = (24, 24, 24, 48)
+    vol = int(np.prod(dims))
+    dims_c = (ctypes.c_int * 4)(*dims)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     for op, kind, seed in (("staggered", "haar", 4), ("wilson", "smooth", 5)):
         gen = synthetic.staggered_spinor if op == "staggered" else synthetic.wilson_spinor
         U = up(synthetic.gauge_links(dims, kind, seed), np.complex64)
         C = up(gen(dims, 12, 104), np.complex64)
         P = up(gen(dims, 12, 105), np.complex64)
-        gU = torch.empty_like(U)
-        import ctypes
-        lib = D._lib
-        dims_c = (ctypes.c_int * 4)(*dims)
-        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        nrot = 2 if op == "staggered" else 1
+        sets = [(torch.roll(C, k, 0).contiguous(), torch.roll(P, k, 0).contiguous(), torch.empty_like(U))
+                for k in range(nrot)]
         code = D.op_code(op)
+        args = [(code, vp(U), vp(c), vp(p), vp(g), None, dims_c, 3, 12, 0.0, 0, stream) for c, p, g in sets]
 
-        def launch(i):
-            rc = lib.dslash_backward(code, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(C.data_ptr()),
-                                     ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(gU.data_ptr()), None, dims_c, 3,
-                                     12, 0.0, 0, stream)
-            if rc:
-                raise RuntimeError(f"dslash_backward failed: {rc}")
-        t = timed(torch, launch, steps, warmup)
-        vol = int(np.prod(dims))
+        def launch(i, args=args):
+            if lib.dslash_backward(*args[i % len(args)]):
+                raise RuntimeError("dslash_backward failed")
         nbytes = site_bytes(op, 12, 8) * vol
-        rows[f"link_grad_{op}_24^3x48_nv12_fp32"] = {"us": t * 1e6, "gbs": nbytes / t / 1e9,
-                                                     "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
-                                                     "bytes_per_launch": nbytes}
-        log(f"link grad {op}: {t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
-        del U, C, P, gU
+        rows[f"link_grad_{op}_24^3x48_nv12_fp32"] = launch_row(torch, launch, steps, warmup, nbytes, nrot,
+                                                               f"link grad {op}")
+        del U, C, P, sets
     torch.cuda.empty_cache()
     # Brillouin link gradient at 24^3 x 48, N_v = 12, FP32: with respect to the stored W
     # (dslash_backward), then through the W construction to V (dslash_brillouin_links_backward)
@@ -419,11 +440,6 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     P = up(synthetic.wilson_spinor(dims, 12, 105), np.complex64)
     gW = torch.empty_like(W)
     gV = torch.empty_like(V)
-    import ctypes
-    lib = D._lib
-    dims_c = (ctypes.c_int * 4)(*dims)
-    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
 
     def wgrad(i):
         if lib.dslash_backward(2, vp(W), vp(C), vp(P), vp(gW), None, dims_c, 3, 12, 0.0, 0, stream):
@@ -432,29 +448,24 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     def vgrad(i):
         if lib.dslash_brillouin_links_backward(vp(V), vp(gW), vp(gV), dims_c, 3, 0, stream):
             raise RuntimeError("dslash_brillouin_links_backward failed")
-    vol = int(np.prod(dims))
     nsteps = max(3, steps // 20)
-    tw = timed(torch, wgrad, nsteps, 1)
-    tv = timed(torch, vgrad, nsteps, 1)
     bw = (2 * 12 * 12 * 8 + 360 * 8) * vol   # chi and psi read, G_W written
     bv = (36 * 8 + 360 * 8 + 36 * 8) * vol   # V and G_W read, G_V written
-    rows["link_grad_brillouin_W_24^3x48_nv12_fp32"] = {"us": tw * 1e6, "gbs": bw / tw / 1e9,
-                                                       "hbm_frac": bw / tw / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bw}
-    rows["brillouin_links_backward_24^3x48_fp32"] = {"us": tv * 1e6, "gbs": bv / tv / 1e9,
-                                                     "hbm_frac": bv / tv / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": bv}
-    log(f"Brillouin link grad: W {tw * 1e6:.1f} us, through W to V {tv * 1e6:.1f} us")
+    rows["link_grad_brillouin_W_24^3x48_nv12_fp32"] = launch_row(torch, wgrad, nsteps, 1, bw, 1,
+                                                                 "Brillouin link grad (W)", single=10)
+    rows["brillouin_links_backward_24^3x48_fp32"] = launch_row(torch, vgrad, nsteps, 1, bv, 1,
+                                                               "Brillouin links backward (V)", single=10)
     del V, W, C, P, gW, gV
     torch.cuda.empty_cache()
     # mixed-precision solve, 32^3 x 64, N_v = 12, m0 = 0.05, smooth links
-    dims = (32, 32, 32, 64)
+    dims = SOLVE_DIMS
     U = up(synthetic.gauge_links(dims, "smooth", 3), np.complex128)
-    B = up(synthetic.wilson_spinor(dims, 12, 103), np.complex128)
-    # inner tolerances: the fastest of a sweep over 1e-3 .. 0.2 on this system
+    B = up(synthetic.wilson_spinor(dims, SOLVE_NV, 103), np.complex128)
     solve = {}
-    for inner, itol in (("c64", 1e-5), ("bf16", 0.02), ("f16", 2e-3)):
+    for inner, itol in SOLVE_SETTINGS["full"]:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = D.solve("wilson", U, B, 0.05, inner=inner, tol=1e-10, inner_tol=itol)
+        x, info = D.solve("wilson", U, B, SOLVE_M0, inner=inner, tol=SOLVE_TOL, inner_tol=itol)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         solve[inner] = {"seconds": t, "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],
@@ -468,10 +479,10 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
     rows["solve_wilson_32^3x64_nv12"] = solve
     # the same solves with the inner CG on the even-site Schur complement
     solve_eo = {}
-    for inner, itol in (("c64", 1e-5), ("bf16", 0.01), ("f16", 5e-3)):
+    for inner, itol in SOLVE_SETTINGS["eo"]:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = D.solve("wilson", U, B, 0.05, inner=inner, tol=1e-10, inner_tol=itol, eo=True)
+        x, info = D.solve("wilson", U, B, SOLVE_M0, inner=inner, tol=SOLVE_TOL, inner_tol=itol, eo=True)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         solve_eo[inner] = {"seconds": t, "inner_iters": info["inner_iters"], "outer_iters": info["outer_iters"],

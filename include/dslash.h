@@ -226,31 +226,46 @@ int dslash_convert(const void* src, int src_dtype, void* dst, int dst_dtype, siz
 /*
  * Workspace bytes dslash_solve needs for this problem (0 on bad arguments).
  */
-size_t dslash_solve_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype);
+size_t dslash_solve_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype);
 
 /*
- * Solve D x = b for all Nv right-hand sides (the paper has no solver; this is
- * the mixed-precision scheme of FP64 defect correction around an inner CG on
- * the normal equations D^dag D e = D^dag r).
- *   Outer loop, FP64 on the GPU:  r = b - D x, relres_v = ||r_v|| / ||b_v||;
+ * Solve D_W x = b for all Nv right-hand sides (the paper has no solver; this
+ * is the mixed-precision scheme of FP64 defect correction around an inner CG
+ * on the normal equations D_W^dag D_W e = D_W^dag r, for the Wilson operator
+ * of eq. def_wils at c_SW = 0).
+ *   Outer loop, FP64 on the GPU:  r = b - D_W x, relres_v = ||r_v|| / ||b_v||;
  *     stop when every relres_v <= tol.
- *   Inner loop: CG on D^dag D with links and vectors stored in inner_dtype
+ *   Inner loop: CG on D_W^dag D_W with links and vectors stored in inner_dtype
  *     (C64, BF16 or F16) and FP32 arithmetic, the right-hand side r scaled
  *     per column to unit RMS, run to inner_tol (relative, per column) or
  *     max_inner iterations; then x += scale * e in FP64.
  *   Inner products and norms are accumulated in FP64 in a fixed order.
- * op: STAGGERED or WILSON.  U64, b64: C128 device arrays; x64: C128 device
- * array holding the initial guess on entry and the solution on exit.
- * workspace: device memory of at least dslash_solve_workspace_bytes bytes.
+ * U64, b64: C128 device arrays (links [..][4][3][3], spinors [..][4][3][Nv]);
+ * U_lo: the same links stored in inner_dtype (e.g. from dslash_convert), read
+ * only, so repeated solves on one gauge field convert the links once; x64:
+ * C128 device array holding the initial guess on entry and the solution on
+ * exit.  workspace: device memory of at least dslash_solve_workspace_bytes
+ * bytes, owned by the caller.  x may not overlap b, U64, U_lo or the
+ * workspace (E_ALIAS).
  * final_relres (host, Nv doubles, nullable): true FP64 relative residuals.
- * iters (host, 2 ints, nullable): total inner iterations, outer iterations.
+ * iters (host, 2 * Nv ints, nullable): iters[v] = inner iterations run on
+ * column v, iters[Nv + v] = outer corrections applied to column v.
  * Synchronises the stream.  Returns E_NOCONV (x still updated) if max_outer
  * outer iterations did not reach tol.
  */
-int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
-                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer,
-                 int max_inner, void* workspace, size_t ws_bytes, double* final_relres, int* iters,
-                 void* stream);
+int dslash_solve(const void* U64, const void* U_lo, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                 void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream);
+
+/*
+ * dslash_solve for op = STAGGERED (Sec. 3) or WILSON, taking only the FP64
+ * links: the inner_dtype copy of the links is made in the workspace on every
+ * call.  Arguments and results as dslash_solve; op = BRILLOUIN -> E_ARG.
+ */
+size_t dslash_solve_op_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype);
+int dslash_solve_op(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                    double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                    void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream);
 
 /*
  * Even-odd (checkerboard) form of D_W, the eo-decomposition named as a next
@@ -291,8 +306,9 @@ size_t dslash_solve_eo_workspace_bytes(const int dims[4], int Nc, int Nv, int in
  * with the inner solve on the even-site Schur complement
  *   M = A - H_eo A^-1 H_oe:   M e_e = rhat_e - H_eo A^-1 rhat_o  (CG on M^dag M),
  *   e_o = A^-1 (rhat_o - H_oe e_e),
- * in inner_dtype storage (C64, BF16 or F16) with FP32 arithmetic.  All
- * extents must be even.  Synchronises the stream.
+ * in inner_dtype storage (C64, BF16 or F16) with FP32 arithmetic; the links
+ * are converted and packed in the workspace.  iters: 2 * Nv ints as for
+ * dslash_solve.  All extents must be even.  Synchronises the stream.
  */
 int dslash_solve_eo(const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv, double m0,
                     int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner, void* workspace,

@@ -39,8 +39,8 @@ Shape site_v_shape(uint32_t vol, int nv) {
   const int l = vc / gcd_int(vc, 64) * 64;
   int sb = l <= 256 ? l / vc : (256 / vc > 0 ? 256 / vc : 1);
   while (vc * sb * 2 <= 256 && l <= 256) sb *= 2;
-  if (const char* e = getenv("DSLASH_SITES_PER_BLOCK")) {
-    int v = atoi(e);
+  if (knobs().sites_per_block.set) {
+    const int v = knobs().sites_per_block.value;
     if (v > 0 && v * vc <= 256) sb = v;  // kernels are built for at most 256 threads
   }
   Shape sh;
@@ -68,9 +68,9 @@ static Launch make_launch(const Geom& g) {
   if (sb > uint32_t(g.n[0])) sb = g.n[0];
   L.rows = sb * vc >= 128;
   int bt = 8;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   L.xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) L.xcd = atoi(e) != 0;
+  L.xcd = knobs().xcd.get(1) != 0;
   if (L.rows) {
     L.tr = make_row_traversal(g, sb, uint32_t(bt > 0 ? bt : 1));
     L.sh.block.y = sb;

@@ -1010,7 +1010,7 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
   if (pp == 1) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (pp == 2) lds += (size_t(2 * R) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (pp == 3) lds += (size_t(2 * R) * HalfStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
-  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
+  lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
 #define DSL_MK(A, P)                                                                                        \
   hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
@@ -1181,21 +1181,20 @@ static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                  const void* in, void* out, const void* add, double c_add, double c_hop,
                                  hipStream_t st) {
-  if (const char* env = getenv("DSLASH_ROWS"))
-    if (atoi(env) == 0) return hipErrorNotSupported;
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   if (e.nv != 12) return hipErrorNotSupported;
   const int pdims[4] = {e.nh, e.n[1], e.n[2], e.n[3]};
   const Geom g = make_geom(pdims, e.nv);
   int R = row_sites_default(g.n[0], g.nv);
-  if (const char* env = getenv("DSLASH_ROW_SITES")) R = atoi(env);
+  R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
   const int word_bytes = int(dtype_bytes(dtype));
   if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
   int bt = 2;
-  if (const char* env = getenv("DSLASH_TBAND")) bt = atoi(env);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* env = getenv("DSLASH_XCD")) xcd = atoi(env) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   switch (dtype) {
     case DT_C64: return wilson_eo_rows_t<12, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
     case DT_BF16: return wilson_eo_rows_t<12, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
@@ -1212,7 +1211,7 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
   size_t lds = (rows_lds_words<NV, S>(R) + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   // DSLASH_ROW_LDS_EXTRA (bytes) lowers the workgroups per CU (tuning).
-  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
+  lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
 #define DSL_RK(A, CL)                                                                                      \
   hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, A, CL, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U, \
@@ -1244,11 +1243,10 @@ static int device_cus() {
 
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                               double mass, hipStream_t st, const void* clover, bool compressed) {
-  if (const char* e = getenv("DSLASH_ROWS"))
-    if (atoi(e) == 0) return hipErrorNotSupported;
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   if (g.nv != 12) return hipErrorNotSupported;
   int R = row_sites_default(g.n[0], g.nv);
-  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
   // the own row's two halo sites (2 * 12 N_v words) must be at most one
@@ -1256,9 +1254,9 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   const int word_bytes = int(dtype_bytes(dtype));
   if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
   int bt = 2;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
   // 0 selects the kernel with one output row per workgroup).
   // DSLASH_ROW_DEPTH: rows in flight per workgroup (default 3 with half-spinor
@@ -1273,8 +1271,8 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // workgroups resident at once) marches 16 steps, otherwise 8.
   int tsteps = 8;
   int pp = 0;
-  if (const char* e = getenv("DSLASH_TSTEPS")) {
-    tsteps = atoi(e);
+  if (knobs().tsteps.set) {
+    tsteps = knobs().tsteps.value;
   } else if (!clover) {
     if (dtype == DT_C64) pp = 3;
     if (dtype == DT_BF16 && !compressed) pp = 2;
@@ -1284,15 +1282,14 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
       if (wgs <= 2u * uint32_t(device_cus())) tsteps = 16;
     }
   }
-  if (const char* e = getenv("DSLASH_MARCH_PP")) pp = atoi(e);
+  pp = knobs().march_pp.get(pp);
   if (pp == 3 && dtype != DT_C64) pp = 2;
   if (pp < 0 || pp > 3 || (compressed && pp != 3)) pp = 0;
-  const char* depth_env = getenv("DSLASH_ROW_DEPTH");
   // the clover term is fused into the one-row-per-workgroup kernel only;
   // compressed links are read by the t-marching kernel only
   if (compressed && (tsteps <= 0 || clover)) return hipErrorNotSupported;
   if (tsteps > 0 && !clover) {
-    const int depth = depth_env ? atoi(depth_env) : (pp == 3 ? 3 : 2);
+    const int depth = knobs().row_depth.get(pp == 3 ? 3 : 2);
 #define DSL_MT(D, LW)                                                                                          \
   switch (dtype) {                                                                                             \
     case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
@@ -1313,7 +1310,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
 #undef DSL_MT
     return hipErrorNotSupported;
   }
-  const int depth = depth_env ? atoi(depth_env) : 3;
+  const int depth = knobs().row_depth.get(3);
 #define DSL_RT(D)                                                                               \
   switch (dtype) {                                                                              \
     case DT_C64: return wilson_rows_t<D, 12, C64, float>(adj, g, R, bt, xcd, U, in, out, clover, mass, st);   \

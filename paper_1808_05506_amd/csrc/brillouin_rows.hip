@@ -355,7 +355,7 @@ static int brillouin_rows_sites(int dtype, const Geom& g) {
   // FP32 only: the FP64 variant would not fit in registers
   if (g.nv != 12 || dtype != DT_C64) return 0;
   int R = row_sites_default(g.n[0], g.nv);
-  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
   // at least 12 sites: the halo sites (2 * 12 N_v words) take at most one
   // 16-byte piece per thread
@@ -368,14 +368,13 @@ static int brillouin_rows_sites(int dtype, const Geom& g) {
 // kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
                                  double mass, hipStream_t st, const void* clover) {
-  if (const char* e = getenv("DSLASH_ROWS"))
-    if (atoi(e) == 0) return hipErrorNotSupported;
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0) return hipErrorNotSupported;
   int bt = 2;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   return brillouin_rows_t<12, C64, float, false>(adj, g, R, bt, xcd, Wl, in, out, clover, mass, st);
 }
 
@@ -387,9 +386,9 @@ hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* 
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0) return hipErrorNotSupported;
   int bt = 2;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   return brillouin_rows_t<12, C64, float, true>(adj, g, R, bt, xcd, V, in, out, clover, mass, st);
 }
 

@@ -78,7 +78,7 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 105; }
+int dslash_version(void) { return 200; }
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
                         int Nv, double mass, int dtype, void* stream, const void* C = nullptr,
@@ -257,32 +257,25 @@ int dslash_convert(const void* src, int src_dtype, void* dst, int dst_dtype, siz
   return DSLASH_OK;
 }
 
-size_t dslash_solve_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype) {
-  if (check_geom(op, dims, Nc, Nv)) return 0;
-  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16) return 0;
-  return dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
-}
+static bool valid_inner(int dt) { return dt == DSLASH_C64 || dt == DSLASH_BF16 || dt == DSLASH_F16; }
 
-int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
-                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
-                 void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream) {
-  g_err[0] = 0;
+// Checks shared by the solve entry points; fills a with everything but the
+// workspace, the caller's links and the eo flag.
+static int solve_args(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                      double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                      double* final_relres, int* iters, void* stream, dsl::SolveArgs& a) {
   if (int rc = check_geom(op, dims, Nc, Nv)) return rc;
-  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16)
+  if (op == DSLASH_BRILLOUIN) return fail(DSLASH_E_ARG, "the solver is built for STAGGERED and WILSON (got BRILLOUIN)");
+  if (!valid_inner(inner_dtype))
     return fail(DSLASH_E_ARG, "inner dtype must be C64, BF16 or F16 (got %d)", inner_dtype);
   if (!U64 || !b64 || !x64) return fail(DSLASH_E_ARG, "NULL field pointer");
   if (!(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1)) return fail(DSLASH_E_ARG, "need tol > 0, 0 < inner_tol < 1");
   if (max_outer < 1 || max_inner < 1) return fail(DSLASH_E_ARG, "iteration limits must be >= 1");
-  const size_t need = dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
-  if (!workspace || ws_bytes < need)
-    return fail(DSLASH_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, workspace ? ws_bytes : size_t(0));
   const uint64_t vol = volume(dims);
   const size_t nspin = size_t(vol) * dsl::spinor_comps(op) * Nv * 16;
   const size_t nlink = size_t(vol) * dsl::links_per_site(op) * 9 * 16;
-  if (overlap(x64, nspin, b64, nspin) || overlap(x64, nspin, U64, nlink) || overlap(x64, nspin, workspace, need) ||
-      overlap(workspace, need, U64, nlink) || overlap(workspace, need, b64, nspin))
-    return fail(DSLASH_E_ALIAS, "x, b, U and workspace must not overlap");
-  dsl::SolveArgs a;
+  if (overlap(x64, nspin, b64, nspin) || overlap(x64, nspin, U64, nlink))
+    return fail(DSLASH_E_ALIAS, "x must not overlap b or U");
   a.op = op;
   a.U64 = U64;
   a.b64 = b64;
@@ -295,10 +288,66 @@ int dslash_solve(int op, const void* U64, const void* b64, void* x64, const int 
   a.inner_tol = inner_tol;
   a.max_outer = max_outer;
   a.max_inner = max_inner;
-  a.workspace = workspace;
   a.final_relres = final_relres;
   a.iters = iters;
   a.stream = (hipStream_t)stream;
+  return DSLASH_OK;
+}
+
+// The workspace must be large enough and overlap none of the caller's arrays.
+static int check_workspace(const dsl::SolveArgs& a, void* workspace, size_t ws_bytes, size_t need,
+                           const void* U_lo) {
+  if (!workspace || ws_bytes < need)
+    return fail(DSLASH_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, workspace ? ws_bytes : size_t(0));
+  const uint64_t vol = volume(a.dims);
+  const size_t nspin = size_t(vol) * dsl::spinor_comps(a.op) * a.nv * 16;
+  const size_t nlink = size_t(vol) * dsl::links_per_site(a.op) * 9 * 16;
+  const size_t nlo = size_t(vol) * dsl::links_per_site(a.op) * 9 * dsl::dtype_bytes(a.inner_dtype);
+  if (overlap(a.x64, nspin, workspace, need) || overlap(workspace, need, a.U64, nlink) ||
+      overlap(workspace, need, a.b64, nspin))
+    return fail(DSLASH_E_ALIAS, "x, b, U and workspace must not overlap");
+  if (U_lo && (overlap(U_lo, nlo, workspace, need) || overlap(U_lo, nlo, a.x64, nspin)))
+    return fail(DSLASH_E_ALIAS, "U_lo must not overlap x or the workspace");
+  return DSLASH_OK;
+}
+
+size_t dslash_solve_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype) {
+  if (check_geom(DSLASH_WILSON, dims, Nc, Nv) || !valid_inner(inner_dtype)) return 0;
+  return dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, false, false);
+}
+
+int dslash_solve(const void* U64, const void* U_lo, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                 double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                 void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream) {
+  g_err[0] = 0;
+  dsl::SolveArgs a;
+  if (int rc = solve_args(DSLASH_WILSON, U64, b64, x64, dims, Nc, Nv, mass, inner_dtype, tol, inner_tol, max_outer,
+                          max_inner, final_relres, iters, stream, a))
+    return rc;
+  if (!U_lo) return fail(DSLASH_E_ARG, "U_lo is NULL");
+  const size_t need = dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, false, false);
+  if (int rc = check_workspace(a, workspace, ws_bytes, need, U_lo)) return rc;
+  a.U_lo = U_lo;
+  a.workspace = workspace;
+  return dsl::solve(a);
+}
+
+size_t dslash_solve_op_workspace_bytes(int op, const int dims[4], int Nc, int Nv, int inner_dtype) {
+  if (check_geom(op, dims, Nc, Nv) || op == DSLASH_BRILLOUIN || !valid_inner(inner_dtype)) return 0;
+  return dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
+}
+
+int dslash_solve_op(int op, const void* U64, const void* b64, void* x64, const int dims[4], int Nc, int Nv,
+                    double mass, int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner,
+                    void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream) {
+  g_err[0] = 0;
+  dsl::SolveArgs a;
+  if (int rc = solve_args(op, U64, b64, x64, dims, Nc, Nv, mass, inner_dtype, tol, inner_tol, max_outer, max_inner,
+                          final_relres, iters, stream, a))
+    return rc;
+  const size_t need = dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
+  if (int rc = check_workspace(a, workspace, ws_bytes, need, nullptr)) return rc;
+  a.workspace = workspace;
   return dsl::solve(a);
 }
 
@@ -362,7 +411,7 @@ int dslash_eo_hop(const void* U_even, const void* U_odd, const void* in, void* o
 
 size_t dslash_solve_eo_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype) {
   if (check_geom(DSLASH_WILSON, dims, Nc, Nv) || check_even(dims)) return 0;
-  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16) return 0;
+  if (!valid_inner(inner_dtype)) return 0;
   return dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, true);
 }
 
@@ -370,40 +419,15 @@ int dslash_solve_eo(const void* U64, const void* b64, void* x64, const int dims[
                     int inner_dtype, double tol, double inner_tol, int max_outer, int max_inner, void* workspace,
                     size_t ws_bytes, double* final_relres, int* iters, void* stream) {
   g_err[0] = 0;
-  if (int rc = check_geom(DSLASH_WILSON, dims, Nc, Nv)) return rc;
+  dsl::SolveArgs a;
+  if (int rc = solve_args(DSLASH_WILSON, U64, b64, x64, dims, Nc, Nv, m0, inner_dtype, tol, inner_tol, max_outer,
+                          max_inner, final_relres, iters, stream, a))
+    return rc;
   if (int rc = check_even(dims)) return rc;
-  if (inner_dtype != DSLASH_C64 && inner_dtype != DSLASH_BF16 && inner_dtype != DSLASH_F16)
-    return fail(DSLASH_E_ARG, "inner dtype must be C64, BF16 or F16 (got %d)", inner_dtype);
-  if (!U64 || !b64 || !x64) return fail(DSLASH_E_ARG, "NULL field pointer");
-  if (!(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1)) return fail(DSLASH_E_ARG, "need tol > 0, 0 < inner_tol < 1");
-  if (max_outer < 1 || max_inner < 1) return fail(DSLASH_E_ARG, "iteration limits must be >= 1");
   if (!(4.0 + m0 != 0.0)) return fail(DSLASH_E_ARG, "4 + m0 must be non-zero");
   const size_t need = dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, true);
-  if (!workspace || ws_bytes < need)
-    return fail(DSLASH_E_WORKSPACE, "workspace needs %zu bytes, got %zu", need, workspace ? ws_bytes : size_t(0));
-  const uint64_t vol = volume(dims);
-  const size_t nspin = size_t(vol) * 12 * Nv * 16;
-  const size_t nlink = size_t(vol) * 36 * 16;
-  if (overlap(x64, nspin, b64, nspin) || overlap(x64, nspin, U64, nlink) || overlap(x64, nspin, workspace, need) ||
-      overlap(workspace, need, U64, nlink) || overlap(workspace, need, b64, nspin))
-    return fail(DSLASH_E_ALIAS, "x, b, U and workspace must not overlap");
-  dsl::SolveArgs a;
-  a.op = DSLASH_WILSON;
-  a.U64 = U64;
-  a.b64 = b64;
-  a.x64 = x64;
-  for (int i = 0; i < 4; ++i) a.dims[i] = dims[i];
-  a.nv = Nv;
-  a.mass = m0;
-  a.inner_dtype = inner_dtype;
-  a.tol = tol;
-  a.inner_tol = inner_tol;
-  a.max_outer = max_outer;
-  a.max_inner = max_inner;
+  if (int rc = check_workspace(a, workspace, ws_bytes, need, nullptr)) return rc;
   a.workspace = workspace;
-  a.final_relres = final_relres;
-  a.iters = iters;
-  a.stream = (hipStream_t)stream;
   a.eo = true;
   return dsl::solve(a);
 }

@@ -220,19 +220,18 @@ static hipError_t grad_rows_t(const Geom& g, int R, int bt, bool xcd, const void
 // uses the direct kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st) {
-  if (const char* e = getenv("DSLASH_ROWS"))
-    if (atoi(e) == 0) return hipErrorNotSupported;
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   if (g.nv != 12 || (op != OP_WILSON && op != OP_STAGGERED)) return hipErrorNotSupported;
   if (dtype != DT_C64 && !(dtype == DT_C128 && op == OP_STAGGERED)) return hipErrorNotSupported;
   int R = row_sites_default(g.n[0], g.nv);
-  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
   // t-band of the row traversal: 4 (2: 587 against 578 us for D_W at 24^3 x 48)
   int bt = 4;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   if (op == OP_WILSON) {
     return grad_rows_t<OP_WILSON, 12, C64, float>(g, R, bt, xcd, chi, psi, G, st);
   }

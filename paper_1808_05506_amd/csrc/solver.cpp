@@ -75,7 +75,7 @@ Layout layout_eo(const int dims[4], int nv, int lodt) {
   return L;
 }
 
-Layout layout(int op, const int dims[4], int nv, int lodt) {
+Layout layout(int op, const int dims[4], int nv, int lodt, bool own_links) {
   const size_t vol = size_t(dims[0]) * dims[1] * dims[2] * dims[3];
   const size_t comps = size_t(spinor_comps(op));
   Layout L;
@@ -89,7 +89,7 @@ Layout layout(int op, const int dims[4], int nv, int lodt) {
     return o;
   };
   const size_t eb = dtype_bytes(lodt);
-  L.u_lo = take(L.links_lo * eb);
+  L.u_lo = own_links ? take(L.links_lo * eb) : 0;
   L.e = take(L.field_lo * eb);
   L.r = take(L.field_lo * eb);
   L.p = take(L.field_lo * eb);
@@ -117,9 +117,47 @@ int hipfail(hipError_t e, const char* where) {
 
 }  // namespace
 
-size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype, bool eo) {
-  return eo ? layout_eo(dims, nv, inner_dtype).total : layout(op, dims, nv, inner_dtype).total;
+size_t solve_workspace_bytes(int op, const int dims[4], int nv, int inner_dtype, bool eo, bool own_links) {
+  return eo ? layout_eo(dims, nv, inner_dtype).total : layout(op, dims, nv, inner_dtype, own_links).total;
 }
+
+namespace {
+// Host-side per-column values of a solve: |b|^2, |r|^2, the active flags, the
+// scales, the relative residuals and the iteration counts.  Either views of the
+// caller's arrays (SolveArgs::host_d / host_i: kHostDoubles / kHostInts per
+// column), so that the solve allocates no memory at all, or owned vectors.
+struct HostBufs {
+  std::vector<double> own_d;
+  std::vector<int> own_i;
+  double *hb, *hr, *hact, *hsc, *relres;
+  int *inner, *outer;
+  int nv;
+  HostBufs(int n, double* ext_d, int* ext_i) : nv(n) {
+    if (!ext_d) {
+      own_d.assign(size_t(kHostDoubles) * n, 0.0);
+      ext_d = own_d.data();
+    }
+    if (!ext_i) {
+      own_i.assign(size_t(kHostInts) * n, 0);
+      ext_i = own_i.data();
+    }
+    hb = ext_d;
+    hr = hb + n;
+    hact = hr + n;
+    hsc = hact + n;  // 2 n: scale, then its inverse
+    relres = hsc + 2 * n;
+    inner = ext_i;
+    outer = ext_i + n;
+    for (int v = 0; v < n; ++v) relres[v] = 0.0, inner[v] = 0, outer[v] = 0;
+  }
+  void store(const SolveArgs& a) const {
+    if (a.final_relres)
+      for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];
+    if (a.iters)
+      for (int v = 0; v < nv; ++v) a.iters[v] = inner[v], a.iters[nv + v] = outer[v];
+  }
+};
+}  // namespace
 
 static int solve_eo(const SolveArgs& a);
 
@@ -127,9 +165,10 @@ int solve(const SolveArgs& a) {
   if (a.eo) return solve_eo(a);
   const int nv = a.nv;
   const int lodt = a.inner_dtype;
-  const Layout L = layout(a.op, a.dims, nv, lodt);
+  const bool own_links = a.U_lo == nullptr;
+  const Layout L = layout(a.op, a.dims, nv, lodt, own_links);
   unsigned char* ws = static_cast<unsigned char*>(a.workspace);
-  void* u_lo = ws + L.u_lo;
+  const void* u_lo = own_links ? static_cast<const void*>(ws + L.u_lo) : a.U_lo;
   void* e = ws + L.e;
   void* r = ws + L.r;
   void* p = ws + L.p;
@@ -148,20 +187,21 @@ int solve(const SolveArgs& a) {
   const int comps = spinor_comps(a.op);
   const double nelem = double(vol) * comps;
 
-  DSL_TRY(launch_convert(a.U64, DT_C128, u_lo, lodt, L.links_lo, st), "link conversion");
+  if (own_links)
+    DSL_TRY(launch_convert(a.U64, DT_C128, ws + L.u_lo, lodt, L.links_lo, st), "link conversion");
   DSL_TRY(launch_norm2(DT_C128, a.b64, vol, comps, nv, partial, nb2, st), "norm of b");
-  std::vector<double> hb(nv), hr(nv), hact(nv), hsc(2 * nv);
-  DSL_TRY(hipMemcpyAsync(hb.data(), nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
+  HostBufs h(nv, a.host_d, a.host_i);
+  double *hb = h.hb, *hr = h.hr, *hact = h.hact, *hsc = h.hsc, *relres = h.relres;
+  DSL_TRY(hipMemcpyAsync(hb, nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
   DSL_TRY(hipStreamSynchronize(st), "sync");
 
-  int total_inner = 0, outer = 0, status = DSLASH_OK;
-  std::vector<double> relres(nv, 0.0);
+  int outer = 0, status = DSLASH_OK;
   for (;;) {
     // r = b - D x in FP64
     DSL_TRY(launch_apply(a.op, false, DT_C128, g, a.U64, a.x64, t64, a.mass, st), "outer apply");
     DSL_TRY(launch_xmy(a.b64, t64, r64, L.field64, st), "outer residual");
     DSL_TRY(launch_norm2(DT_C128, r64, vol, comps, nv, partial, nr2, st), "outer norm");
-    DSL_TRY(hipMemcpyAsync(hr.data(), nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
+    DSL_TRY(hipMemcpyAsync(hr, nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
     DSL_TRY(hipStreamSynchronize(st), "sync");
     bool done = true;
     for (int v = 0; v < nv; ++v) {
@@ -179,9 +219,10 @@ int solve(const SolveArgs& a) {
       const bool work = relres[v] > a.tol && hr[v] > 0;
       const double rms = sqrt(hr[v] / nelem);
       hsc[v] = work ? rms : 0.0;
+      h.outer[v] += work;
       hsc[nv + v] = work ? 1.0 / rms : 0.0;
     }
-    DSL_TRY(hipMemcpyAsync(scale, hsc.data(), 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
+    DSL_TRY(hipMemcpyAsync(scale, hsc, 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
     DSL_TRY(launch_scale_to(r64, lodt, q, inv, vol, comps, nv, st), "scale residual");
     // inner CG on D^dag D e = D^dag rhat
     DSL_TRY(launch_apply(a.op, true, lodt, g, u_lo, q, r, a.mass, st), "inner rhs");
@@ -190,7 +231,7 @@ int solve(const SolveArgs& a) {
     DSL_TRY(launch_norm2(lodt, r, vol, comps, nv, partial, rr, st), "inner norm");
     DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
     for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
-    DSL_TRY(hipMemcpyAsync(active, hact.data(), nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    DSL_TRY(hipMemcpyAsync(active, hact, nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
     for (int k = 0; k < a.max_inner; ++k) {
       DSL_TRY(launch_apply(a.op, false, lodt, g, u_lo, p, q, a.mass, st), "inner D p");
       DSL_TRY(launch_norm2(lodt, q, vol, comps, nv, partial, pq, st), "|Dp|^2");
@@ -199,8 +240,8 @@ int solve(const SolveArgs& a) {
       DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, vol, comps, nv, partial, rr_new, st), "x/r update");
       DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
       DSL_TRY(launch_cg_update_p(lodt, p, r, beta, vol, comps, nv, st), "p update");
-      ++total_inner;
-      DSL_TRY(hipMemcpyAsync(hact.data(), active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
+      for (int v = 0; v < nv; ++v) h.inner[v] += hact[v] != 0.0;
+      DSL_TRY(hipMemcpyAsync(hact, active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
       DSL_TRY(hipStreamSynchronize(st), "sync");
       bool any = false;
       for (int v = 0; v < nv; ++v) any = any || hact[v] != 0.0;
@@ -208,12 +249,7 @@ int solve(const SolveArgs& a) {
     }
     DSL_TRY(launch_axpy_promote(a.x64, lodt, e, scale, vol, comps, nv, st), "x update");
   }
-  if (a.final_relres)
-    for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];
-  if (a.iters) {
-    a.iters[0] = total_inner;
-    a.iters[1] = outer;
-  }
+  h.store(a);
   return status;
 }
 
@@ -259,17 +295,17 @@ static int solve_eo(const SolveArgs& a) {
   DSL_TRY(launch_eo_copy(true, eg, 0, u_full, u_even, link_site, st), "pack even links");
   DSL_TRY(launch_eo_copy(true, eg, 1, u_full, u_odd, link_site, st), "pack odd links");
   DSL_TRY(launch_norm2(DT_C128, a.b64, vol, comps, nv, partial, nb2, st), "norm of b");
-  std::vector<double> hb(nv), hr(nv), hact(nv), hsc(2 * nv);
-  DSL_TRY(hipMemcpyAsync(hb.data(), nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
+  HostBufs h(nv, a.host_d, a.host_i);
+  double *hb = h.hb, *hr = h.hr, *hact = h.hact, *hsc = h.hsc, *relres = h.relres;
+  DSL_TRY(hipMemcpyAsync(hb, nb2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |b|^2");
   DSL_TRY(hipStreamSynchronize(st), "sync");
 
-  int total_inner = 0, outer = 0, status = DSLASH_OK;
-  std::vector<double> relres(nv, 0.0);
+  int outer = 0, status = DSLASH_OK;
   for (;;) {
     DSL_TRY(launch_apply(OP_WILSON, false, DT_C128, g, a.U64, a.x64, t64, a.mass, st), "outer apply");
     DSL_TRY(launch_xmy(a.b64, t64, r64, L.field64, st), "outer residual");
     DSL_TRY(launch_norm2(DT_C128, r64, vol, comps, nv, partial, nr2, st), "outer norm");
-    DSL_TRY(hipMemcpyAsync(hr.data(), nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
+    DSL_TRY(hipMemcpyAsync(hr, nr2, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy |r|^2");
     DSL_TRY(hipStreamSynchronize(st), "sync");
     bool done = true;
     for (int v = 0; v < nv; ++v) {
@@ -286,9 +322,10 @@ static int solve_eo(const SolveArgs& a) {
       const bool work = relres[v] > a.tol && hr[v] > 0;
       const double rms = sqrt(hr[v] / nelem);
       hsc[v] = work ? rms : 0.0;
+      h.outer[v] += work;
       hsc[nv + v] = work ? 1.0 / rms : 0.0;
     }
-    DSL_TRY(hipMemcpyAsync(scale, hsc.data(), 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
+    DSL_TRY(hipMemcpyAsync(scale, hsc, 2 * nv * sizeof(double), hipMemcpyHostToDevice, st), "copy scales");
     DSL_TRY(launch_scale_to(r64, lodt, rfull, inv, vol, comps, nv, st), "scale residual");
     DSL_TRY(launch_eo_copy(true, eg, 0, rfull, re, spin_site, st), "pack even residual");
     DSL_TRY(launch_eo_copy(true, eg, 1, rfull, ro, spin_site, st), "pack odd residual");
@@ -300,7 +337,7 @@ static int solve_eo(const SolveArgs& a) {
     DSL_TRY(launch_norm2(lodt, r, hvol, comps, nv, partial, rr, st), "inner norm");
     DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
     for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
-    DSL_TRY(hipMemcpyAsync(active, hact.data(), nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    DSL_TRY(hipMemcpyAsync(active, hact, nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
     for (int k = 0; k < a.max_inner; ++k) {
       DSL_TRY(schur(false, p, q), "inner M p");
       DSL_TRY(launch_norm2(lodt, q, hvol, comps, nv, partial, pq, st), "|Mp|^2");
@@ -309,8 +346,8 @@ static int solve_eo(const SolveArgs& a) {
       DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, hvol, comps, nv, partial, rr_new, st), "x/r update");
       DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
       DSL_TRY(launch_cg_update_p(lodt, p, r, beta, hvol, comps, nv, st), "p update");
-      ++total_inner;
-      DSL_TRY(hipMemcpyAsync(hact.data(), active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
+      for (int v = 0; v < nv; ++v) h.inner[v] += hact[v] != 0.0;
+      DSL_TRY(hipMemcpyAsync(hact, active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
       DSL_TRY(hipStreamSynchronize(st), "sync");
       bool any = false;
       for (int v = 0; v < nv; ++v) any = any || hact[v] != 0.0;
@@ -322,12 +359,7 @@ static int solve_eo(const SolveArgs& a) {
     DSL_TRY(launch_eo_copy(false, eg, 1, eodd, rfull, spin_site, st), "unpack odd");
     DSL_TRY(launch_axpy_promote(a.x64, lodt, rfull, scale, vol, comps, nv, st), "x update");
   }
-  if (a.final_relres)
-    for (int v = 0; v < nv; ++v) a.final_relres[v] = relres[v];
-  if (a.iters) {
-    a.iters[0] = total_inner;
-    a.iters[1] = outer;
-  }
+  h.store(a);
   return status;
 }
 

@@ -514,7 +514,7 @@ static hipError_t staggered_march_t(bool adj, const Geom& g, int R, int tsteps, 
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
   size_t lds = smarch_lds_words<NV, S, LW>(R) * sizeof(W);
-  if (const char* e = getenv("DSLASH_ROW_LDS_EXTRA")) lds += size_t(atoi(e));
+  lds += size_t(knobs().row_lds_extra.get(0));
   if (adj)
     hipLaunchKernelGGL((staggered_march_kernel<DEPTH, true, NV, S, T, LW>), grid, block, lds, st, g, m, int(xcd),
                        (const W*)U, (const W*)in, (W*)out, T(mass));
@@ -545,25 +545,24 @@ static hipError_t staggered_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 // kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_staggered_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st, bool compressed) {
-  if (const char* e = getenv("DSLASH_ROWS"))
-    if (atoi(e) == 0) return hipErrorNotSupported;
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   if (g.nv != 12 || (dtype != DT_C64 && dtype != DT_C128)) return hipErrorNotSupported;
   int R = row_sites_default(g.n[0], g.nv);
-  if (const char* e = getenv("DSLASH_ROW_SITES")) R = atoi(e);
+  R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
   // R >= 11 also gives every thread at most one piece of the own row's halo
   // (2 sites of 3 N_v words) and one word of a row's backward links (9 n words)
   if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
   int bt = 4;
-  if (const char* e = getenv("DSLASH_TBAND")) bt = atoi(e);
+  bt = knobs().tband.get(bt);
   bool xcd = true;
-  if (const char* e = getenv("DSLASH_XCD")) xcd = atoi(e) != 0;
+  xcd = knobs().xcd.get(xcd) != 0;
   int depth = 3;
-  if (const char* e = getenv("DSLASH_ROW_DEPTH")) depth = atoi(e);
+  depth = knobs().row_depth.get(depth);
   // DSLASH_TSTEPS: t steps per workgroup of the t-marching kernel (default 8;
   // 0 selects the kernel with one output row per workgroup)
   int tsteps = 8;
-  if (const char* e = getenv("DSLASH_TSTEPS")) tsteps = atoi(e);
+  tsteps = knobs().tsteps.get(tsteps);
   if (tsteps > 0) {
 #define DSL_SMT(D, LW)                                                                                          \
   return dtype == DT_C64 ? staggered_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st) \

@@ -48,10 +48,14 @@ def _load():
     lib.dslash_backward.argtypes = [i, vp, vp, vp, vp, vp, ip, i, i, d, i, vp]
     lib.dslash_brillouin_links.argtypes = [vp, vp, ip, i, i, vp]
     lib.dslash_convert.argtypes = [vp, i, vp, i, sz, vp]
-    lib.dslash_solve_workspace_bytes.argtypes = [i, ip, i, i, i]
+    lib.dslash_solve_workspace_bytes.argtypes = [ip, i, i, i]
     lib.dslash_solve_workspace_bytes.restype = sz
-    lib.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+    lib.dslash_solve.argtypes = [vp, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                  ctypes.POINTER(ctypes.c_double), ip, vp]
+    lib.dslash_solve_op_workspace_bytes.argtypes = [i, ip, i, i, i]
+    lib.dslash_solve_op_workspace_bytes.restype = sz
+    lib.dslash_solve_op.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                                    ctypes.POINTER(ctypes.c_double), ip, vp]
     lib.dslash_eo_pack.argtypes = [vp, vp, vp, ip, sz, vp]
     lib.dslash_eo_unpack.argtypes = [vp, vp, vp, ip, sz, vp]
     lib.dslash_eo_hop.argtypes = [vp, vp, vp, vp, ip, i, i, i, i, i, vp]
@@ -68,8 +72,8 @@ def _load():
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
-                 "dslash_convert", "dslash_solve", "dslash_version", "dslash_eo_pack", "dslash_eo_unpack",
-                 "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
+                 "dslash_convert", "dslash_solve", "dslash_solve_op", "dslash_version", "dslash_eo_pack",
+                 "dslash_eo_unpack", "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
                  "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward", "dslash_apply_brillouin_fly"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -351,44 +355,71 @@ def convert(x: torch.Tensor, dtype: str) -> torch.Tensor:
 
 def solve(op, U: torch.Tensor, b: torch.Tensor, mass: float, inner: str = "bf16", tol: float = 1e-10,
           inner_tol: float = 0.05, max_outer: int = 100, max_inner: int = 20000, x0: torch.Tensor | None = None,
-          eo: bool = False):
+          eo: bool = False, U_lo: torch.Tensor | None = None):
     """Solve D x = b by FP64 defect correction around a low-precision CG on D^dag D.
 
-    U, b: complex128.  eo=True (WILSON only): the inner solve runs on the
-    even-site Schur complement (dslash_solve_eo).  Returns (x, info) with
-    info = {relres: per-column FP64 ||b - D x||/||b||, inner_iters,
-    outer_iters, status}.  Raises on argument errors; non-convergence is
-    reported in info['status'] (5).
+    U, b: complex128.  WILSON runs ``dslash_solve`` with the links in the inner
+    storage ``U_lo`` (converted from U here when not given, so a caller solving
+    repeatedly on one gauge field can convert once with ``convert``);
+    STAGGERED runs ``dslash_solve_op``.  eo=True (WILSON only): the inner solve
+    runs on the even-site Schur complement (``dslash_solve_eo``).  x0: initial
+    guess, complex128 of b's shape on b's device (not modified).  Returns
+    (x, info) with info = {relres: per-column FP64 ||b - D x||/||b||,
+    inner_iters_per_column, outer_iters_per_column, inner_iters and
+    outer_iters (their maxima over the columns), status}.  Raises ValueError
+    on bad arguments before any library call; non-convergence is reported in
+    info['status'] (5).
     """
     op = op_code(op)
     lat, nv = _validate(op, U, b)
     if U.dtype != torch.complex128:
         raise ValueError("solve takes complex128 links and right-hand sides")
+    if op == BRILLOUIN:
+        raise ValueError("the solver is built for STAGGERED and WILSON")
     if eo and op != WILSON:
         raise ValueError("the even-odd solve is built for WILSON only")
-    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    if inner not in ("c64", "bf16", "f16"):
+        raise ValueError(f"inner storage must be 'c64', 'bf16' or 'f16' (got {inner!r})")
+    if x0 is not None:
+        _require(x0, "x0")
+        if x0.device != b.device or x0.dtype != torch.complex128 or x0.shape != b.shape:
+            raise ValueError("x0 must be a complex128 tensor of b's shape on b's device")
     code = _NAMES[inner]
+    use_lo = op == WILSON and not eo
+    if U_lo is not None:
+        if not use_lo:
+            raise ValueError("U_lo is taken by the full-lattice Wilson solve only")
+        _require(U_lo, "U_lo")
+        if U_lo.device != U.device or _dtype_code(U_lo) != code or _core_shape(U_lo) != tuple(U.shape):
+            raise ValueError(f"U_lo must be the links of U stored as {inner} on U's device")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
     dims = _dims_c(lat)
     if eo:
         nbytes = _lib.dslash_solve_eo_workspace_bytes(dims, 3, nv, code)
+    elif use_lo:
+        nbytes = _lib.dslash_solve_workspace_bytes(dims, 3, nv, code)
     else:
-        nbytes = _lib.dslash_solve_workspace_bytes(op, dims, 3, nv, code)
+        nbytes = _lib.dslash_solve_op_workspace_bytes(op, dims, 3, nv, code)
     if nbytes == 0:
         raise ValueError(f"unsupported solver configuration (inner={inner}, eo={eo})")
+    if use_lo and U_lo is None:
+        U_lo = convert(U, inner)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
     relres = (ctypes.c_double * nv)()
-    iters = (ctypes.c_int * 2)()
+    iters = (ctypes.c_int * (2 * nv))()
+    rest = (dims, 3, nv, float(mass), code, float(tol), float(inner_tol), int(max_outer), int(max_inner), _ptr(ws),
+            nbytes, relres, iters, _stream(b))
     if eo:
-        rc = _lib.dslash_solve_eo(_ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
-                                  float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
-                                  _stream(b))
+        name, rc = "dslash_solve_eo", _lib.dslash_solve_eo(_ptr(U), _ptr(b), _ptr(x), *rest)
+    elif use_lo:
+        name, rc = "dslash_solve", _lib.dslash_solve(_ptr(U), _ptr(U_lo), _ptr(b), _ptr(x), *rest)
     else:
-        rc = _lib.dslash_solve(op, _ptr(U), _ptr(b), _ptr(x), dims, 3, nv, float(mass), code, float(tol),
-                               float(inner_tol), int(max_outer), int(max_inner), _ptr(ws), nbytes, relres, iters,
-                               _stream(b))
+        name, rc = "dslash_solve_op", _lib.dslash_solve_op(op, _ptr(U), _ptr(b), _ptr(x), *rest)
     if rc not in (0, 5):
-        raise DslashError(rc, "dslash_solve_eo" if eo else "dslash_solve")
-    return x, {"relres": list(relres), "inner_iters": iters[0], "outer_iters": iters[1], "status": rc}
+        raise DslashError(rc, name)
+    inner_cols, outer_cols = list(iters[:nv]), list(iters[nv:])
+    return x, {"relres": list(relres), "inner_iters_per_column": inner_cols, "outer_iters_per_column": outer_cols,
+               "inner_iters": max(inner_cols), "outer_iters": max(outer_cols), "status": rc}
 
 
 def _site_bytes(t: torch.Tensor) -> int:

@@ -24,10 +24,14 @@ def lib():
     l.dslash_backward.argtypes = [i, vp, vp, vp, vp, vp, ip, i, i, d, i, vp]
     l.dslash_brillouin_links.argtypes = [vp, vp, ip, i, i, vp]
     l.dslash_convert.argtypes = [vp, i, vp, i, sz, vp]
-    l.dslash_solve_workspace_bytes.argtypes = [i, ip, i, i, i]
+    l.dslash_solve_workspace_bytes.argtypes = [ip, i, i, i]
     l.dslash_solve_workspace_bytes.restype = sz
-    l.dslash_solve.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+    l.dslash_solve.argtypes = [vp, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
                                ctypes.POINTER(ctypes.c_double), ip, vp]
+    l.dslash_solve_op_workspace_bytes.argtypes = [i, ip, i, i, i]
+    l.dslash_solve_op_workspace_bytes.restype = sz
+    l.dslash_solve_op.argtypes = [i, vp, vp, vp, ip, i, i, d, i, d, d, i, i, vp, sz,
+                                  ctypes.POINTER(ctypes.c_double), ip, vp]
     l.dslash_eo_pack.argtypes = [vp, vp, vp, ip, sz, vp]
     l.dslash_eo_unpack.argtypes = [vp, vp, vp, ip, sz, vp]
     l.dslash_eo_hop.argtypes = [vp, vp, vp, vp, ip, i, i, i, i, i, vp]
@@ -51,10 +55,24 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 21
+    assert len(declared) == 23
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 105
+    assert lib.dslash_version() == 200
+
+
+def test_solve_signatures_follow_the_header():
+    # the full-lattice Wilson solve takes the FP64 links, the caller's
+    # low-precision links and per-column iteration counts; the op-taking
+    # variant converts the links itself
+    text = " ".join(open(HEADER).read().split())
+    assert ("size_t dslash_solve_workspace_bytes(const int dims[4], int Nc, int Nv, int inner_dtype);" in text)
+    assert ("int dslash_solve(const void* U64, const void* U_lo, const void* b64, void* x64, const int dims[4], "
+            "int Nc, int Nv, double mass, int inner_dtype, double tol, double inner_tol, int max_outer, "
+            "int max_inner, void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream);"
+            in text)
+    assert "iters (host, 2 * Nv ints, nullable)" in text
+    assert "int dslash_solve_op(int op, const void* U64, const void* b64, void* x64," in text
 
 
 def test_status_strings(lib):
@@ -106,18 +124,34 @@ def test_links_convert_validation(lib):
 
 def test_solve_validation(lib):
     d = _dims(4, 4, 4, 4)
-    assert lib.dslash_solve_workspace_bytes(1, d, 3, 2, 2) > 0
-    assert lib.dslash_solve_workspace_bytes(1, d, 3, 2, 1) == 0   # C128 inner not allowed
-    assert lib.dslash_solve_workspace_bytes(1, d, 4, 2, 2) == 0
+    L = 0x30000000                                                  # fake low-precision links
+    assert lib.dslash_solve_workspace_bytes(d, 3, 2, 2) > 0
+    assert lib.dslash_solve_workspace_bytes(d, 3, 2, 1) == 0        # C128 inner not allowed
+    assert lib.dslash_solve_workspace_bytes(d, 4, 2, 2) == 0
+    # the caller's links take no workspace
+    assert lib.dslash_solve_workspace_bytes(d, 3, 2, 2) < lib.dslash_solve_op_workspace_bytes(1, d, 3, 2, 2)
     rel = (ctypes.c_double * 2)()
-    it = (ctypes.c_int * 2)()
-    ws_need = lib.dslash_solve_workspace_bytes(1, d, 3, 2, 2)
-    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, None, 0, rel, it, None) == 6
-    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, 0x20000000, ws_need - 1, rel, it, None) == 6
-    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, -1.0, 0.1, 10, 100, 0x20000000, ws_need, rel, it, None) == 1
-    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 1.5, 10, 100, 0x20000000, ws_need, rel, it, None) == 1
-    assert lib.dslash_solve(1, A, B, C, d, 3, 2, 0.05, 0, 1e-10, 0.1, 0, 100, 0x20000000, ws_need, rel, it, None) == 1
-    assert lib.dslash_solve(1, A, B, B, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, 0x20000000, ws_need, rel, it, None) == 3
+    it = (ctypes.c_int * 4)()
+    ws = 0x20000000
+    need = lib.dslash_solve_workspace_bytes(d, 3, 2, 2)
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, None, 0, rel, it, None) == 6
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, need - 1, rel, it, None) == 6
+    assert lib.dslash_solve(A, None, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, need, rel, it, None) == 1
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 2, -1.0, 0.1, 10, 100, ws, need, rel, it, None) == 1
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 2, 1e-10, 1.5, 10, 100, ws, need, rel, it, None) == 1
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 0, 1e-10, 0.1, 0, 100, ws, need, rel, it, None) == 1
+    assert lib.dslash_solve(A, L, B, B, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, need, rel, it, None) == 3
+    assert lib.dslash_solve(A, ws, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, need, rel, it, None) == 3
+    assert lib.dslash_solve(A, L, B, C, d, 3, 2, 0.05, 1, 1e-10, 0.1, 10, 100, ws, need, rel, it, None) == 1
+    # the op-taking variant: STAGGERED and WILSON only
+    need_op = lib.dslash_solve_op_workspace_bytes(1, d, 3, 2, 2)
+    assert lib.dslash_solve_op_workspace_bytes(2, d, 3, 2, 2) == 0
+    assert lib.dslash_solve_op(2, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, 1 << 30, rel, it, None) == 1
+    assert b"BRILLOUIN" in lib.dslash_last_error()
+    assert lib.dslash_solve_op(1, A, B, C, d, 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, need_op - 1, rel, it,
+                               None) == 6
+    assert lib.dslash_solve_op(0, A, B, C, _dims(4, 3, 4, 4), 3, 2, 0.05, 2, 1e-10, 0.1, 10, 100, ws, 1 << 30, rel,
+                               it, None) == 1
 
 
 def test_binding_rejects_cpu_tensors():
@@ -146,7 +180,7 @@ def test_even_odd_validation(lib):
     assert lib.dslash_solve_eo_workspace_bytes(even, 3, 2, 1) == 0          # FP64 inner
     assert lib.dslash_solve_eo_workspace_bytes(even, 3, 2, 2) > 0
     rel = (ctypes.c_double * 2)()
-    it = (ctypes.c_int * 2)()
+    it = (ctypes.c_int * 4)()
     assert lib.dslash_solve_eo(A, B, C, odd, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1
     assert lib.dslash_solve_eo(A, B, C, even, 3, 2, 0.1, 2, 1e-10, 0.1, 10, 10, D, 16, rel, it, None) == 6
     assert lib.dslash_solve_eo(A, B, C, even, 3, 2, -4.0, 2, 1e-10, 0.1, 10, 10, D, 1 << 30, rel, it, None) == 1

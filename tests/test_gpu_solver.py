@@ -94,31 +94,41 @@ def test_wilson_solve_nv12_row_kernels(inner, itol):
     assert np.allclose(info["relres"], res, rtol=1e-3, atol=1e-13)
 
 
-def test_wilson_solve_32cube64_nv12_sampled():
-    # the solver workload: 32^3 x 64, N_v = 12, m0 = 0.05, smooth links (seed 3),
-    # rhs seed 103; BF16 inner storage on the full lattice and FP16 on the
-    # even-odd Schur complement.  ||b - D x||_2 <= 1e-10 ||b||_2 per column
-    # bounds every single element of the residual, which the oracle evaluates
-    # in FP64 at sampled sites.
-    dims, nv, m0 = (32, 32, 32, 64), 12, 0.05
-    say(f"case solve wilson {dims} nv={nv} sampled")
+def test_solve_rejects_bad_initial_guess():
+    # x0 is checked before anything reaches the library: a host tensor, the
+    # wrong precision or the wrong shape raise ValueError
+    dims, nv, m0 = (4, 4, 4, 4), 2, 0.05
     u = synthetic.gauge_links(dims, "smooth", 3)
     b = synthetic.wilson_spinor(dims, nv, 103)
     U, B = up(u, "c128"), up(b, "c128")
-    bnorm = np.linalg.norm(b.reshape(-1, nv), axis=0)
-    sites = local.sample_sites(dims, 48, 11)
-    bs = local._at(b, sites)
-    for inner, itol, eo in (("bf16", 0.05, False), ("f16", 5e-3, True)):
-        x, info = D.solve("wilson", U, B, m0, inner=inner, tol=1e-10, inner_tol=itol, eo=eo)
-        say(f"inner={inner} eo={eo}: {info['inner_iters']} inner / {info['outer_iters']} outer, "
-            f"max relres {max(info['relres']):.2e}")
-        assert info["status"] == 0
-        assert max(info["relres"]) <= 1e-10
-        xh = down(x)
-        del x
-        torch.cuda.empty_cache()
-        r = bs - local.wilson_at(u, xh, m0, sites)
-        worst = np.abs(r).reshape(len(sites), -1, nv).max(axis=(0, 1))
-        say(f"sampled |b - D x| max per column / ||b||: {(worst / bnorm).max():.2e}")
-        assert np.all(worst <= 1e-10 * bnorm)
-        del xh
+    say("case solve bad x0")
+    bad = [torch.zeros(B.shape, dtype=torch.complex128),                  # on the host
+           torch.zeros_like(B).to(torch.complex64),                       # FP32
+           torch.zeros(B.shape[:-1] + (nv + 1,), dtype=torch.complex128, device=B.device),   # shape
+           torch.zeros_like(B).transpose(0, 1)]                           # not contiguous
+    for x0 in bad:
+        with pytest.raises(ValueError):
+            D.solve("wilson", U, B, m0, inner="c64", x0=x0)
+    with pytest.raises(ValueError):
+        D.solve("brillouin", U, B, m0)
+    with pytest.raises(ValueError):
+        D.solve("wilson", U, B, m0, inner="c128")
+
+
+@pytest.mark.parametrize("inner", ["c64", "bf16"])
+def test_solve_with_caller_links(inner):
+    # dslash_solve with the caller's low-precision links: the same iterations
+    # and solution as the call that converts them itself, and per-column counts
+    dims, nv, m0 = (12, 4, 2, 4), 12, 0.05
+    say(f"case solve caller links inner={inner}")
+    u = synthetic.gauge_links(dims, "smooth", 9)
+    b = synthetic.wilson_spinor(dims, nv, 109)
+    U, B = up(u, "c128"), up(b, "c128")
+    x1, i1 = D.solve("wilson", U, B, m0, inner=inner, inner_tol=1e-5 if inner == "c64" else 0.05)
+    x2, i2 = D.solve("wilson", U, B, m0, inner=inner, inner_tol=1e-5 if inner == "c64" else 0.05,
+                     U_lo=D.convert(U, inner))
+    assert i1 == i2
+    assert torch.equal(x1, x2)
+    assert len(i1["inner_iters_per_column"]) == nv and min(i1["inner_iters_per_column"]) > 0
+    res = solver.relative_residual(lambda v: wilson.apply(u, v, m0), b, down(x2))
+    assert np.all(res <= 1e-10)
