@@ -268,6 +268,26 @@ int dslash_solve_op(int op, const void* U64, const void* b64, void* x64, const i
                     void* workspace, size_t ws_bytes, double* final_relres, int* iters, void* stream);
 
 /*
+ * dslash_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, the same arguments and results, with no workspace argument.
+ * Its workspace is a static device array of DSLASH_SOLVE_NOALLOC_MAX_BYTES
+ * bytes inside the library, one per GPU the library runs on, held until the
+ * process ends; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine, no host heap memory).  Problems whose workspace
+ * (dslash_solve_workspace_bytes) exceeds the array, or with Nv > 256, return
+ * E_WORKSPACE / E_UNSUPPORTED before any launch.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind (the solve initialises all
+ * it reads): calls that overlap on one GPU -- on different streams or from
+ * different host threads -- race and must be serialised by the caller.
+ * Synchronises the stream, so it cannot itself be captured into a graph.
+ */
+#define DSLASH_SOLVE_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+int dslash_solve_noalloc(const void* U64, const void* U_lo, const void* b64, void* x64, const int dims[4], int Nc,
+                         int Nv, double mass, int inner_dtype, double tol, double inner_tol, int max_outer,
+                         int max_inner, double* final_relres, int* iters, void* stream);
+
+/*
  * Even-odd (checkerboard) form of D_W, the eo-decomposition named as a next
  * tuning step at the end of Sec. 4.  All four extents must be even (E_ARG
  * otherwise).  parity(x) = (x + y + z + t) mod 2; every hop of D_W joins

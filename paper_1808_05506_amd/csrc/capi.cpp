@@ -9,6 +9,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/dslash.h"
 #include "launch.hpp"
 #include "solver.hpp"
@@ -348,6 +350,71 @@ int dslash_solve_op(int op, const void* U64, const void* b64, void* x64, const i
   const size_t need = dsl::solve_workspace_bytes(op, dims, Nv, inner_dtype);
   if (int rc = check_workspace(a, workspace, ws_bytes, need, nullptr)) return rc;
   a.workspace = workspace;
+  return dsl::solve(a);
+}
+
+// ------------------------------------------------ solve without allocation
+// dslash_solve_noalloc keeps its workspace in `scratch`, one static array per
+// GPU that the library has run on, held until the process ends.  In host code
+// the array's name is only a host-side stand-in: its device address is taken
+// once per device with hipGetSymbolAddress (with that device current) and only
+// that address reaches kernels and copies.
+constexpr size_t kScratchBytes = DSLASH_SOLVE_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+constexpr int kNoallocMaxNv = 256;
+
+static int scratch_address(hipStream_t st, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "device of the stream");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DSLASH_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int cur = -1;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return hip_fail(e, "current device");
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return hip_fail(e, "select the stream's device");
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess && e2 != hipSuccess) e = e2;
+    }
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return DSLASH_OK;
+}
+
+int dslash_solve_noalloc(const void* U64, const void* U_lo, const void* b64, void* x64, const int dims[4], int Nc,
+                         int Nv, double mass, int inner_dtype, double tol, double inner_tol, int max_outer,
+                         int max_inner, double* final_relres, int* iters, void* stream) {
+  g_err[0] = 0;
+  dsl::SolveArgs a;
+  if (int rc = solve_args(DSLASH_WILSON, U64, b64, x64, dims, Nc, Nv, mass, inner_dtype, tol, inner_tol, max_outer,
+                          max_inner, final_relres, iters, stream, a))
+    return rc;
+  if (!U_lo) return fail(DSLASH_E_ARG, "U_lo is NULL");
+  if (Nv > kNoallocMaxNv) return fail(DSLASH_E_UNSUPPORTED, "at most %d right-hand sides (got %d)", kNoallocMaxNv, Nv);
+  const size_t need = dsl::solve_workspace_bytes(DSLASH_WILSON, dims, Nv, inner_dtype, false, false);
+  if (need > kScratchBytes)
+    return fail(DSLASH_E_WORKSPACE, "the problem needs %zu bytes of workspace, the static scratch holds %zu", need,
+                kScratchBytes);
+  void* ws = nullptr;
+  if (int rc = scratch_address(a.stream, &ws)) return rc;
+  const uint64_t vol = volume(dims);
+  const size_t nlo = size_t(vol) * 36 * dsl::dtype_bytes(inner_dtype);
+  const size_t nspin = size_t(vol) * 12 * Nv * 16;
+  if (overlap(U_lo, nlo, a.x64, nspin)) return fail(DSLASH_E_ALIAS, "U_lo must not overlap x");
+  double host_d[dsl::kHostDoubles * kNoallocMaxNv];
+  int host_i[dsl::kHostInts * kNoallocMaxNv];
+  a.U_lo = U_lo;
+  a.workspace = ws;
+  a.host_d = host_d;
+  a.host_i = host_i;
   return dsl::solve(a);
 }
 
