@@ -457,7 +457,20 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
                                                                "Brillouin links backward (V)", single=10)
     del V, W, C, P, gW, gV
     torch.cuda.empty_cache()
-    # mixed-precision solve, 32^3 x 64, N_v = 12, m0 = 0.05, smooth links
+    rows.update(solve_rows_bench(torch, D, np, synthetic))
+    return rows
+
+
+def solve_rows_bench(torch, D, np, synthetic):
+    """The mixed-precision solves of D_W x = b on 32^3 x 64, N_v = 12, m0 = 0.05,
+    smooth links: wall time to ||b - D x|| / ||b|| <= 1e-10 with FP32, BF16 and
+    FP16 inner storage, on the full lattice and on the even-odd Schur complement."""
+    rows = {}
+    dev = torch.device("cuda:0")
+
+    def up(a, dt):
+        return torch.from_numpy(a.astype(dt)).to(dev)
+
     dims = SOLVE_DIMS
     U = up(synthetic.gauge_links(dims, "smooth", 3), np.complex128)
     B = up(synthetic.wilson_spinor(dims, SOLVE_NV, 103), np.complex128)
@@ -493,6 +506,8 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
             f"max relres {max(info['relres']):.2e}")
         del x
     rows["solve_wilson_eo_32^3x64_nv12"] = solve_eo
+    del U, B
+    torch.cuda.empty_cache()
     return rows
 
 
@@ -502,8 +517,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=4)
-    ap.add_argument("--rows", choices=["all", "none", "staggered"], default="all",
-                    help="the other rows: all, none, or only the D_S ones")
+    ap.add_argument("--rows", choices=["all", "none", "staggered", "solve"], default="all",
+                    help="the other rows: all, none, or only the D_S ones or the solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain FP32 complex copy of this many MiB (counter calibration)")
@@ -555,6 +570,8 @@ def main():
         rows = rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
     elif args.rows == "staggered":
         rows = staggered_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
+    elif args.rows == "solve":
+        rows = solve_rows_bench(torch, D, np, synthetic)
 
     cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
     if args.rows == "all" and not args.no_cpu:

@@ -578,7 +578,7 @@ __device__ __forceinline__ void hold_acc(cpx<T> (&acc)[4][3]) {
 // Two or three rows in flight fit the 168 VGPRs of three waves per SIMD.
 template <int DEPTH> struct MarchWaves { static constexpr int value = DEPTH <= 3 ? 3 : 2; };
 
-template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW, int EPI = EPI_STORE>
 __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            const typename S::word* __restrict__ U,
                                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
@@ -588,7 +588,7 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            u32x4 (&r2)[RowPieces<S>::CH + 1], u32x4 (&r3)[RowPieces<S>::CH + 1],
                                            u32x4 (&r4)[RowPieces<S>::CH + 1], u32x4 (&r5)[RowPieces<S>::CH + 1],
                                            u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[LinkK<S, NV, LW>::value + 1],
-                                           cpx<T> (&carry)[2][3]) {
+                                           cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
   constexpr int LK = LinkK<S, NV, LW>::value;
@@ -674,11 +674,7 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
     const int xc = xl < c.n ? xl : c.n - 1;
     const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
     u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
-    u32x4 r[CH];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(r[j], &dst[j * NV + v]);
+    epi_copy_out<EPI, NV, S, CH>(src, dst, v, xl < c.n, ep);
   }
   __syncthreads();
 }
@@ -686,7 +682,7 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
 // The same step with two row buffers used in turn: row k + 1 is written to
 // one buffer while row k is applied from the other, so each staged row costs
 // one barrier instead of two.  LDS: buf0, buf1 [(R + 2) SSW], lown, lnb0, lnb1.
-template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW>
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW, int EPI = EPI_STORE>
 __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
                                               const typename S::word* __restrict__ U,
                                               const typename S::word* __restrict__ in,
@@ -697,7 +693,7 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
                                               u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
                                               u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
                                               u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
-                                              u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3]) {
+                                              u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
   constexpr int LK = LinkK<S, NV, LW>::value;
@@ -789,11 +785,7 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
     const int xc = xl < c.n ? xl : c.n - 1;
     const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * SSP;
     u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
-    u32x4 r[CH];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(r[j], &dst[j * NV + v]);
+    epi_copy_out<EPI, NV, S, CH>(src, dst, v, xl < c.n, ep);
   }
   __syncthreads();
 }
@@ -806,7 +798,7 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
 // LDS: bo [(R + 2) SSW], ba, bb [R SSW], lown, lnba, lnbb [R LW].
 // HALF: the +-y, +-z and first -t rows go through ba and bb as half spinors
 // (ba, bb [R HSW], adjacent), and the output through ba and bb together.
-template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW, bool HALF = false>
+template <bool FIRST, int DEPTH, bool ADJ, int NV, class S, class T, int LW, bool HALF = false, int EPI = EPI_STORE>
 __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                              const typename S::word* __restrict__ in,
                                              typename S::word* __restrict__ out, typename S::word* bo,
@@ -816,7 +808,7 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
                                              u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
                                              u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
                                              u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
-                                             u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3]) {
+                                             u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeqO<FIRST>;
   constexpr int LK = LinkK<S, NV, LW>::value;
@@ -918,11 +910,7 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
     const int xc = xl < c.n ? xl : c.n - 1;
     const u32x4* src = reinterpret_cast<const u32x4*>(ob) + xc * OSP;
     u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
-    u32x4 rr[CH];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) rr[j] = src[j * NV + v];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(rr[j], &dst[j * NV + v]);
+    epi_copy_out<EPI, NV, S, CH>(src, dst, v, xl < c.n, ep);
   }
   __syncthreads();
 }
@@ -932,10 +920,11 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
 // same with half-spinor neighbour rows (FP32 storage).
 template <int PP, int DEPTH> struct MarchOcc { static constexpr int value = PP ? 2 : MarchWaves<DEPTH>::value; };
 
-template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, int PP = 0>
+template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, int PP = 0, int EPI = EPI_STORE>
 __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
     wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
-                        const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag) {
+                        const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag,
+                        EpiArgs ea) {
   using W = typename S::word;
   constexpr int CH = RowPieces<S>::CH, LK = LinkK<S, NV, LW>::value;
   constexpr int SSW = SiteStride<NV, S>::WORDS;
@@ -962,6 +951,8 @@ __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
   u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
   u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
+  EpiLane<S> ep;
+  ep.template init<NV>(ea, v, EPI == EPI_AXPY);
   using Q0 = typename std::conditional<PP >= 2, MarchSeqO<true>, MarchSeq<true>>::type;
 #define DSL_PISSUE(P) \
   march_issue_o<PP == 3, Q0::at(P), NV, S, LW>(g, c, U, in, xm, xp, xl, v, tid, r0, r1, r2, r3, r4, r5, r6)
@@ -973,63 +964,87 @@ __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
 #undef DSL_PISSUE
   links_issue<S, LK, LW>(c, U, xm, tid, nth, lr);
   if constexpr (PP >= 2)
-    march_step_o<true, DEPTH, ADJ, NV, S, T, LW, PP == 3>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm, xp,
-                                                          xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr,
-                                                          carry);
+    march_step_o<true, DEPTH, ADJ, NV, S, T, LW, PP == 3, EPI>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm,
+                                                               xp, xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6,
+                                                               lr, carry, ep);
   else if constexpr (PP == 1)
-    march_step_pp<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v, tid,
-                                                  nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    march_step_pp<true, DEPTH, ADJ, NV, S, T, LW, EPI>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v,
+                                                       tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry, ep);
   else
-    march_step<true, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
-                                               r0, r1, r2, r3, r4, r5, r6, lr, carry);
+    march_step<true, DEPTH, ADJ, NV, S, T, LW, EPI>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth, diag,
+                                                    r0, r1, r2, r3, r4, r5, r6, lr, carry, ep);
 #pragma nounroll
   for (int k = 1; k < steps; ++k) {
     c.t += 1;
     c.row_base += uint32_t(g.stride[3]);
     if constexpr (PP >= 2)
-      march_step_o<false, DEPTH, ADJ, NV, S, T, LW, PP == 3>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1, xm,
-                                                             xp, xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr,
-                                                             carry);
+      march_step_o<false, DEPTH, ADJ, NV, S, T, LW, PP == 3, EPI>(g, c, U, in, out, buf, buf1, buf2, lown, lnb, lnb1,
+                                                                  xm, xp, xl, v, tid, nth, diag, r0, r1, r2, r3, r4, r5,
+                                                                  r6, lr, carry, ep);
     else if constexpr (PP == 1)
-      march_step_pp<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl, v,
-                                                     tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+      march_step_pp<false, DEPTH, ADJ, NV, S, T, LW, EPI>(g, c, U, in, out, buf, buf1, lown, lnb, lnb1, xm, xp, xl,
+                                                          v, tid, nth, diag, r0, r1, r2, r3, r4, r5, r6, lr, carry, ep);
     else
-      march_step<false, DEPTH, ADJ, NV, S, T, LW>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
-                                                  diag, r0, r1, r2, r3, r4, r5, r6, lr, carry);
+      march_step<false, DEPTH, ADJ, NV, S, T, LW, EPI>(g, c, U, in, out, buf, lown, lnb, xm, xp, xl, v, tid, nth,
+                                                       diag, r0, r1, r2, r3, r4, r5, r6, lr, carry, ep);
   }
+  epi_finish<EPI, NV, S>(ea, ep, reinterpret_cast<double*>(smem_march), xl, v, R);
+}
+
+// The fused epilogues are built for the solver's two forms only (D with
+// EPI_NORM, D^dag with EPI_AXPY), on full links and the default prefetch depth
+// of each buffer scheme.
+template <int PP, int DEPTH, int LW>
+struct MarchEpiBuilt {
+  static constexpr bool value = LW == 9 && DEPTH == (PP == 3 ? 3 : 2);
+};
+
+template <int DEPTH, int NV, class S, class T, int LW, int PP>
+static hipError_t march_launch(bool adj, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Geom& g,
+                               const MarchTraversal& m, bool xcd, const void* U, const void* in, void* out, T diag,
+                               const EpiArgs& ea) {
+  using W = typename S::word;
+#define DSL_MK(A, E)                                                                                           \
+  hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, PP, E>), grid, block, lds, st, g, m, int(xcd), \
+                     (const W*)U, (const W*)in, (W*)out, diag, ea)
+  if (epi == EPI_STORE) {
+    if (adj) DSL_MK(true, EPI_STORE); else DSL_MK(false, EPI_STORE);
+  } else if constexpr (MarchEpiBuilt<PP, DEPTH, LW>::value) {
+    if (epi == EPI_NORM && !adj) DSL_MK(false, EPI_NORM);
+    else if (epi == EPI_AXPY && adj) DSL_MK(true, EPI_AXPY);
+    else return hipErrorNotSupported;
+  } else {
+    return hipErrorNotSupported;
+  }
+#undef DSL_MK
+  return hipGetLastError();
 }
 
 template <int DEPTH, int NV, class S, class T, int LW = 9>
 static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int pp, bool xcd, const void* U,
-                                 const void* in, void* out, double mass, hipStream_t st) {
+                                 const void* in, void* out, double mass, hipStream_t st, int epi, EpiArgs& ea) {
   using W = typename S::word;
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
   const dim3 block(NV, R), grid(m.rows * nseg);
+  if (epi != EPI_STORE && grid.x > ea.capacity) return hipErrorNotSupported;
+  ea.blocks = grid.x;
   size_t lds = rows_lds_words<NV, S, LW>(R) * sizeof(W);
   if (pp == 1) lds += (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (pp == 2) lds += (size_t(2 * R) * SiteStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   if (pp == 3) lds += (size_t(2 * R) * HalfStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
-#define DSL_MK(A, P)                                                                                        \
-  hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, P>), grid, block, lds, st, g, m, int(xcd), \
-                     (const W*)U, (const W*)in, (W*)out, diag)
-  if (pp == 3) {
-    if constexpr (sizeof(W) == 8 && NV % 2 == 0) {
-      if (adj) DSL_MK(true, 3); else DSL_MK(false, 3);
-    } else {
-      return hipErrorInvalidValue;
-    }
-  } else if (pp == 2) {
-    if (adj) DSL_MK(true, 2); else DSL_MK(false, 2);
-  } else if (pp == 1) {
-    if (adj) DSL_MK(true, 1); else DSL_MK(false, 1);
-  } else {
-    if (adj) DSL_MK(true, 0); else DSL_MK(false, 0);
+  switch (pp) {
+    case 3:
+      if constexpr (sizeof(W) == 8 && NV % 2 == 0)
+        return march_launch<DEPTH, NV, S, T, LW, 3>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+      else
+        return hipErrorInvalidValue;
+    case 2: return march_launch<DEPTH, NV, S, T, LW, 2>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+    case 1: return march_launch<DEPTH, NV, S, T, LW, 1>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+    default: return march_launch<DEPTH, NV, S, T, LW, 0>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
   }
-#undef DSL_MK
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- even-odd hop
@@ -1039,12 +1054,12 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
 // index i of the neighbour rows of `in`; the x neighbours are in the same row
 // of `in` at i + r (x + 1) and i - 1 + r (x - 1), r = (p + y + z + t) mod 2.
 // Forward links come from Uo (parity p), backward ones from Ui (parity 1 - p).
-template <int DEPTH, bool ADJ, int NV, class S, class T>
+template <int DEPTH, bool ADJ, int NV, class S, class T, int EPI = EPI_STORE>
 __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
     wilson_eo_rows_kernel(Geom g, RowTraversal tr, int xcd, int p, const typename S::word* __restrict__ Uo,
                           const typename S::word* __restrict__ Ui, const typename S::word* __restrict__ in,
                           typename S::word* __restrict__ out, const typename S::word* __restrict__ add, T c_add,
-                          T c_hop) {
+                          T c_hop, EpiArgs ea) {
   using W = typename S::word;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   constexpr int SSW = SiteStride<NV, S>::WORDS, SSP = SiteStride<NV, S>::PIECES;
@@ -1150,28 +1165,37 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
     const int xc = xl < c.n ? xl : c.n - 1;
     const u32x4* src = reinterpret_cast<const u32x4*>(buf) + xc * SSP;
     u32x4* dst = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xc) * SW);
-    u32x4 o[CH];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) o[j] = src[j * NV + v];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(o[j], &dst[j * NV + v]);
+    EpiLane<S> ep;
+    ep.template init<NV>(ea, v, EPI == EPI_AXPY);
+    epi_copy_out<EPI, NV, S, CH>(src, dst, v, xl < c.n, ep);
+    epi_finish<EPI, NV, S>(ea, ep, reinterpret_cast<double*>(smem_eo), xl, v, R);
   }
 }
 
 template <int NV, class S, class T>
 static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, int parity, const void* Uo,
                                    const void* Ui, const void* in, void* out, const void* add, double c_add,
-                                   double c_hop, hipStream_t st) {
+                                   double c_hop, hipStream_t st, int epi, EpiArgs& ea) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+  if (epi != EPI_STORE && grid.x > ea.capacity) return hipErrorNotSupported;
+  ea.blocks = grid.x;
   const size_t lds = (rows_lds_words<NV, S>(R) + size_t(R) * 9) * sizeof(W);
-  if (adj)
-    hipLaunchKernelGGL((wilson_eo_rows_kernel<3, true, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), parity,
-                       (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop));
-  else
-    hipLaunchKernelGGL((wilson_eo_rows_kernel<3, false, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), parity,
-                       (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop));
+#define DSL_EK(A, E)                                                                                          \
+  hipLaunchKernelGGL((wilson_eo_rows_kernel<3, A, NV, S, T, E>), grid, block, lds, st, g, tr, int(xcd), parity, \
+                     (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop), ea)
+  // fused epilogues: the Schur operator M with EPI_NORM, M^dag with EPI_AXPY
+  if (epi == EPI_STORE) {
+    if (adj) DSL_EK(true, EPI_STORE); else DSL_EK(false, EPI_STORE);
+  } else if (epi == EPI_NORM && !adj) {
+    DSL_EK(false, EPI_NORM);
+  } else if (epi == EPI_AXPY && adj) {
+    DSL_EK(true, EPI_AXPY);
+  } else {
+    return hipErrorNotSupported;
+  }
+#undef DSL_EK
   return hipGetLastError();
 }
 
@@ -1180,8 +1204,11 @@ static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 // uses the direct kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                  const void* in, void* out, const void* add, double c_add, double c_hop,
-                                 hipStream_t st) {
+                                 hipStream_t st, int epi, EpiArgs* ea) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (epi != EPI_STORE && !ea) return hipErrorNotSupported;
+  EpiArgs none;
+  EpiArgs& ep = ea ? *ea : none;
   if (e.nv != 12) return hipErrorNotSupported;
   const int pdims[4] = {e.nh, e.n[1], e.n[2], e.n[3]};
   const Geom g = make_geom(pdims, e.nv);
@@ -1196,9 +1223,12 @@ hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parit
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
   switch (dtype) {
-    case DT_C64: return wilson_eo_rows_t<12, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
-    case DT_BF16: return wilson_eo_rows_t<12, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
-    case DT_F16: return wilson_eo_rows_t<12, F16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
+    case DT_C64: return wilson_eo_rows_t<12, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
+                                                      st, epi, ep);
+    case DT_BF16: return wilson_eo_rows_t<12, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
+                                                      st, epi, ep);
+    case DT_F16: return wilson_eo_rows_t<12, F16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
+                                                      st, epi, ep);
   }
   return hipErrorNotSupported;
 }
@@ -1242,8 +1272,12 @@ static int device_cus() {
 }
 
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st, const void* clover, bool compressed) {
+                              double mass, hipStream_t st, const void* clover, bool compressed, int epi,
+                              EpiArgs* ea) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (epi != EPI_STORE && (!ea || clover || compressed)) return hipErrorNotSupported;
+  EpiArgs none;
+  EpiArgs& e = ea ? *ea : none;
   if (g.nv != 12) return hipErrorNotSupported;
   int R = row_sites_default(g.n[0], g.nv);
   R = knobs().row_sites.get(R);
@@ -1289,12 +1323,14 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // compressed links are read by the t-marching kernel only
   if (compressed && (tsteps <= 0 || clover)) return hipErrorNotSupported;
   if (tsteps > 0 && !clover) {
-    const int depth = knobs().row_depth.get(pp == 3 ? 3 : 2);
-#define DSL_MT(D, LW)                                                                                          \
-  switch (dtype) {                                                                                             \
-    case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
-    case DT_BF16: return wilson_march_t<D, 12, BF16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st); \
-    case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st);   \
+    // the fused epilogues take the default depth of the buffer scheme
+    const int depth = epi != EPI_STORE ? (pp == 3 ? 3 : 2) : knobs().row_depth.get(pp == 3 ? 3 : 2);
+#define DSL_MT(D, LW)                                                                                               \
+  switch (dtype) {                                                                                                  \
+    case DT_C64: return wilson_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st, epi, e); \
+    case DT_BF16:                                                                                                   \
+      return wilson_march_t<D, 12, BF16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st, epi, e);       \
+    case DT_F16: return wilson_march_t<D, 12, F16, float, LW>(adj, g, R, tsteps, pp, xcd, U, in, out, mass, st, epi, e); \
   }
     if (compressed) {
       if (depth <= 2) {
@@ -1310,6 +1346,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
 #undef DSL_MT
     return hipErrorNotSupported;
   }
+  if (epi != EPI_STORE) return hipErrorNotSupported;
   const int depth = knobs().row_depth.get(3);
 #define DSL_RT(D)                                                                               \
   switch (dtype) {                                                                              \

@@ -373,7 +373,8 @@ hipError_t launch_axpy_promote(void* x, int lodt, const void* e, const double* s
 
 // e += alpha p; r -= alpha q; per-column |r|^2 partials (FP32 arithmetic for the
 // updates, FP64 for the norm)
-template <class S>
+// XE = false: the residual update alone (e and p unused).
+template <class S, bool XE = true>
 __global__ void __launch_bounds__(256) cg_update_xr_kernel(typename S::word* __restrict__ e, typename S::word* __restrict__ r,
                                                            const typename S::word* __restrict__ p,
                                                            const typename S::word* __restrict__ q,
@@ -386,11 +387,12 @@ __global__ void __launch_bounds__(256) cg_update_xr_kernel(typename S::word* __r
     const float a = float(alpha[v]);
     for (size_t row = size_t(blockIdx.x) * blockDim.y + threadIdx.y; row < rows; row += size_t(gridDim.x) * blockDim.y) {
       const size_t i = row * nv + v;
-      cpx<float> ev = S::template load<float>(e + i), pv = S::template load<float>(p + i);
+      if constexpr (XE) {
+        cpx<float> ev = S::template load<float>(e + i), pv = S::template load<float>(p + i);
+        S::template store<float>(e + i, rmadd(ev, a, pv));
+      }
       cpx<float> rv = S::template load<float>(r + i), qv = S::template load<float>(q + i);
-      ev = rmadd(ev, a, pv);
       rv = rmadd(rv, -a, qv);
-      S::template store<float>(e + i, ev);
       S::template store<float>(r + i, rv);
       cpx<double> rs = S::template load<double>(r + i);  // the stored (rounded) residual
       acc = fma(rs.r, rs.r, fma(rs.i, rs.i, acc));
@@ -402,7 +404,7 @@ __global__ void __launch_bounds__(256) cg_update_xr_kernel(typename S::word* __r
 
 // Vectorised e += alpha p; r -= alpha q with the |r|^2 partials of the stored
 // (rounded) residual.
-template <class S>
+template <class S, bool XE = true>
 __global__ void __launch_bounds__(256) cg_update_xr_vec_kernel(u32x4* __restrict__ e, u32x4* __restrict__ r,
                                                                const u32x4* __restrict__ p,
                                                                const u32x4* __restrict__ q,
@@ -425,27 +427,34 @@ __global__ void __launch_bounds__(256) cg_update_xr_vec_kernel(u32x4* __restrict
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const size_t cu = c + u * G < chunks ? c + u * G : c;
-      ze[u] = e[cu];
-      zp[u] = p[cu];
+      if constexpr (XE) {
+        ze[u] = e[cu];
+        zp[u] = p[cu];
+      }
       zr[u] = r[cu];
       zq[u] = q[cu];
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (c + u * G < chunks) {
-        W we[VW], wp[VW], wr[VW], wq[VW];
-        Vec<S>::unpack(ze[u], we);
-        Vec<S>::unpack(zp[u], wp);
+        W wr[VW], wq[VW];
+        if constexpr (XE) {
+          W we[VW], wp[VW];
+          Vec<S>::unpack(ze[u], we);
+          Vec<S>::unpack(zp[u], wp);
+#pragma unroll
+          for (int k = 0; k < VW; ++k)
+            S::template store<float>(&we[k], rmadd(S::template load<float>(&we[k]), a[k], S::template load<float>(&wp[k])));
+          e[c + u * G] = Vec<S>::pack(we);
+        }
         Vec<S>::unpack(zr[u], wr);
         Vec<S>::unpack(zq[u], wq);
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
-          S::template store<float>(&we[k], rmadd(S::template load<float>(&we[k]), a[k], S::template load<float>(&wp[k])));
           S::template store<float>(&wr[k], rmadd(S::template load<float>(&wr[k]), -a[k], S::template load<float>(&wq[k])));
           const cpx<double> rs = S::template load<double>(&wr[k]);
           acc[k] = fma(rs.r, rs.r, fma(rs.i, rs.i, acc[k]));
         }
-        e[c + u * G] = Vec<S>::pack(we);
         r[c + u * G] = Vec<S>::pack(wr);
       }
     }
@@ -453,13 +462,13 @@ __global__ void __launch_bounds__(256) cg_update_xr_vec_kernel(u32x4* __restrict
   vec_block_partial<VW>(acc, shd, partial, nv);
 }
 
-template <class S>
+template <class S, bool XE = true>
 static void cg_update_xr_vec(void* e, void* r, const void* p, const void* q, const double* alpha, size_t n, int nv,
                              double* partial, hipStream_t st) {
   const int cols = nv / Vec<S>::VW;
   const int ry = 256 / cols > 0 ? 256 / cols : 1;
   const size_t lds = size_t(cols) * ry * sizeof(double);
-  hipLaunchKernelGGL(cg_update_xr_vec_kernel<S>, dim3(kReduceBlocks), dim3(cols, ry), lds, st, (u32x4*)e, (u32x4*)r,
+  hipLaunchKernelGGL((cg_update_xr_vec_kernel<S, XE>), dim3(kReduceBlocks), dim3(cols, ry), lds, st, (u32x4*)e, (u32x4*)r,
                      (const u32x4*)p, (const u32x4*)q, alpha, n / Vec<S>::VW, nv, partial);
 }
 
@@ -522,6 +531,145 @@ hipError_t launch_cg_update_p(int dtype, void* p, const void* r, const double* b
     case DT_F16: hipLaunchKernelGGL(cg_update_p_kernel<F16>, gr, bl, 0, st, (uint32_t*)p, (const uint32_t*)r, beta, n, nv); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <class S>
+static hipError_t update_r_t(void* r, const void* s_, const double* alpha, size_t rows, int nv, double* partial,
+                             hipStream_t st) {
+  using W = typename S::word;
+  if (vec_ok<S>(nv, r) && vec_ok<S>(nv, s_) && nv / Vec<S>::VW <= 256) {
+    cg_update_xr_vec<S, false>(nullptr, r, nullptr, s_, alpha, rows * nv, nv, partial, st);
+  } else {
+    const ColShape c = col_shape(nv);
+    const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
+    hipLaunchKernelGGL((cg_update_xr_kernel<S, false>), c.grid, c.block, lds, st, (W*)nullptr, (W*)r,
+                       (const W*)nullptr, (const W*)s_, alpha, rows, nv, partial);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_r(int dtype, void* r, const void* s_, const double* alpha, size_t sites, int comps, int nv,
+                              double* partial, double* out, hipStream_t st) {
+  const size_t rows = sites * comps;
+  hipError_t err;
+  switch (dtype) {
+    case DT_C64: err = update_r_t<C64>(r, s_, alpha, rows, nv, partial, st); break;
+    case DT_BF16: err = update_r_t<BF16>(r, s_, alpha, rows, nv, partial, st); break;
+    case DT_F16: err = update_r_t<F16>(r, s_, alpha, rows, nv, partial, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess) return err;
+  return finish(partial, nv, out, st);
+}
+
+// e += alpha[v] p;  p = r + beta[v] p  (the old p in both), FP32 arithmetic.
+// Vectorised: thread (cx, y) of a (nv / VW, ry) block keeps the columns
+// cx VW .. cx VW + VW - 1 (as in the reductions).
+template <class S>
+__global__ void __launch_bounds__(256) cg_update_ep_vec_kernel(u32x4* __restrict__ e, u32x4* __restrict__ p,
+                                                               const u32x4* __restrict__ r,
+                                                               const double* __restrict__ alpha,
+                                                               const double* __restrict__ beta, size_t chunks) {
+  using W = typename S::word;
+  constexpr int VW = Vec<S>::VW;
+  const size_t G = size_t(gridDim.x) * blockDim.x * blockDim.y;
+  const size_t g0 = (size_t(blockIdx.x) * blockDim.y + threadIdx.y) * blockDim.x + threadIdx.x;
+  float a[VW], b[VW];
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    a[k] = float(alpha[threadIdx.x * VW + k]);
+    b[k] = float(beta[threadIdx.x * VW + k]);
+  }
+  for (size_t c = g0; c < chunks; c += G) {
+    W we[VW], wp[VW], wr[VW];
+    Vec<S>::unpack(e[c], we);
+    Vec<S>::unpack(p[c], wp);
+    Vec<S>::unpack(r[c], wr);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      const cpx<float> pv = S::template load<float>(&wp[k]);
+      S::template store<float>(&we[k], rmadd(S::template load<float>(&we[k]), a[k], pv));
+      S::template store<float>(&wp[k], rmadd(S::template load<float>(&wr[k]), b[k], pv));
+    }
+    e[c] = Vec<S>::pack(we);
+    p[c] = Vec<S>::pack(wp);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) cg_update_ep_kernel(typename S::word* __restrict__ e,
+                                                           typename S::word* __restrict__ p,
+                                                           const typename S::word* __restrict__ r,
+                                                           const double* __restrict__ alpha,
+                                                           const double* __restrict__ beta, size_t n, int nv) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int v = int(i % nv);
+    const float a = float(alpha[v]), b = float(beta[v]);
+    const cpx<float> pv = S::template load<float>(p + i);
+    S::template store<float>(e + i, rmadd(S::template load<float>(e + i), a, pv));
+    S::template store<float>(p + i, rmadd(S::template load<float>(r + i), b, pv));
+  }
+}
+
+template <class S>
+static hipError_t update_ep_t(void* e, void* p, const void* r, const double* alpha, const double* beta, size_t n,
+                              int nv, hipStream_t st) {
+  using W = typename S::word;
+  if (vec_ok<S>(nv, e) && vec_ok<S>(nv, p) && vec_ok<S>(nv, r) && nv / Vec<S>::VW <= 256) {
+    const int cols = nv / Vec<S>::VW;
+    const int ry = 256 / cols > 0 ? 256 / cols : 1;
+    const size_t chunks = n / Vec<S>::VW;
+    size_t blocks = (chunks + size_t(cols) * ry - 1) / (size_t(cols) * ry);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(cg_update_ep_vec_kernel<S>, dim3(unsigned(blocks)), dim3(cols, ry), 0, st, (u32x4*)e,
+                       (u32x4*)p, (const u32x4*)r, alpha, beta, chunks);
+  } else {
+    hipLaunchKernelGGL(cg_update_ep_kernel<S>, stream_grid(n), dim3(256), 0, st, (W*)e, (W*)p, (const W*)r, alpha,
+                       beta, n, nv);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_ep(int dtype, void* e, void* p, const void* r, const double* alpha, const double* beta,
+                               size_t sites, int comps, int nv, hipStream_t st) {
+  const size_t n = sites * comps * nv;
+  switch (dtype) {
+    case DT_C64: return update_ep_t<C64>(e, p, r, alpha, beta, n, nv, st);
+    case DT_BF16: return update_ep_t<BF16>(e, p, r, alpha, beta, n, nv, st);
+    case DT_F16: return update_ep_t<F16>(e, p, r, alpha, beta, n, nv, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// fold[b][v] = sum of partial[i][v] over the rows i of chunk b (chunks of
+// ceil(nb / kReduceBlocks) consecutive rows), in a fixed order: thread (v, y)
+// adds rows y, y + ry, ... of the chunk, then a fixed LDS tree over y.
+__global__ void __launch_bounds__(256) fold_rows_kernel(const double* __restrict__ partial, int nb, int nv,
+                                                        int chunk, double* __restrict__ fold) {
+  extern __shared__ double shd[];
+  const int v = blockIdx.y * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.x * chunk, r1 = r0 + chunk < nb ? r0 + chunk : nb;
+  double acc = 0.0;
+  if (v < nv)
+    for (int r = r0 + int(threadIdx.y); r < r1; r += blockDim.y) acc += partial[size_t(r) * nv + v];
+  double tot = block_col_sum(acc, shd);
+  if (threadIdx.y == 0 && v < nv) fold[size_t(blockIdx.x) * nv + v] = tot;
+}
+
+hipError_t launch_finish_sum(const double* partial, int nb, int nv, double* out, double* fold, hipStream_t st) {
+  if (nb > 2 * kReduceBlocks && fold) {
+    const ColShape c = col_shape(nv);
+    const size_t lds = size_t(c.block.x) * c.block.y * sizeof(double);
+    const int chunk = (nb + kReduceBlocks - 1) / kReduceBlocks;
+    hipLaunchKernelGGL(fold_rows_kernel, c.grid, c.block, lds, st, partial, nb, nv, chunk, fold);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    partial = fold;
+    nb = kReduceBlocks;
+  }
+  hipLaunchKernelGGL(finish_sum_kernel, dim3(nv), dim3(256), 0, st, partial, nb, nv, out);
   return hipGetLastError();
 }
 

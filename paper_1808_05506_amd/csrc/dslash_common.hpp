@@ -266,4 +266,16 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, bool on =
   return b;
 }
 
+// Output epilogues of the D_W row kernels fused for the solver (see rows.hpp):
+// EPI_STORE out = result; EPI_NORM also the per-column |out|^2 sums;
+// EPI_AXPY out -= alpha[v] result in place, with the |out|^2 sums.
+enum { EPI_STORE = 0, EPI_NORM = 1, EPI_AXPY = 2 };
+
+struct EpiArgs {
+  const double* alpha = nullptr;  // EPI_AXPY: one coefficient per column (device)
+  double* partial = nullptr;      // EPI_NORM, EPI_AXPY: [workgroups][nv] (device)
+  uint32_t capacity = 0;          // workgroups the partial array holds
+  uint32_t blocks = 0;            // set by the launcher: workgroups that wrote partials
+};
+
 }  // namespace dsl

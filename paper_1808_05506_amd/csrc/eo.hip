@@ -188,9 +188,10 @@ __global__ void __launch_bounds__(256, 3) wilson_eo_hop_kernel(EoGeom e, int p, 
 
 hipError_t launch_wilson_eo_hop(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                 const void* in, void* out, const void* add, double c_add, double c_hop,
-                                hipStream_t st) {
-  const hipError_t rows = launch_wilson_eo_rows(adj, dtype, e, parity, Uo, Ui, in, out, add, c_add, c_hop, st);
-  if (rows != hipErrorNotSupported) return rows;
+                                hipStream_t st, int epi, EpiArgs* ea) {
+  const hipError_t rows =
+      launch_wilson_eo_rows(adj, dtype, e, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ea);
+  if (rows != hipErrorNotSupported || epi != EPI_STORE) return rows;
   Shape sh = site_v_shape(e.hvol, e.nv);
 #define DSL_EO(SS, TT)                                                                                          \
   do {                                                                                                           \

@@ -20,7 +20,7 @@ struct Knob {
   int get(int dflt) const { return set ? value : dflt; }
 };
 struct Knobs {
-  Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra;
+  Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra, cg_fuse;
 };
 inline Knob read_knob(const char* name) {
   Knob k;
@@ -42,6 +42,7 @@ inline const Knobs& knobs() {
     r.march_pp = read_knob("DSLASH_MARCH_PP");
     r.rows = read_knob("DSLASH_ROWS");
     r.row_lds_extra = read_knob("DSLASH_ROW_LDS_EXTRA");
+    r.cg_fuse = read_knob("DSLASH_CG_FUSE");
     return r;
   }();
   return k;
@@ -67,8 +68,12 @@ Shape site_v_shape(uint32_t vol, int nv);
 // rows of every link (6 words per link; STAGGERED and WILSON, not with clover).
 hipError_t launch_apply(int op, bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
                         double mass, hipStream_t st, const void* clover = nullptr, bool compressed = false);
+// epi, ea: fused output epilogue (EPI_*, EpiArgs: the solver's D with EPI_NORM
+// and D^dag with EPI_AXPY on the t-marching kernels); hipErrorNotSupported
+// when the chosen kernel has no such form.
 hipError_t launch_wilson_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
-                              double mass, hipStream_t st, const void* clover = nullptr, bool compressed = false);
+                              double mass, hipStream_t st, const void* clover = nullptr, bool compressed = false,
+                              int epi = 0, EpiArgs* ea = nullptr);
 hipError_t launch_staggered_rows(bool adjoint, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st, bool compressed = false);
 hipError_t launch_compress_links(int dtype, size_t links, const void* V, void* Vc, hipStream_t st);
@@ -101,12 +106,14 @@ EoGeom make_eo_geom(const int dims[4], int nv);
 hipError_t launch_eo_copy(bool to_packed, const EoGeom& e, int parity, const void* src, void* dst, size_t site_bytes,
                           hipStream_t st);
 // out = c_add add + c_hop H in on the packed parity-`parity` sites (add may be null)
+// epi, ea: fused output epilogue as for launch_wilson_rows (the Schur operator
+// M with EPI_NORM, M^dag with EPI_AXPY; row-staged kernel only)
 hipError_t launch_wilson_eo_hop(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                 const void* in, void* out, const void* add, double c_add, double c_hop,
-                                hipStream_t st);
+                                hipStream_t st, int epi = 0, EpiArgs* ea = nullptr);
 hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                  const void* in, void* out, const void* add, double c_add, double c_hop,
-                                 hipStream_t st);
+                                 hipStream_t st, int epi = 0, EpiArgs* ea = nullptr);
 
 // ---- solver BLAS-1 (fields of `comps` complex numbers per site times nv columns,
 //      column index fastest; per-column scalars are device arrays of nv doubles)
@@ -125,6 +132,15 @@ hipError_t launch_axpy_promote(void* x, int lodt, const void* e, const double* s
 // e += alpha[v] p;  r -= alpha[v] q;  partial |r|^2 -> out
 hipError_t launch_cg_update_xr(int dtype, void* e, void* r, const void* p, const void* q, const double* alpha,
                                size_t sites, int comps, int nv, double* partial, double* out, hipStream_t st);
+// r -= alpha[v] s;  partial |r|^2 -> out
+hipError_t launch_cg_update_r(int dtype, void* r, const void* s, const double* alpha, size_t sites, int comps, int nv,
+                              double* partial, double* out, hipStream_t st);
+// e += alpha[v] p;  p = r + beta[v] p
+hipError_t launch_cg_update_ep(int dtype, void* e, void* p, const void* r, const double* alpha, const double* beta,
+                               size_t sites, int comps, int nv, hipStream_t st);
+// out[v] = sum over b < nb of partial[b][v], in a fixed order (many rows are
+// first folded to kReduceBlocks rows in fold, kReduceBlocks x nv doubles)
+hipError_t launch_finish_sum(const double* partial, int nb, int nv, double* out, double* fold, hipStream_t st);
 // p = r + beta[v] p
 hipError_t launch_cg_update_p(int dtype, void* p, const void* r, const double* beta, size_t sites, int comps,
                               int nv, hipStream_t st);

@@ -220,4 +220,157 @@ __device__ __forceinline__ void copy_pieces(void* __restrict__ dst, const void* 
   }
 }
 
+// ---------------------------------------------------------------- output epilogues
+// Fused forms of a D_W application for the inner CG on D^dag D (the solver):
+//   EPI_STORE  out = result
+//   EPI_NORM   out = result, and per column v the sum of |out|^2 over the
+//              workgroup's sites (of the stored, rounded values) goes to
+//              partial[workgroup][v]
+//   EPI_AXPY   out holds the residual r and is updated in place,
+//              r -= alpha[v] result (result as stored, i.e. rounded to the
+//              storage format first), and the sums of |r|^2 of the stored r
+//              go to partial[workgroup][v]
+// A lane's 16-byte output pieces always cover the same VW columns, so it keeps
+// VW FP32 sums over its few sites and steps in a fixed order (registers are
+// what bounds these kernels' occupancy); the workgroup adds them in FP64 in a
+// fixed tree at the end.  The kernel reads the stencil input only, so
+// r can be updated in place; the partials are summed over workgroups in a
+// fixed order by the caller (bitwise reproducible).
+// (EPI_* and EpiArgs are in dslash_common.hpp.)
+
+template <class S>
+struct EpiLane {
+  using W = typename S::word;
+  static constexpr int VW = 16 / int(sizeof(W));  // columns per 16-byte piece
+  const double* alpha;                            // EPI_AXPY coefficients, read where used
+  int col0;                                       // first of the lane's VW columns
+  float sum[VW];                                  // the lane's |out|^2 sums, one per column
+
+  template <int NV>
+  __device__ __forceinline__ void init(const EpiArgs& e, int v, bool axpy) {
+    static_assert(NV % VW == 0, "a piece holds whole columns");
+    alpha = axpy ? e.alpha : nullptr;
+    col0 = (v * VW) % NV;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) sum[k] = 0.f;
+  }
+};
+
+// The VW storage words of a 16-byte piece and back, element by element (a bit
+// cast of a vector element is miscompiled by this compiler).
+template <class S>
+__device__ __forceinline__ void piece_unpack(u32x4 z, typename S::word (&w)[EpiLane<S>::VW]) {
+  using W = typename S::word;
+  constexpr int VW = EpiLane<S>::VW;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    if constexpr (VW == 1) {
+      w[k] = __builtin_bit_cast(W, z);
+    } else if constexpr (VW == 2) {
+      w[k] = __builtin_bit_cast(W, u32x2{z[2 * k], z[2 * k + 1]});
+    } else {
+      static_assert(__is_same(W, uint32_t), "4-byte storage words are uint32_t");
+      w[k] = z[k];
+    }
+  }
+}
+
+template <class S>
+__device__ __forceinline__ u32x4 piece_pack(const typename S::word (&w)[EpiLane<S>::VW]) {
+  constexpr int VW = EpiLane<S>::VW;
+  u32x4 z;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    if constexpr (VW == 1) {
+      z = __builtin_bit_cast(u32x4, w[k]);
+    } else if constexpr (VW == 2) {
+      const u32x2 a = __builtin_bit_cast(u32x2, w[k]);
+      z[2 * k] = a[0];
+      z[2 * k + 1] = a[1];
+    } else {
+      z[k] = w[k];
+    }
+  }
+  return z;
+}
+
+// Copy-out of one site's CH pieces (lane v takes pieces j NV + v) from LDS to
+// global memory with the epilogue EPI; `live` is false for lanes past a
+// partial chunk's end, which then store and count nothing.
+template <int EPI, int NV, class S, int CH>
+__device__ __forceinline__ void epi_copy_out(const u32x4* src, u32x4* dst, int v, bool live, EpiLane<S>& e) {
+  using W = typename S::word;
+  constexpr int VW = EpiLane<S>::VW;
+  u32x4 z[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) z[j] = src[j * NV + v];
+  if constexpr (EPI == EPI_AXPY) {
+    float al[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) al[k] = float(e.alpha[e.col0 + k]);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      W ws[VW], wr[VW];
+      piece_unpack<S>(z[j], ws);
+      piece_unpack<S>(live ? dst[j * NV + v] : u32x4{0u, 0u, 0u, 0u}, wr);
+#pragma unroll
+      for (int k = 0; k < VW; ++k)
+        S::template store<float>(&wr[k], rmadd(S::template load<float>(&wr[k]), -al[k],
+                                               S::template load<float>(&ws[k])));
+      z[j] = piece_pack<S>(wr);
+    }
+  }
+  if constexpr (EPI == EPI_STORE) {
+    // lanes past a partial chunk's end repeat the last site: same data, same place
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(z[j], &dst[j * NV + v]);
+  } else if (live) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) __builtin_nontemporal_store(z[j], &dst[j * NV + v]);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      W w[VW];
+      piece_unpack<S>(z[j], w);
+#pragma unroll
+      for (int k = 0; k < VW; ++k) {
+        const cpx<float> q = S::template load<float>(&w[k]);
+        e.sum[k] = fmaf(q.r, q.r, fmaf(q.i, q.i, e.sum[k]));
+      }
+    }
+  }
+}
+
+// The workgroup's per-column sums into partial[blockIdx.x][0 .. NV): the
+// lanes' sums go to LDS as [VW][R][NV] (lds: at least VW R NV doubles, free
+// apart from a barrier), are added over the R sites in a fixed tree, and
+// thread v < NV adds the lanes v' < NV whose pieces hold column v.
+template <int EPI, int NV, class S>
+__device__ __forceinline__ void epi_finish(const EpiArgs& ea, const EpiLane<S>& e, double* lds, int xl, int v,
+                                           int R) {
+  if constexpr (EPI != EPI_STORE) {
+    constexpr int VW = EpiLane<S>::VW;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VW; ++k) lds[(k * R + xl) * NV + v] = double(e.sum[k]);
+    __syncthreads();
+    for (int w = 1; w < R; w <<= 1) {
+      if ((xl & (2 * w - 1)) == 0 && xl + w < R) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) lds[(k * R + xl) * NV + v] += lds[(k * R + xl + w) * NV + v];
+      }
+      __syncthreads();
+    }
+    const int tid = xl * NV + v;
+    if (tid < NV) {
+      double s = 0.0;
+      for (int lv = 0; lv < NV; ++lv) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k)
+          if ((lv * VW + k) % NV == tid) s += lds[k * R * NV + lv];
+      }
+      ea.partial[size_t(blockIdx.x) * NV + tid] = s;
+    }
+  }
+}
+
 }  // namespace dsl

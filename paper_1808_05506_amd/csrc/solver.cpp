@@ -33,8 +33,17 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Rows of per-workgroup partial sums the workspace holds: the reductions of
+// the BLAS-1 kernels (kReduceBlocks) and of the fused D_W epilogues (one per
+// workgroup; their row-staged kernels cover at least 8 sites per workgroup,
+// and a launch with more workgroups falls back to the unfused form).
+uint32_t partial_blocks(size_t vol) {
+  const size_t b = vol / 8;
+  return uint32_t(b > size_t(kReduceBlocks) ? b : size_t(kReduceBlocks));
+}
+
 struct Layout {
-  size_t u_lo, e, r, p, q, s, t64, r64, partial, scal, total;
+  size_t u_lo, e, r, p, q, s, t64, r64, partial, fold, scal, total;
   size_t field_lo, field64, links_lo;
   // even-odd only: full-lattice links before packing, the scaled residual
   // (full), its packed halves, the odd temporary and the odd solution
@@ -69,7 +78,8 @@ Layout layout_eo(const int dims[4], int nv, int lodt) {
   L.eodd = take(half * eb);
   L.t64 = take(L.field64 * 16);
   L.r64 = take(L.field64 * 16);
-  L.partial = take(size_t(kReduceBlocks) * nv * sizeof(double));
+  L.partial = take(size_t(partial_blocks(vol)) * nv * sizeof(double));
+  L.fold = take(size_t(kReduceBlocks) * nv * sizeof(double));
   L.scal = take(size_t(12) * nv * sizeof(double));
   L.total = off;
   return L;
@@ -97,7 +107,8 @@ Layout layout(int op, const int dims[4], int nv, int lodt, bool own_links) {
   L.s = take(L.field_lo * eb);
   L.t64 = take(L.field64 * 16);
   L.r64 = take(L.field64 * 16);
-  L.partial = take(size_t(kReduceBlocks) * nv * sizeof(double));
+  L.partial = take(size_t(partial_blocks(vol)) * nv * sizeof(double));
+  L.fold = take(size_t(kReduceBlocks) * nv * sizeof(double));
   L.scal = take(size_t(12) * nv * sizeof(double));
   L.total = off;
   return L;
@@ -177,6 +188,7 @@ int solve(const SolveArgs& a) {
   void* t64 = ws + L.t64;
   void* r64 = ws + L.r64;
   double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* fold = reinterpret_cast<double*>(ws + L.fold);
   double* sc = reinterpret_cast<double*>(ws + L.scal);
   double *rr = sc, *rr_new = sc + nv, *pq = sc + 2 * nv, *rr0 = sc + 3 * nv, *alpha = sc + 4 * nv,
          *beta = sc + 5 * nv, *active = sc + 6 * nv, *nb2 = sc + 7 * nv, *nr2 = sc + 8 * nv,
@@ -232,14 +244,39 @@ int solve(const SolveArgs& a) {
     DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
     for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
     DSL_TRY(hipMemcpyAsync(active, hact, nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    // One CG iteration on D^dag D: q = D p with |q|^2 fused into the apply,
+    // r -= alpha D^dag q with |r|^2 fused into the adjoint apply (s never
+    // stored), then e += alpha p and p = r + beta p in one pass.  Kernels
+    // without the fused forms fall back to separate passes.
     for (int k = 0; k < a.max_inner; ++k) {
-      DSL_TRY(launch_apply(a.op, false, lodt, g, u_lo, p, q, a.mass, st), "inner D p");
-      DSL_TRY(launch_norm2(lodt, q, vol, comps, nv, partial, pq, st), "|Dp|^2");
+      EpiArgs ea;
+      ea.alpha = alpha;
+      ea.partial = partial;
+      ea.capacity = partial_blocks(vol);
+      const bool fuse = a.op == OP_WILSON && knobs().cg_fuse.get(1) != 0;
+      hipError_t fe = fuse ? launch_wilson_rows(false, lodt, g, u_lo, p, q, a.mass, st, nullptr, false, EPI_NORM, &ea)
+                           : hipErrorNotSupported;
+      if (fe == hipSuccess) {
+        DSL_TRY(launch_finish_sum(partial, int(ea.blocks), nv, pq, fold, st), "|Dp|^2");
+      } else if (fe == hipErrorNotSupported) {
+        DSL_TRY(launch_apply(a.op, false, lodt, g, u_lo, p, q, a.mass, st), "inner D p");
+        DSL_TRY(launch_norm2(lodt, q, vol, comps, nv, partial, pq, st), "|Dp|^2");
+      } else {
+        return hipfail(fe, "inner D p");
+      }
       DSL_TRY(launch_cg_scalars(0, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "alpha");
-      DSL_TRY(launch_apply(a.op, true, lodt, g, u_lo, q, s, a.mass, st), "inner D^dag q");
-      DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, vol, comps, nv, partial, rr_new, st), "x/r update");
+      fe = fuse ? launch_wilson_rows(true, lodt, g, u_lo, q, r, a.mass, st, nullptr, false, EPI_AXPY, &ea)
+                : hipErrorNotSupported;
+      if (fe == hipSuccess) {
+        DSL_TRY(launch_finish_sum(partial, int(ea.blocks), nv, rr_new, fold, st), "|r|^2");
+      } else if (fe == hipErrorNotSupported) {
+        DSL_TRY(launch_apply(a.op, true, lodt, g, u_lo, q, s, a.mass, st), "inner D^dag q");
+        DSL_TRY(launch_cg_update_r(lodt, r, s, alpha, vol, comps, nv, partial, rr_new, st), "r update");
+      } else {
+        return hipfail(fe, "inner D^dag q");
+      }
       DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
-      DSL_TRY(launch_cg_update_p(lodt, p, r, beta, vol, comps, nv, st), "p update");
+      DSL_TRY(launch_cg_update_ep(lodt, e, p, r, alpha, beta, vol, comps, nv, st), "e and p update");
       for (int v = 0; v < nv; ++v) h.inner[v] += hact[v] != 0.0;
       DSL_TRY(hipMemcpyAsync(hact, active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
       DSL_TRY(hipStreamSynchronize(st), "sync");
@@ -271,6 +308,7 @@ static int solve_eo(const SolveArgs& a) {
   void* t64 = ws + L.t64;
   void* r64 = ws + L.r64;
   double* partial = reinterpret_cast<double*>(ws + L.partial);
+  double* fold = reinterpret_cast<double*>(ws + L.fold);
   double* sc = reinterpret_cast<double*>(ws + L.scal);
   double *rr = sc, *rr_new = sc + nv, *pq = sc + 2 * nv, *rr0 = sc + 3 * nv, *alpha = sc + 4 * nv,
          *beta = sc + 5 * nv, *active = sc + 6 * nv, *nb2 = sc + 7 * nv, *nr2 = sc + 8 * nv,
@@ -338,14 +376,40 @@ static int solve_eo(const SolveArgs& a) {
     DSL_TRY(hipMemcpyAsync(rr0, rr, nv * sizeof(double), hipMemcpyDeviceToDevice, st), "rr0");
     for (int v = 0; v < nv; ++v) hact[v] = hsc[nv + v] != 0.0 ? 1.0 : 0.0;
     DSL_TRY(hipMemcpyAsync(active, hact, nv * sizeof(double), hipMemcpyHostToDevice, st), "active");
+    // CG on M^dag M with the same fusions as the full-lattice loop: |q|^2 in
+    // the second hop of q = M p, r -= alpha M^dag q in the second hop of M^dag q
     for (int k = 0; k < a.max_inner; ++k) {
-      DSL_TRY(schur(false, p, q), "inner M p");
-      DSL_TRY(launch_norm2(lodt, q, hvol, comps, nv, partial, pq, st), "|Mp|^2");
+      EpiArgs ea;
+      ea.alpha = alpha;
+      ea.partial = partial;
+      ea.capacity = partial_blocks(vol);
+      const bool fuse = knobs().cg_fuse.get(1) != 0;
+      DSL_TRY(launch_wilson_eo_hop(false, lodt, eg, 1, u_odd, u_even, p, tmp, nullptr, 0.0, 1.0, st), "inner M p");
+      hipError_t fe = fuse ? launch_wilson_eo_hop(false, lodt, eg, 0, u_even, u_odd, tmp, q, p, A, -1.0 / A, st,
+                                                  EPI_NORM, &ea)
+                           : hipErrorNotSupported;
+      if (fe == hipSuccess) {
+        DSL_TRY(launch_finish_sum(partial, int(ea.blocks), nv, pq, fold, st), "|Mp|^2");
+      } else if (fe == hipErrorNotSupported) {
+        DSL_TRY(launch_wilson_eo_hop(false, lodt, eg, 0, u_even, u_odd, tmp, q, p, A, -1.0 / A, st), "inner M p");
+        DSL_TRY(launch_norm2(lodt, q, hvol, comps, nv, partial, pq, st), "|Mp|^2");
+      } else {
+        return hipfail(fe, "inner M p");
+      }
       DSL_TRY(launch_cg_scalars(0, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "alpha");
-      DSL_TRY(schur(true, q, s), "inner M^dag q");
-      DSL_TRY(launch_cg_update_xr(lodt, e, r, p, s, alpha, hvol, comps, nv, partial, rr_new, st), "x/r update");
+      DSL_TRY(launch_wilson_eo_hop(true, lodt, eg, 1, u_odd, u_even, q, tmp, nullptr, 0.0, 1.0, st), "inner M^dag q");
+      fe = fuse ? launch_wilson_eo_hop(true, lodt, eg, 0, u_even, u_odd, tmp, r, q, A, -1.0 / A, st, EPI_AXPY, &ea)
+                : hipErrorNotSupported;
+      if (fe == hipSuccess) {
+        DSL_TRY(launch_finish_sum(partial, int(ea.blocks), nv, rr_new, fold, st), "|r|^2");
+      } else if (fe == hipErrorNotSupported) {
+        DSL_TRY(launch_wilson_eo_hop(true, lodt, eg, 0, u_even, u_odd, tmp, s, q, A, -1.0 / A, st), "inner M^dag q");
+        DSL_TRY(launch_cg_update_r(lodt, r, s, alpha, hvol, comps, nv, partial, rr_new, st), "r update");
+      } else {
+        return hipfail(fe, "inner M^dag q");
+      }
       DSL_TRY(launch_cg_scalars(1, nv, rr, rr_new, pq, rr0, alpha, beta, active, a.inner_tol, st), "beta");
-      DSL_TRY(launch_cg_update_p(lodt, p, r, beta, hvol, comps, nv, st), "p update");
+      DSL_TRY(launch_cg_update_ep(lodt, e, p, r, alpha, beta, hvol, comps, nv, st), "e and p update");
       for (int v = 0; v < nv; ++v) h.inner[v] += hact[v] != 0.0;
       DSL_TRY(hipMemcpyAsync(hact, active, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy active");
       DSL_TRY(hipStreamSynchronize(st), "sync");
