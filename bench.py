@@ -57,8 +57,8 @@ CLOVER_FLOPS = 576             # two 6x6 complex matrix-vector products and thei
 # inner tolerance on this system for each storage).
 SOLVE_DIMS, SOLVE_NV, SOLVE_M0, SOLVE_TOL = (32, 32, 32, 64), 12, 0.05, 1e-10
 SOLVE_SETTINGS = {
-    "full": (("c64", 1e-5), ("bf16", 0.02), ("f16", 2e-3)),
-    "eo": (("c64", 1e-5), ("bf16", 0.01), ("f16", 5e-3)),
+    "full": (("c64", 3e-4), ("bf16", 0.02), ("f16", 2e-3)),
+    "eo": (("c64", 3e-4), ("bf16", 5e-3), ("f16", 5e-3)),
 }
 
 
