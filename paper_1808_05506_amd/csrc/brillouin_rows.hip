@@ -349,6 +349,198 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- FP64, staged straight into LDS
+// The FP64 D_B keeps the row staging of brillouin_rows_kernel, but its rows
+// are copied from global memory into LDS by the direct-to-LDS load path
+// (global_load_lds_dwordx4: lane l of a wave writes LDS bytes [b + 16 l,
+// b + 16 l + 16) for a wave-uniform b), so no staged row passes through
+// registers.  With the hop computed one colour row of the link at a time the
+// kernel fits three waves per SIMD, where register staging of FP64 rows
+// allowed one.  A row in LDS is [halo x0 - 1][the chunk's n sites][halo
+// x0 + n] without padding (16-byte reads of consecutive lanes fall on
+// consecutive banks), then its three link columns [dx + 1][site][9].
+// Workgroup: 16 sites x N_v right-hand sides, a multiple of 64 threads, so
+// every wave covers whole 64-piece LDS ranges; chunks of fewer live sites
+// (the row's last, or rows shorter than 16) stage only their own.
+constexpr int kDmaSites = 16;
+
+__device__ __forceinline__ void lds_dma16(const void* src, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
+// Stage row r (spinor run with halos, three link columns) of chunk c into buf
+// and wbuf: LDS piece L of the row is loaded by lane L % 64 of wave
+// (L / 64) % waves, instruction L / (64 waves).
+template <int NV>
+__device__ __forceinline__ void bri_dma_row(const Geom& g, const RowChunk& c, const C128::word* __restrict__ Wl,
+                                            const C128::word* __restrict__ in, int r, int xm, int xp, int wave,
+                                            int lane, int waves, char* buf, char* wbuf) {
+  constexpr int SP = 12 * NV;  // 16-byte pieces (FP64 complex words) per site
+  int dy, dz, dt;
+  bri_row_offset(r, dy, dz, dt);
+  const uint32_t nb = bri_row_base(g, c, dy, dz, dt);
+  const int np = (c.n + 2) * SP;
+  for (int base = wave * 64; base < np; base += waves * 64) {
+    const int L = base + lane;
+    if (L < np) {
+      const int slot = L / SP, pp = L - slot * SP;
+      const int site = slot == 0 ? xm : (slot == c.n + 1 ? xp : c.x0 + slot - 1);
+      lds_dma16(in + size_t(nb + site) * SP + pp, buf + size_t(__builtin_amdgcn_readfirstlane(base)) * 16);
+    }
+  }
+  const int nw = 27 * kDmaSites;
+  for (int base = wave * 64; base < nw; base += waves * 64) {
+    const int L = base + lane;
+    if (L < nw) {
+      const int col = L / (9 * kDmaSites), rem = L - col * 9 * kDmaSites;
+      int site = rem / 9;
+      const int e = rem - site * 9;
+      site = site < c.n ? site : c.n - 1;
+      const int code = bri_code(col - 1, dy, dz, dt);
+      size_t idx;
+      if (code > 40) {
+        idx = (size_t(c.row_base + c.x0 + site) * 40 + (code - 41)) * 9 + e;  // W_d(x), stored
+      } else {
+        const int slot = code == 40 ? 0 : 39 - code;  // W_{-d}(x + d); d = 0: any valid word (unused)
+        idx = (size_t(nb + wrap_x(g, c.x0 + site + col - 1)) * 40 + slot) * 9 + e;
+      }
+      lds_dma16(Wl + idx, wbuf + size_t(__builtin_amdgcn_readfirstlane(base)) * 16);
+    }
+  }
+}
+
+// acc += (a + b d.gamma) W' psi for one hop, W' = the link or its adjoint,
+// taken one source spin at a time: chi_q = W' psi_q (one colour triple) goes
+// to acc_q with weight a and, for every non-zero d_mu, to the spin that
+// gamma_mu pairs with q (chiral basis, as in bri_hop), so only psi_q and chi_q
+// are live beside the link.
+template <int NV, class T>
+__device__ __forceinline__ void bri_hop_lean(const C128::word* site, const C128::word* link, bool dag, int v, T a,
+                                             T B1, T B2, T B3, T B4, int d0, int d1, int d2, int d3,
+                                             cpx<T> (&acc)[4][3]) {
+  cpx<T> u[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const cpx<T> l = C128::template load<T>(link + (dag ? j * 3 + i : i * 3 + j));
+      u[i][j].r = l.r;
+      u[i][j].i = dag ? -l.i : l.i;
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cpx<T> p[3], chi[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) p[b] = C128::template load<T>(site + (q * 3 + b) * NV + v);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      cpx<T> t = zero<T>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t = cmadd(t, u[cc][b], p[b]);
+      chi[cc] = t;
+      acc[q][cc] = rmadd(acc[q][cc], a, t);
+    }
+    // partner spins: gamma_4 and gamma_3 pair q with q ^ 2, gamma_2 and gamma_1
+    // with 3 - q; the factors, by source spin q = 0, 1, 2, 3:
+    //   gamma_4: B4 (all)   gamma_3: i B3 (+, -, -, +)
+    //   gamma_2: B2 (-, +, +, -)   gamma_1: i B1 (+, +, -, -)
+    const int P43 = q ^ 2, P21 = 3 - q;
+    const T s3 = (q == 1 || q == 2) ? T(-1) : T(1);
+    const T s2 = (q == 1 || q == 2) ? T(1) : T(-1);
+    const T s1 = q <= 1 ? T(1) : T(-1);
+    // d is uniform over the workgroup: scalar branches skip the zero axes
+    if (__builtin_amdgcn_readfirstlane(d3) != 0) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[P43][cc] = rmadd(acc[P43][cc], B4, chi[cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d2) != 0) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[P43][cc] = cmadd_i(acc[P43][cc], s3 * B3, chi[cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d1) != 0) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[P21][cc] = rmadd(acc[P21][cc], s2 * B2, chi[cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d0) != 0) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) acc[P21][cc] = cmadd_i(acc[P21][cc], s1 * B1, chi[cc]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) hold(acc[q][cc]);
+}
+
+constexpr size_t kDmaRowBytes = (size_t(kDmaSites + 2) * 12 * 12 + size_t(27) * kDmaSites) * 16;
+
+// One row buffer, three workgroups per CU: each loads a row, then applies it,
+// while the others do the same out of step.
+template <bool ADJ, int NV>
+__global__ void __launch_bounds__(kDmaSites * NV, 3)
+    brillouin_rows_dma_kernel(Geom g, RowTraversal tr, int xcd, const C128::word* __restrict__ Wl,
+                              const C128::word* __restrict__ in, C128::word* __restrict__ out, double diag) {
+  using T = double;
+  constexpr int SW = 12 * NV;
+  extern __shared__ uint4 smem_bdma[];
+  char* const buf = reinterpret_cast<char*>(smem_bdma);       // [(16 + 2) SW] pieces: the row with its halos
+  char* const wbuf = buf + size_t(kDmaSites + 2) * SW * 16;   // [3][16][9] pieces: its link columns
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const RowChunk c = row_chunk(g, tr, L);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v;
+  const int wave = tid >> 6, lane = tid & 63, waves = kDmaSites * NV / 64;
+  const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) acc[q][cc] = zero<T>();
+
+#pragma nounroll
+  for (int r = 0; r < kBriRows; ++r) {
+    __syncthreads();  // the previous row's hops are done with the buffers
+    bri_dma_row<NV>(g, c, Wl, in, r, xm, xp, wave, lane, waves, buf, wbuf);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const C128::word* lrow = reinterpret_cast<const C128::word*>(buf);
+    const C128::word* lw = reinterpret_cast<const C128::word*>(wbuf);
+    int dy, dz, dt;
+    bri_row_offset(r, dy, dz, dt);
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int k = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
+      const C128::word* site = lrow + (xl + 1 + dx) * SW;
+      if (k == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            acc[q][cc] = rmadd(acc[q][cc], diag, C128::template load<T>(site + (q * 3 + cc) * NV + v));
+        continue;
+      }
+      const T a = T(-0.5) * bri_lambda<T>(k);
+      const T b = (ADJ ? T(-1) : T(1)) * bri_rho<T>(k);
+      const C128::word* link = lw + ((dx + 1) * kDmaSites + xl) * 9;
+      bri_hop_lean<NV, T>(site, link, bri_code(dx, dy, dz, dt) <= 40, v, a, b * T(dx), b * T(dy), b * T(dz),
+                          b * T(dt), dx, dy, dz, dt, acc);
+    }
+  }
+  // each lane writes its own 12 words: the N_v lanes of a site cover 16 N_v
+  // contiguous bytes per component
+  if (xl < c.n) {
+    u32x4* o = reinterpret_cast<u32x4*>(out + size_t(c.row_base + c.x0 + xl) * SW + v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        __builtin_nontemporal_store(__builtin_bit_cast(u32x4, make_double2(acc[q][cc].r, acc[q][cc].i)),
+                                    o + (q * 3 + cc) * NV);
+  }
+}
+
 // Chunk length of the row-staged D_B for N_v = 12 in C64, or 0 when the
 // configuration is not covered.
 static int brillouin_rows_sites(int dtype, const Geom& g) {
@@ -369,6 +561,19 @@ static int brillouin_rows_sites(int dtype, const Geom& g) {
 hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
                                  double mass, hipStream_t st, const void* clover) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (dtype == DT_C128 && g.nv == 12 && !clover) {
+    // FP64: the direct-to-LDS staged kernel, chunks of 16 sites
+    const RowTraversal tr = make_row_traversal(g, uint32_t(kDmaSites), uint32_t(knobs().tband.get(2)));
+    const dim3 block(12, kDmaSites), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+    const bool xcd = knobs().xcd.get(1) != 0;
+    const double diag = mass + 15.0 / 8.0;
+#define DSL_BD(A)                                                                                         \
+  hipLaunchKernelGGL((brillouin_rows_dma_kernel<A, 12>), grid, block, kDmaRowBytes, st, g, tr, int(xcd), \
+                     (const C128::word*)Wl, (const C128::word*)in, (C128::word*)out, diag)
+    if (adj) DSL_BD(true); else DSL_BD(false);
+#undef DSL_BD
+    return hipGetLastError();
+  }
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0) return hipErrorNotSupported;
   int bt = 2;
