@@ -463,11 +463,11 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
             raise RuntimeError("dslash_backward failed")
 
     def vgrad(i):
-        if lib.dslash_brillouin_links_backward(vp(V), vp(gW), vp(gV), dims_c, 3, 0, stream):
+        if lib.dslash_brillouin_links_backward(vp(V), vp(W), vp(gW), vp(gV), dims_c, 3, 0, stream):
             raise RuntimeError("dslash_brillouin_links_backward failed")
     nsteps = max(3, steps // 20)
     bw = (2 * 12 * 12 * 8 + 360 * 8) * vol   # chi and psi read, G_W written
-    bv = (36 * 8 + 360 * 8 + 36 * 8) * vol   # V and G_W read, G_V written
+    bv = (360 * 8 + 360 * 8 + 36 * 8) * vol   # W and G_W read, G_V written
     rows["link_grad_brillouin_W_24^3x48_nv12_fp32"] = launch_row(torch, wgrad, nsteps, 1, bw, 1,
                                                                  "Brillouin link grad (W)", single=10)
     rows["brillouin_links_backward_24^3x48_fp32"] = launch_row(torch, vgrad, nsteps, 1, bv, 1,

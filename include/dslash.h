@@ -143,12 +143,16 @@ int dslash_apply_clover(int op, const void* U, const void* C, const void* in, vo
  * (P, Q the products before and after it), or the adjoint of that for a hop
  * against the link (A_i = V_mu(y - mu)^dag).  Together with the BRILLOUIN
  * branch of dslash_backward this is the link gradient of D_B with respect to
- * V.  V: [..][4][3][3]; grad_W: [..][40][3][3]; grad_V: [..][4][3][3]
+ * V.  V: [..][4][3][3]; W (nullable): dslash_brillouin_links(V), the stored
+ * off-axis links of the same V -- with it the orderings that share the hops
+ * before and after hop i are summed at once as |S|! |R|! W_S^dag grad_W W_R^dag
+ * (W_S, W_R the path averages of the sub-displacements), without it every
+ * ordering is walked through V; grad_W: [..][40][3][3]; grad_V: [..][4][3][3]
  * (written, deterministic: no atomics).  C64 and C128 only.  grad_V must not
- * overlap V or grad_W (E_ALIAS).  Asynchronous on `stream`.
+ * overlap V, W or grad_W (E_ALIAS).  Asynchronous on `stream`.
  */
-int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* grad_V, const int dims[4], int Nc,
-                                    int dtype, void* stream);
+int dslash_brillouin_links_backward(const void* V, const void* W, const void* grad_W, void* grad_V, const int dims[4],
+                                    int Nc, int dtype, void* stream);
 
 /*
  * out = D_B in (adjoint == 0) or D_B^dag in, with the off-axis links W_d(x)

@@ -325,6 +325,128 @@ __global__ void __launch_bounds__(128) bri_links_backward_kernel(Geom g, const t
     for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
 }
 
+// W_{dd}(x) for any displacement dd in {-1, 0, 1}^4: the stored W_dd(x), or
+// W_{-dd}(x + dd)^dag (Tab. 1 caption) for the other 40, or 1 for dd = 0.
+template <class S, class T>
+DSL_HD void load_w_any(const Geom& g, const typename S::word* __restrict__ W, const int (&x)[4], const int (&dd)[4],
+                       cpx<T> (&w)[3][3]) {
+  const int n = (dd[0] + 1) + 3 * (dd[1] + 1) + 9 * (dd[2] + 1) + 27 * (dd[3] + 1);
+  if (n == 40) {
+    m3_identity(w);
+  } else if (n > 40) {
+    load_link<S, T>(W, (size_t(site_of(g, x)) * 40 + (n - 41)) * 9, w);
+  } else {
+    int y[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) y[mu] = wrap(x[mu] + dd[mu], g.n[mu]);
+    cpx<T> t[3][3];
+    load_link<S, T>(W, (size_t(site_of(g, y)) * 40 + (39 - n)) * 9, t);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) w[a][b] = conj(t[b][a]);
+  }
+}
+
+// The adjoint of the W construction with the path averages of W itself.  The
+// hop along mu sits in the k! orderings of d behind the hops of a subset S of
+// d's other axes (in any order) and before the rest R; summed over those
+// orderings the products before and after it are |S|! W_{e_S}(x) and
+// |R|! W_{e_R}(z), the path averages of the sub-displacements (x the path's
+// start, z the site after the hop).  So
+//   G_V = sum_d sum_S |S|! |R|! / k! W_{e_S}(x)^dag G_{W_d}(x) W_{e_R}(z)^dag,
+// adjoint for a hop against the link: 2^(k-1) terms per direction instead of
+// k! walks of up to k - 1 links.  W: the stored off-axis links of V.
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_links_backward_w_kernel(Geom g, const typename S::word* __restrict__ W,
+                                                                  const typename S::word* __restrict__ GW,
+                                                                  typename S::word* __restrict__ GV) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = int(blockIdx.y);  // link direction, uniform over the block
+  if (y >= g.vol) return;
+  const SiteNbr nb = site_nbr(g, y);
+  cpx<T> acc[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = zero<T>();
+  const int fact[5] = {1, 1, 2, 6, 24};
+
+#pragma unroll 1
+  for (int j = 0; j < 40; ++j) {
+    int d[4];
+    stored_direction(j, d);
+    if (d[mu] == 0) continue;  // uniform: j and mu are the same for the whole wave
+    const int sg = d[mu];
+    int other[3], no = 0;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu)
+      if (nu != mu && d[nu] != 0) other[no++] = nu;
+    const int k = no + 1;
+    // the hop starts at y (forward) or at y + mu (against the link); it ends at z
+    int h[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]}, z[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+    if (sg < 0) h[mu] = wrap(h[mu] + 1, g.n[mu]);
+    else z[mu] = wrap(z[mu] + 1, g.n[mu]);
+#pragma unroll 1
+    for (int mask = 0; mask < (1 << no); ++mask) {
+      int eS[4] = {0, 0, 0, 0}, eR[4] = {0, 0, 0, 0}, ns = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (i >= no) continue;
+        const int nu = other[i];
+        if (mask & (1 << i)) {
+          eS[nu] = d[nu];
+          ++ns;
+        } else {
+          eR[nu] = d[nu];
+        }
+      }
+      int x[4];
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) x[nu] = wrap(h[nu] - eS[nu], g.n[nu]);
+      const T coef = T(fact[ns] * fact[no - ns]) / T(fact[k]);
+      // an empty S or R is the identity: its product is skipped (mask is
+      // uniform over the wave)
+      cpx<T> X[3][3], Tm[3][3];
+      load_link<S, T>(GW, (size_t(site_of(g, x)) * 40 + j) * 9, X);
+      if (ns > 0) {
+        cpx<T> WS[3][3];
+        load_w_any<S, T>(g, W, x, eS, WS);
+        m3_adj_mul(WS, X, Tm);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) X[r][c] = Tm[r][c];
+      }
+      if (ns < no) {
+        cpx<T> WR[3][3];
+        load_w_any<S, T>(g, W, z, eR, WR);
+        m3_mul_adj(X, WR, Tm);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) X[r][c] = Tm[r][c];
+      }
+      if (sg > 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][c] = rmadd(acc[r][c], coef, X[r][c]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][c] = rmadd(acc[r][c], coef, conj(X[c][r]));
+      }
+    }
+  }
+  typename S::word* o = GV + (size_t(y) * 4 + mu) * 9;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
+}
+
 namespace {
 
 template <class S, class T>
@@ -339,10 +461,14 @@ hipError_t wgrad_t(const Geom& g, const void* chi, const void* psi, void* GW, hi
 }
 
 template <class S, class T>
-hipError_t links_backward_t(const Geom& g, const void* V, const void* GW, void* GV, hipStream_t st) {
+hipError_t links_backward_t(const Geom& g, const void* V, const void* Wl, const void* GW, void* GV, hipStream_t st) {
   using W = typename S::word;
   const dim3 block(128), grid((g.vol + 127) / 128, 4);
-  hipLaunchKernelGGL((bri_links_backward_kernel<S, T>), grid, block, 0, st, g, (const W*)V, (const W*)GW, (W*)GV);
+  if (Wl)
+    hipLaunchKernelGGL((bri_links_backward_w_kernel<S, T>), grid, block, 0, st, g, (const W*)Wl, (const W*)GW,
+                       (W*)GV);
+  else
+    hipLaunchKernelGGL((bri_links_backward_kernel<S, T>), grid, block, 0, st, g, (const W*)V, (const W*)GW, (W*)GV);
   return hipGetLastError();
 }
 
@@ -357,11 +483,11 @@ hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, con
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* GW, void* GV,
-                                           hipStream_t st) {
+hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* W, const void* GW,
+                                           void* GV, hipStream_t st) {
   switch (dtype) {
-    case DT_C64: return links_backward_t<C64, float>(g, V, GW, GV, st);
-    case DT_C128: return links_backward_t<C128, double>(g, V, GW, GV, st);
+    case DT_C64: return links_backward_t<C64, float>(g, V, W, GW, GV, st);
+    case DT_C128: return links_backward_t<C128, double>(g, V, W, GW, GV, st);
   }
   return hipErrorInvalidValue;
 }

@@ -214,8 +214,8 @@ int dslash_backward(int op, const void* U, const void* grad_out, const void* in,
   return DSLASH_OK;
 }
 
-int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* grad_V, const int dims[4], int Nc,
-                                    int dtype, void* stream) {
+int dslash_brillouin_links_backward(const void* V, const void* W, const void* grad_W, void* grad_V, const int dims[4],
+                                    int Nc, int dtype, void* stream) {
   g_err[0] = 0;
   if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return rc;
   if (dtype != DSLASH_C64 && dtype != DSLASH_C128)
@@ -224,10 +224,10 @@ int dslash_brillouin_links_backward(const void* V, const void* grad_W, void* gra
   const uint64_t vol = volume(dims);
   const size_t eb = dsl::dtype_bytes(dtype);
   const size_t nv = size_t(vol) * 36 * eb, nw = size_t(vol) * 360 * eb;
-  if (overlap(grad_V, nv, V, nv) || overlap(grad_V, nv, grad_W, nw))
+  if (overlap(grad_V, nv, V, nv) || overlap(grad_V, nv, grad_W, nw) || (W && overlap(grad_V, nv, W, nw)))
     return fail(DSLASH_E_ALIAS, "grad_V overlaps an input");
   const dsl::Geom g = dsl::make_geom(dims, 1);
-  hipError_t e = dsl::launch_brillouin_links_backward(dtype, g, V, grad_W, grad_V, (hipStream_t)stream);
+  hipError_t e = dsl::launch_brillouin_links_backward(dtype, g, V, W, grad_W, grad_V, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "dslash_brillouin_links_backward launch");
   return DSLASH_OK;
 }

@@ -67,7 +67,7 @@ def _load():
     lib.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     lib.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
-    lib.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
+    lib.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, vp, ip, i, i, vp]
     lib.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
@@ -301,8 +301,10 @@ def brillouin_links(V: torch.Tensor) -> torch.Tensor:
     return W
 
 
-def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor) -> torch.Tensor:
-    """Gradient with respect to V of Re sum conj(grad_W) W[V] (adjoint of ``brillouin_links``)."""
+def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Tensor | None = None) -> torch.Tensor:
+    """Gradient with respect to V of Re sum conj(grad_W) W[V] (adjoint of ``brillouin_links``).
+    W: optional ``brillouin_links(V)``; with it the adjoint sums the orderings
+    of each path through the path averages of W (faster)."""
     _require(V, "V")
     _require(grad_W, "grad_W")
     vs = _core_shape(V)
@@ -310,22 +312,28 @@ def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor) -> torch.Ten
         raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
     if tuple(grad_W.shape) != vs[:4] + (40, 3, 3) or grad_W.dtype != V.dtype:
         raise ValueError("grad_W must be [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
+    if W is not None:
+        _require(W, "W")
+        if W.shape != grad_W.shape or W.dtype != V.dtype or W.device != V.device:
+            raise ValueError("W must be brillouin_links(V): [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
     gV = torch.empty_like(V)
-    _check(_lib.dslash_brillouin_links_backward(_ptr(V), _ptr(grad_W), _ptr(gV), _dims_c(vs), 3, _dtype_code(V),
-                                                _stream(V)), "dslash_brillouin_links_backward")
+    _check(_lib.dslash_brillouin_links_backward(_ptr(V), _ptr(W) if W is not None else None, _ptr(grad_W), _ptr(gV),
+                                                _dims_c(vs), 3, _dtype_code(V), _stream(V)),
+           "dslash_brillouin_links_backward")
     return gV
 
 
 class _BrillouinLinksFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, V):
-        ctx.save_for_backward(V)
-        return brillouin_links(V)
+        W = brillouin_links(V)
+        ctx.save_for_backward(V, W)
+        return W
 
     @staticmethod
     def backward(ctx, g):
-        (V,) = ctx.saved_tensors
-        return brillouin_links_backward(V, g.contiguous())
+        V, W = ctx.saved_tensors
+        return brillouin_links_backward(V, g.contiguous(), W)
 
 
 def brillouin_links_autograd(V: torch.Tensor) -> torch.Tensor:

@@ -43,7 +43,7 @@ def lib():
     l.dslash_apply_clover.argtypes = [i, vp, vp, vp, vp, ip, i, i, d, i, i, vp]
     l.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     l.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
-    l.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, ip, i, i, vp]
+    l.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, vp, ip, i, i, vp]
     l.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     return l
 
@@ -214,11 +214,13 @@ def test_compressed_validation(lib):
 
 def test_brillouin_links_backward_validation(lib):
     dims = _dims(4, 4, 4, 4)
-    assert lib.dslash_brillouin_links_backward(None, B, C, dims, 3, 0, None) == 1   # NULL V
-    assert lib.dslash_brillouin_links_backward(A, B, A, dims, 3, 0, None) == 3      # grad_V == V
-    assert lib.dslash_brillouin_links_backward(A, B, B, dims, 3, 0, None) == 3      # grad_V == grad_W
-    assert lib.dslash_brillouin_links_backward(A, B, C, dims, 3, 2, None) == 2      # BF16
-    assert lib.dslash_brillouin_links_backward(A, B, C, dims, 2, 0, None) == 2      # Nc != 3
+    D = 0x20000000
+    assert lib.dslash_brillouin_links_backward(None, None, B, C, dims, 3, 0, None) == 1   # NULL V
+    assert lib.dslash_brillouin_links_backward(A, None, B, A, dims, 3, 0, None) == 3      # grad_V == V
+    assert lib.dslash_brillouin_links_backward(A, None, B, B, dims, 3, 0, None) == 3      # grad_V == grad_W
+    assert lib.dslash_brillouin_links_backward(A, D, B, D, dims, 3, 0, None) == 3         # grad_V == W
+    assert lib.dslash_brillouin_links_backward(A, None, B, C, dims, 3, 2, None) == 2      # BF16
+    assert lib.dslash_brillouin_links_backward(A, None, B, C, dims, 2, 0, None) == 2      # Nc != 3
 
 
 def test_brillouin_fly_validation(lib):

@@ -36,14 +36,18 @@ def test_wgrad_matches_oracle(dt, dims, nv):
     compare(down(gi), brillouin.apply(down(W), down(up(chi, dt)), 0.1, True), dt, "grad_in")
 
 
+@pytest.mark.parametrize("with_w", [False, True])
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("dims", [(3, 3, 2, 3), (4, 3, 3, 5)])
-def test_links_backward_matches_oracle(dt, dims):
-    say(f"case brillouin links backward {dims} {dt}")
+@pytest.mark.parametrize("dims", [(3, 3, 2, 3), (4, 3, 3, 5), (5, 4, 3, 4)])
+def test_links_backward_matches_oracle(dt, dims, with_w):
+    # without W every hop ordering is walked through V; with W the orderings
+    # that share the hops before and after the link are summed through the
+    # path averages of W
+    say(f"case brillouin links backward {dims} {dt} with_w={with_w}")
     v = synthetic.gauge_links(dims, "haar", 120)
     gw = synthetic.gaussian(v.shape[:4] + (40, 3, 3), 121)
     V, GW = up(v, dt), up(gw, dt)
-    gV = D.brillouin_links_backward(V, GW)
+    gV = D.brillouin_links_backward(V, GW, D.brillouin_links(V) if with_w else None)
     ref = grad.brillouin_links_backward(down(V), down(GW))
     compare(down(gV), ref, dt, "G_V from G_W")
 
@@ -80,4 +84,7 @@ def test_brillouin_gradients_deterministic():
     assert torch.equal(a, b)
     ga = D.brillouin_links_backward(V, a)
     gb = D.brillouin_links_backward(V, a)
+    assert torch.equal(ga, gb)
+    ga = D.brillouin_links_backward(V, a, W)
+    gb = D.brillouin_links_backward(V, a, W)
     assert torch.equal(ga, gb)
