@@ -306,6 +306,24 @@ def staggered_rows_bench(torch, D, np, synthetic, steps, warmup):
     return rows
 
 
+def block_size_rows_bench(torch, D, np, synthetic, steps, warmup):
+    """D_W on the headline lattice (16^3 x 32, FP32, smooth links seed 1, rhs
+    seed 101) at other block sizes N_v: 4, 8, 16 and 24 take the row-staged
+    t-marching kernel, N_v = 1 the direct one."""
+    rows = {}
+    dev = torch.device("cuda:0")
+    dims = (16, 16, 16, 32)
+    U = torch.from_numpy(synthetic.gauge_links(dims, "smooth", 1).astype(np.complex64)).to(dev)
+    for nv in (1, 4, 8, 16, 24):
+        P = torch.from_numpy(synthetic.wilson_spinor(dims, nv, 101).astype(np.complex64)).to(dev)
+        rows[f"wilson_16^3x32_nv{nv}_fp32"], _ = bench_apply(torch, D, "wilson", U, P, 0.1, steps, warmup, 4, 8,
+                                                             f"D_W 16^3x32 nv{nv} fp32")
+        del P
+    del U
+    torch.cuda.empty_cache()
+    return rows
+
+
 def brillouin_rows_bench(torch, D, np, synthetic, steps, fly=False):
     """The D_B rows on 32^4, N_v = 12: FP32 and FP64 with the W construction
     time, and (fly) the clover term and W built on the fly in FP32."""
@@ -382,6 +400,7 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
         return torch.from_numpy(a.astype(dt)).to(dev)
 
     rows.update(staggered_rows_bench(torch, D, np, synthetic, steps, warmup))
+    rows.update(block_size_rows_bench(torch, D, np, synthetic, steps, warmup))
     rows.update(brillouin_rows_bench(torch, D, np, synthetic, steps, fly=True))
     # D_W with BF16 storage (FP32 arithmetic) on the headline workload
     dims = (16, 16, 16, 32)
@@ -534,8 +553,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=4)
-    ap.add_argument("--rows", choices=["all", "none", "staggered", "solve", "brillouin"], default="all",
-                    help="the other rows: all, none, or only the D_S ones, the solves or the D_B ones")
+    ap.add_argument("--rows", choices=["all", "none", "staggered", "solve", "brillouin", "nv"], default="all",
+                    help="the other rows: all, none, or only the D_S ones, the solves, the D_B ones or the D_W "
+                         "ones at other block sizes N_v")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain FP32 complex copy of this many MiB (counter calibration)")
@@ -591,6 +611,8 @@ def main():
         rows = solve_rows_bench(torch, D, np, synthetic)
     elif args.rows == "brillouin":
         rows = brillouin_rows_bench(torch, D, np, synthetic, args.steps)
+    elif args.rows == "nv":
+        rows = block_size_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
 
     cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
     if args.rows == "all" and not args.no_cpu:

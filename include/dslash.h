@@ -347,6 +347,16 @@ const char* dslash_last_error(void);
 /* ABI version (major*100 + minor). */
 int dslash_version(void);
 
+/*
+ * Re-reads the tuning variables DSLASH_<NAME> (chunk length, prefetch depth,
+ * t steps per workgroup, buffer scheme, kernel family, ...) from the
+ * environment.  They are read once per process, at the first launch that
+ * consults them; a caller that changes them later (a tuning sweep, a test of
+ * each kernel form) calls this afterwards.  Not to be called while another
+ * thread launches.  Returns DSLASH_OK.
+ */
+int dslash_reload_tuning(void);
+
 #ifdef __cplusplus
 }
 #endif

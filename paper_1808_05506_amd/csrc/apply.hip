@@ -137,25 +137,30 @@ static hipError_t apply_op(bool adj, int dtype, const Geom& g, const void* U, co
   return hipErrorInvalidValue;
 }
 
+// DSLASH_ROWS: 0 the direct kernels only, 1 (default) the row-staged kernel
+// where it covers the configuration and the direct one elsewhere, 2 the
+// row-staged kernel or hipErrorNotSupported (to test that a configuration
+// takes it).
 hipError_t launch_apply(int op, bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                         double mass, hipStream_t st, const void* clover, bool compressed) {
+  const bool rows_only = knobs().rows.get(1) == 2;
   switch (op) {
     case OP_STAGGERED: {
       if (clover) return hipErrorInvalidValue;
       const hipError_t e = launch_staggered_rows(adj, dtype, g, U, in, out, mass, st, compressed);
-      if (e != hipErrorNotSupported) return e;
+      if (e != hipErrorNotSupported || rows_only) return e;
       return apply_op<OP_STAGGERED>(adj, dtype, g, U, in, out, nullptr, mass, compressed, st);
     }
     case OP_WILSON: {
       if (clover && compressed) return hipErrorInvalidValue;
       const hipError_t e = launch_wilson_rows(adj, dtype, g, U, in, out, mass, st, clover, compressed);
-      if (e != hipErrorNotSupported) return e;
+      if (e != hipErrorNotSupported || rows_only) return e;
       return apply_op<OP_WILSON>(adj, dtype, g, U, in, out, clover, mass, compressed, st);
     }
     case OP_BRILLOUIN: {
       if (compressed) return hipErrorInvalidValue;
       const hipError_t e = launch_brillouin_rows(adj, dtype, g, U, in, out, mass, st, clover);
-      if (e != hipErrorNotSupported) return e;
+      if (e != hipErrorNotSupported || rows_only) return e;
       return apply_op<OP_BRILLOUIN>(adj, dtype, g, U, in, out, clover, mass, false, st);
     }
   }

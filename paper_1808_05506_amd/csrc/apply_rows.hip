@@ -82,14 +82,139 @@ __device__ __forceinline__ W piece_to_word(u32x4 z) {
 }
 
 // One thread's share of a neighbour row in flight: CH 16-byte pieces of the
-// spinor run (pieces tid, tid + nth, ...) plus, for a backward hop, one word of
-// the V_mu piece of the row's links (held as a 16-byte register group so the
-// whole row is one array).  The piece count per thread does not depend on R:
-// a row chunk is R * 12 NV words and the workgroup has R * NV threads.
+// spinor run (pieces tid, tid + nth, ...) plus E more 16-byte register groups
+// (so that the whole row is one array) for, on a backward hop, the thread's
+// ceil(9 / N_v) words of the row's V_mu links, packed, or, on the own row, its
+// pieces of the two halo sites.  The piece count per thread does not depend on
+// R: a row chunk is R * 12 NV words and the workgroup has R * NV threads.
 template <class S>
 struct RowPieces {
   static constexpr int CH = 12 * int(sizeof(typename S::word)) / 16;
 };
+
+// E for N_v right-hand sides and wb-byte storage words.  The halo needs
+// 2 * 12 N_v words in R N_v threads, 24 wb / (16 R) groups a thread: one at
+// the R >= 16 that a workgroup of at most 256 threads holds up to N_v = 16,
+// two for the R = 8 taken at larger N_v with 8-byte words.
+DSL_HD constexpr int row_extra_groups(int nv, int wb) {
+  const int links = (((9 + nv - 1) / nv) * wb + 15) / 16;
+  const int halo = nv > 16 ? (24 * wb / 16 + 7) / 8 : 1;
+  return links > halo ? links : halo;
+}
+
+template <int NV, class S>
+struct RowRegs {
+  static constexpr int CH = RowPieces<S>::CH;
+  static constexpr int E = row_extra_groups(NV, int(sizeof(typename S::word)));
+  static constexpr int N = CH + E;
+};
+
+template <int NV, class S>
+using RowBuf = u32x4[RowRegs<NV, S>::N];
+
+// Word i of the thread's link words (i = 0 .. KW - 1) in group i / PER of the
+// extra groups, PER = 16 / word bytes words to a group, and back.
+template <class W, int KW>
+__device__ __forceinline__ u32x4 pack_words(const W (&w)[KW], int i0) {
+  constexpr int WB = int(sizeof(W));
+  if constexpr (WB == 16) {
+    return i0 < KW ? __builtin_bit_cast(u32x4, w[i0]) : u32x4{0u, 0u, 0u, 0u};
+  } else if constexpr (WB == 8) {
+    const u32x2 a = i0 < KW ? __builtin_bit_cast(u32x2, w[i0]) : u32x2{0u, 0u};
+    const u32x2 b = i0 + 1 < KW ? __builtin_bit_cast(u32x2, w[i0 + 1]) : u32x2{0u, 0u};
+    return u32x4{a.x, a.y, b.x, b.y};
+  } else {
+    static_assert(__is_same(W, uint32_t), "4-byte storage words are uint32_t");
+    return u32x4{i0 < KW ? w[i0] : 0u, i0 + 1 < KW ? w[i0 + 1] : 0u, i0 + 2 < KW ? w[i0 + 2] : 0u,
+                 i0 + 3 < KW ? w[i0 + 3] : 0u};
+  }
+}
+
+template <class W>
+__device__ __forceinline__ W unpack_word(u32x4 z, int k) {
+  constexpr int WB = int(sizeof(W));
+  if constexpr (WB == 16) {
+    return __builtin_bit_cast(W, z);
+  } else if constexpr (WB == 8) {
+    return __builtin_bit_cast(W, k == 0 ? u32x2{z.x, z.y} : u32x2{z.z, z.w});
+  } else {
+    return k == 0 ? z.x : (k == 1 ? z.y : (k == 2 ? z.z : z.w));
+  }
+}
+
+// The backward hop's links V_mu(x - mu) of the chunk's n sites (LW words at
+// stride 4 LW in U, from row site nrow): the thread's word i is word
+// tid + i nth of the run, clamped to its last word.
+template <int MU, int NV, class S, int LW>
+__device__ __forceinline__ void lnb_issue(const typename S::word* __restrict__ U, uint32_t nrow, int n, int tid,
+                                          RowBuf<NV, S>& r) {
+  using W = typename S::word;
+  constexpr int CH = RowRegs<NV, S>::CH, E = RowRegs<NV, S>::E;
+  constexpr int KW = (LW + NV - 1) / NV, PER = 16 / int(sizeof(W));
+  static_assert((KW + PER - 1) / PER <= E, "the link words fit the extra groups");
+  const int nth = KW > 1 ? int(blockDim.x * blockDim.y) : 0;
+  const int lim = n * LW - 1;
+  W w[KW];
+#pragma unroll
+  for (int i = 0; i < KW; ++i) {
+    const int q = tid + i * nth, wi = q < lim ? q : lim;
+    const int k = wi / LW, e = wi - k * LW;
+    w[i] = U[(size_t(nrow + k) * 4 + MU) * LW + e];
+  }
+#pragma unroll
+  for (int s = 0; s < E; ++s) r[CH + s] = pack_words<W, KW>(w, s * PER);
+}
+
+template <int NV, class S, int LW>
+__device__ __forceinline__ void lnb_commit(const RowBuf<NV, S>& r, typename S::word* lnb, int n,
+                                           int tid) {
+  using W = typename S::word;
+  constexpr int CH = RowRegs<NV, S>::CH, KW = (LW + NV - 1) / NV, PER = 16 / int(sizeof(W));
+  const int nth = KW > 1 ? int(blockDim.x * blockDim.y) : 0;
+  const int lim = n * LW - 1;
+#pragma unroll
+  for (int i = 0; i < KW; ++i) {
+    const int q = tid + i * nth;
+    lnb[q < lim ? q : lim] = unpack_word<W>(r[CH + i / PER], i % PER);
+  }
+}
+
+template <int NV, class S>
+__device__ __forceinline__ void extra_clear(RowBuf<NV, S>& r) {
+  constexpr int CH = RowRegs<NV, S>::CH, E = RowRegs<NV, S>::E;
+#pragma unroll
+  for (int s = 0; s < E; ++s) r[CH + s] = u32x4{0u, 0u, 0u, 0u};
+}
+
+// The own row's halo sites x0 - 1 (xm) and x0 + n (xp), SP pieces each: the
+// thread's group s holds piece tid + s nth of the 2 SP, clamped to the last.
+template <int NV, class S>
+__device__ __forceinline__ void halo_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm, int xp,
+                                           int tid, RowBuf<NV, S>& r) {
+  constexpr int SW = 12 * NV, CH = RowRegs<NV, S>::CH, E = RowRegs<NV, S>::E;
+  constexpr int SP = SW * int(sizeof(typename S::word)) / 16;
+  const int nth = E > 1 ? int(blockDim.x * blockDim.y) : 0;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int q = tid + s * nth, h = q < 2 * SP ? q : 2 * SP - 1;
+    const int hs = h < SP ? xm : xp;
+    r[CH + s] = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+  }
+}
+
+template <int NV, class S>
+__device__ __forceinline__ void halo_commit(const RowChunk& c, const RowBuf<NV, S>& r,
+                                            typename S::word* buf, int tid) {
+  constexpr int SW = 12 * NV, CH = RowRegs<NV, S>::CH, E = RowRegs<NV, S>::E;
+  constexpr int SP = SW * int(sizeof(typename S::word)) / 16, SSP = SiteStride<NV, S>::PIECES;
+  const int nth = E > 1 ? int(blockDim.x * blockDim.y) : 0;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int q = tid + s * nth, h = q < 2 * SP ? q : 2 * SP - 1;
+    u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
+    hdst[h < SP ? h : h - SP] = r[CH + s];
+  }
+}
 
 template <int NV, class S, int LW>
 size_t rows_lds_words(int R) {
@@ -104,7 +229,7 @@ size_t rows_lds_words(int R) {
 template <int MU, int SGN, int NV, class S, int LW = 9>
 __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                           const typename S::word* __restrict__ in, int xl, int v, int tid,
-                                          u32x4 (&r)[RowPieces<S>::CH + 1]) {
+                                          RowBuf<NV, S>& r) {
   using W = typename S::word;
   constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   const uint32_t nrow = row_base_shift(g, c, MU, SGN) + uint32_t(c.x0);
@@ -113,19 +238,17 @@ __device__ __forceinline__ void row_issue(const Geom& g, const RowChunk& c, cons
 #pragma unroll
   for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
   if (SGN < 0) {
-    const int w = tid < c.n * LW ? tid : c.n * LW - 1;
-    const int k = w / LW, e = w - k * LW;
-    r[CH] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * LW + e]);
+    lnb_issue<MU, NV, S, LW>(U, nrow, c.n, tid, r);
   } else {
     // every row writes the whole array, so that call sites merged into one
     // array store the same elements (the compiler's store sinking would
     // otherwise make the array addressable and put it in scratch memory)
-    r[CH] = u32x4{0u, 0u, 0u, 0u};
+    extra_clear<NV, S>(r);
   }
 }
 
 template <int SGN, int NV, class S, int LW = 9>
-__device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+__device__ __forceinline__ void row_commit(const RowChunk& c, const RowBuf<NV, S>& r,
                                            typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
   using W = typename S::word;
   constexpr int CH = RowPieces<S>::CH, SSP = SiteStride<NV, S>::PIECES;
@@ -133,63 +256,52 @@ __device__ __forceinline__ void row_commit(const RowChunk& c, const u32x4 (&r)[R
   u32x4* dst = reinterpret_cast<u32x4*>(row) + xc * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
-  if (SGN < 0) lnb[tid < c.n * LW ? tid : c.n * LW - 1] = piece_to_word<W>(r[CH]);
+  if (SGN < 0) lnb_commit<NV, S, LW>(r, lnb, c.n, tid);
 }
 
 // The chunk's own row in the same register shape: CH pieces of site x and,
-// in slot CH, at most one piece of the two halo sites x0 - 1, x0 + n (2 * 12 N_v
-// words, never more pieces than threads; the launcher checks this).
+// in the extra groups, the thread's pieces of the two halo sites x0 - 1, x0 + n
+// (2 * 12 N_v words; the launcher checks that the groups of the workgroup
+// hold them).
 template <int NV, class S>
 __device__ __forceinline__ void own_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm,
-                                          int xp, int xl, int v, int tid, u32x4 (&r)[RowPieces<S>::CH + 1]) {
+                                          int xp, int xl, int v, int tid, RowBuf<NV, S>& r) {
   using W = typename S::word;
-  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(W)) / 16;
+  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH;
   const int xc = xl < c.n ? xl : c.n - 1;
   const u32x4* src = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + c.x0 + xc) * SW);
 #pragma unroll
   for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
-  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
-  const int hs = h < SP ? xm : xp;
-  r[CH] = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+  halo_issue<NV, S>(c, in, xm, xp, tid, r);
 }
 
 template <int NV, class S>
-__device__ __forceinline__ void own_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+__device__ __forceinline__ void own_commit(const RowChunk& c, const RowBuf<NV, S>& r,
                                            typename S::word* buf, int xl, int v, int tid) {
-  using W = typename S::word;
-  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(W)) / 16;
-  constexpr int SSP = SiteStride<NV, S>::PIECES;
+  constexpr int CH = RowPieces<S>::CH, SSP = SiteStride<NV, S>::PIECES;
   const int xc = xl < c.n ? xl : c.n - 1;
   u32x4* dst = reinterpret_cast<u32x4*>(buf) + (xc + 1) * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
-  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
-  u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
-  hdst[h < SP ? h : h - SP] = r[CH];
+  halo_commit<NV, S>(c, r, buf, tid);
 }
 
 // Only the halo sites x0 - 1, x0 + n of the own row (its interior is already
-// in LDS), in slot CH; the other slots are cleared so that every call site
-// writes the whole register array.
+// in LDS), in the extra groups; the spinor slots are cleared so that every
+// call site writes the whole register array.
 template <int NV, class S>
 __device__ __forceinline__ void own_halo_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm,
-                                               int xp, int tid, u32x4 (&r)[RowPieces<S>::CH + 1]) {
-  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(typename S::word)) / 16;
+                                               int xp, int tid, RowBuf<NV, S>& r) {
+  constexpr int CH = RowPieces<S>::CH;
 #pragma unroll
   for (int j = 0; j < CH; ++j) r[j] = u32x4{0u, 0u, 0u, 0u};
-  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
-  const int hs = h < SP ? xm : xp;
-  r[CH] = reinterpret_cast<const u32x4*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+  halo_issue<NV, S>(c, in, xm, xp, tid, r);
 }
 
 template <int NV, class S>
-__device__ __forceinline__ void own_halo_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+__device__ __forceinline__ void own_halo_commit(const RowChunk& c, const RowBuf<NV, S>& r,
                                                 typename S::word* buf, int tid) {
-  constexpr int SW = 12 * NV, CH = RowPieces<S>::CH, SP = SW * int(sizeof(typename S::word)) / 16;
-  constexpr int SSP = SiteStride<NV, S>::PIECES;
-  const int h = tid < 2 * SP ? tid : 2 * SP - 1;
-  u32x4* hdst = reinterpret_cast<u32x4*>(buf) + (h < SP ? 0 : (c.n + 1) * SSP);
-  hdst[h < SP ? h : h - SP] = r[CH];
+  halo_commit<NV, S>(c, r, buf, tid);
 }
 
 template <int MU, int SGN, bool ADJ, int NV, class S, class T, int LW = 9>
@@ -231,7 +343,7 @@ struct HalfStride {
 template <int MU, int SGN, int NV, class S, int LW = 9>
 __device__ __forceinline__ void half_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                            const typename S::word* __restrict__ in, int xl, int v, int tid,
-                                           u32x4 (&r)[RowPieces<S>::CH + 1]) {
+                                           RowBuf<NV, S>& r) {
   static_assert(sizeof(typename S::word) == 8 && NV % 2 == 0 && RowPieces<S>::CH == 6,
                 "half-spinor rows take FP32 complex storage and an even N_v");
   constexpr int SW = 12 * NV, HP = NV / 2, P0 = HalfPartner<MU>::value;
@@ -245,17 +357,14 @@ __device__ __forceinline__ void half_issue(const Geom& g, const RowChunk& c, con
     r[cc] = src[(sa * 3 + cc) * HP + q];
     r[3 + cc] = src[(sb * 3 + cc) * HP + q];
   }
-  if (SGN < 0) {
-    const int w = tid < c.n * LW ? tid : c.n * LW - 1;
-    const int k = w / LW, e = w - k * LW;
-    r[6] = word_to_piece(U[(size_t(nrow + k) * 4 + MU) * LW + e]);
-  } else {
-    r[6] = u32x4{0u, 0u, 0u, 0u};
-  }
+  if (SGN < 0)
+    lnb_issue<MU, NV, S, LW>(U, nrow, c.n, tid, r);
+  else
+    extra_clear<NV, S>(r);
 }
 
 template <int MU, int SGN, bool ADJ, int NV, class S, int LW = 9>
-__device__ __forceinline__ void half_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+__device__ __forceinline__ void half_commit(const RowChunk& c, const RowBuf<NV, S>& r,
                                             typename S::word* hrow, typename S::word* lnb, int xl, int v, int tid) {
   using W = typename S::word;
   constexpr int HP = NV / 2, HSP = HalfStride<NV, S>::PIECES;
@@ -278,7 +387,7 @@ __device__ __forceinline__ void half_commit(const RowChunk& c, const u32x4 (&r)[
     const f32x4 h = f32x4{a.x + sg * x.x, a.y + sg * x.y, a.z + sg * x.z, a.w + sg * x.w};
     dst[cc * HP] = __builtin_bit_cast(u32x4, h);
   }
-  if (SGN < 0) lnb[tid < c.n * LW ? tid : c.n * LW - 1] = piece_to_word<W>(r[6]);
+  if (SGN < 0) lnb_commit<NV, S, LW>(r, lnb, c.n, tid);
 }
 
 template <int MU, int SGN, bool ADJ, int NV, class S, class T, int LW = 9>
@@ -309,7 +418,7 @@ __device__ __forceinline__ void half_compute(const typename S::word* hrow, const
 
 // Full or half-spinor staging of a neighbour row, by HALF.
 template <bool HALF, int MU, int SGN, bool ADJ, int NV, class S, int LW>
-__device__ __forceinline__ void o_commit(const RowChunk& c, const u32x4 (&r)[RowPieces<S>::CH + 1],
+__device__ __forceinline__ void o_commit(const RowChunk& c, const RowBuf<NV, S>& r,
                                          typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
   if constexpr (HALF)
     half_commit<MU, SGN, ADJ, NV, S, LW>(c, r, row, lnb, xl, v, tid);
@@ -357,7 +466,8 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   // then the chunk's own row with its halo sites.  Row k is requested DEPTH
   // steps before it is consumed (DEPTH = 7: all at once), each into its own
   // register array.
-  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  constexpr int RN = RowRegs<NV, S>::N;
+  u32x4 r0[RN], r1[RN], r2[RN], r3[RN], r4[RN], r5[RN], r6[RN];
 #define DSL_ISSUE(K)                                                                   \
   do {                                                                                 \
     if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, U, in, xl, v, tid, r0);        \
@@ -477,10 +587,10 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
 template <int K, int NV, class S, int LW = 9>
 __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                             const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
-                                            int tid, u32x4 (&r0)[RowPieces<S>::CH + 1],
-                                            u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
-                                            u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
-                                            u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1]) {
+                                            int tid, RowBuf<NV, S>& r0,
+                                            RowBuf<NV, S>& r1, RowBuf<NV, S>& r2,
+                                            RowBuf<NV, S>& r3, RowBuf<NV, S>& r4,
+                                            RowBuf<NV, S>& r5, RowBuf<NV, S>& r6) {
   if constexpr (K == 0) row_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);
   if constexpr (K == 1) row_issue<1, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r1);
   if constexpr (K == 2) row_issue<2, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r2);
@@ -495,10 +605,10 @@ __device__ __forceinline__ void march_issue(const Geom& g, const RowChunk& c, co
 template <bool HALF, int K, int NV, class S, int LW = 9>
 __device__ __forceinline__ void march_issue_o(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                               const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
-                                              int tid, u32x4 (&r0)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1]) {
+                                              int tid, RowBuf<NV, S>& r0,
+                                              RowBuf<NV, S>& r1, RowBuf<NV, S>& r2,
+                                              RowBuf<NV, S>& r3, RowBuf<NV, S>& r4,
+                                              RowBuf<NV, S>& r5, RowBuf<NV, S>& r6) {
   if constexpr (HALF && K == 0) half_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);
   else if constexpr (HALF && K == 1) half_issue<1, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r1);
   else if constexpr (HALF && K == 2) half_issue<2, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r2);
@@ -584,10 +694,10 @@ __device__ __forceinline__ void march_step(const Geom& g, const RowChunk& c,
                                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                                            typename S::word* buf, typename S::word* lown, typename S::word* lnb,
                                            int xm, int xp, int xl, int v, int tid, int nth, T diag,
-                                           u32x4 (&r0)[RowPieces<S>::CH + 1], u32x4 (&r1)[RowPieces<S>::CH + 1],
-                                           u32x4 (&r2)[RowPieces<S>::CH + 1], u32x4 (&r3)[RowPieces<S>::CH + 1],
-                                           u32x4 (&r4)[RowPieces<S>::CH + 1], u32x4 (&r5)[RowPieces<S>::CH + 1],
-                                           u32x4 (&r6)[RowPieces<S>::CH + 1], u32x4 (&lr)[LinkK<S, NV, LW>::value + 1],
+                                           RowBuf<NV, S>& r0, RowBuf<NV, S>& r1,
+                                           RowBuf<NV, S>& r2, RowBuf<NV, S>& r3,
+                                           RowBuf<NV, S>& r4, RowBuf<NV, S>& r5,
+                                           RowBuf<NV, S>& r6, u32x4 (&lr)[LinkK<S, NV, LW>::value + 1],
                                            cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
@@ -689,10 +799,10 @@ __device__ __forceinline__ void march_step_pp(const Geom& g, const RowChunk& c,
                                               typename S::word* __restrict__ out, typename S::word* buf0,
                                               typename S::word* buf1, typename S::word* lown, typename S::word* lnb0,
                                               typename S::word* lnb1, int xm, int xp, int xl, int v, int tid, int nth,
-                                              T diag, u32x4 (&r0)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
-                                              u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
+                                              T diag, RowBuf<NV, S>& r0,
+                                              RowBuf<NV, S>& r1, RowBuf<NV, S>& r2,
+                                              RowBuf<NV, S>& r3, RowBuf<NV, S>& r4,
+                                              RowBuf<NV, S>& r5, RowBuf<NV, S>& r6,
                                               u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeq<FIRST>;
@@ -804,10 +914,10 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
                                              typename S::word* __restrict__ out, typename S::word* bo,
                                              typename S::word* ba, typename S::word* bb, typename S::word* lown,
                                              typename S::word* lnba, typename S::word* lnbb, int xm, int xp, int xl,
-                                             int v, int tid, int nth, T diag, u32x4 (&r0)[RowPieces<S>::CH + 1],
-                                             u32x4 (&r1)[RowPieces<S>::CH + 1], u32x4 (&r2)[RowPieces<S>::CH + 1],
-                                             u32x4 (&r3)[RowPieces<S>::CH + 1], u32x4 (&r4)[RowPieces<S>::CH + 1],
-                                             u32x4 (&r5)[RowPieces<S>::CH + 1], u32x4 (&r6)[RowPieces<S>::CH + 1],
+                                             int v, int tid, int nth, T diag, RowBuf<NV, S>& r0,
+                                             RowBuf<NV, S>& r1, RowBuf<NV, S>& r2,
+                                             RowBuf<NV, S>& r3, RowBuf<NV, S>& r4,
+                                             RowBuf<NV, S>& r5, RowBuf<NV, S>& r6,
                                              u32x4 (&lr)[LinkK<S, NV, LW>::value + 1], cpx<T> (&carry)[2][3], EpiLane<S>& ep) {
   using W = typename S::word;
   using Q = MarchSeqO<FIRST>;
@@ -889,8 +999,9 @@ __device__ __forceinline__ void march_step_o(const Geom& g, const RowChunk& c, c
 #undef DSL_OCOMMIT
 #undef DSL_OISSUE
   // out = diag psi - 1/2 (hops) = -1/2 acc, through a free buffer (HALF: ba
-  // and bb together, with a site stride of 12 N_v + 4 words)
-  constexpr int OSW = HALF ? 12 * NV + 4 : SSW;
+  // and bb together, with a site stride of 12 N_v + 4 words where that fits,
+  // 12 N_v otherwise)
+  constexpr int OSW = HALF ? (12 * NV + 4 <= 2 * HalfStride<NV, S>::WORDS ? 12 * NV + 4 : 12 * NV) : SSW;
   constexpr int OSP = OSW * int(sizeof(W)) / 16;
   static_assert(!HALF || OSW <= 2 * HalfStride<NV, S>::WORDS, "the output fits ba and bb");
   {
@@ -948,7 +1059,8 @@ __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
 
-  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  constexpr int RN = RowRegs<NV, S>::N;
+  u32x4 r0[RN], r1[RN], r2[RN], r3[RN], r4[RN], r5[RN], r6[RN];
   u32x4 lr[LK + 1];
   cpx<T> carry[2][3];
   EpiLane<S> ep;
@@ -992,11 +1104,11 @@ __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
 }
 
 // The fused epilogues are built for the solver's two forms only (D with
-// EPI_NORM, D^dag with EPI_AXPY), on full links and the default prefetch depth
-// of each buffer scheme.
-template <int PP, int DEPTH, int LW>
+// EPI_NORM, D^dag with EPI_AXPY), on N_v = 12, full links and the default
+// prefetch depth of each buffer scheme.
+template <int PP, int DEPTH, int LW, int NV>
 struct MarchEpiBuilt {
-  static constexpr bool value = LW == 9 && DEPTH == (PP == 3 ? 3 : 2);
+  static constexpr bool value = NV == 12 && LW == 9 && DEPTH == (PP == 3 ? 3 : 2);
 };
 
 template <int DEPTH, int NV, class S, class T, int LW, int PP>
@@ -1009,7 +1121,7 @@ static hipError_t march_launch(bool adj, int epi, dim3 grid, dim3 block, size_t 
                      (const W*)U, (const W*)in, (W*)out, diag, ea)
   if (epi == EPI_STORE) {
     if (adj) DSL_MK(true, EPI_STORE); else DSL_MK(false, EPI_STORE);
-  } else if constexpr (MarchEpiBuilt<PP, DEPTH, LW>::value) {
+  } else if constexpr (MarchEpiBuilt<PP, DEPTH, LW, NV>::value) {
     if (epi == EPI_NORM && !adj) DSL_MK(false, EPI_NORM);
     else if (epi == EPI_AXPY && adj) DSL_MK(true, EPI_AXPY);
     else return hipErrorNotSupported;
@@ -1020,9 +1132,11 @@ static hipError_t march_launch(bool adj, int epi, dim3 grid, dim3 block, size_t 
   return hipGetLastError();
 }
 
-template <int DEPTH, int NV, class S, class T, int LW = 9>
+// ONLY_PP >= 0 builds that buffer scheme only (pp must equal it).
+template <int DEPTH, int NV, class S, class T, int LW = 9, int ONLY_PP = -1>
 static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int pp, bool xcd, const void* U,
                                  const void* in, void* out, double mass, hipStream_t st, int epi, EpiArgs& ea) {
+  if (ONLY_PP >= 0 && pp != ONLY_PP) return hipErrorInvalidValue;
   using W = typename S::word;
   const MarchTraversal m = make_march_traversal(g, uint32_t(R), uint32_t(tsteps));
   const uint32_t nseg = (uint32_t(g.n[3]) + m.T - 1) / m.T;
@@ -1035,15 +1149,20 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
   if (pp == 3) lds += (size_t(2 * R) * HalfStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
-  switch (pp) {
-    case 3:
-      if constexpr (sizeof(W) == 8 && NV % 2 == 0)
-        return march_launch<DEPTH, NV, S, T, LW, 3>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
-      else
-        return hipErrorInvalidValue;
-    case 2: return march_launch<DEPTH, NV, S, T, LW, 2>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
-    case 1: return march_launch<DEPTH, NV, S, T, LW, 1>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
-    default: return march_launch<DEPTH, NV, S, T, LW, 0>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+  if constexpr (ONLY_PP >= 0) {
+    if constexpr (ONLY_PP == 3 && !(sizeof(W) == 8 && NV % 2 == 0)) return hipErrorInvalidValue;
+    else return march_launch<DEPTH, NV, S, T, LW, ONLY_PP>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+  } else {
+    switch (pp) {
+      case 3:
+        if constexpr (sizeof(W) == 8 && NV % 2 == 0)
+          return march_launch<DEPTH, NV, S, T, LW, 3>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+        else
+          return hipErrorInvalidValue;
+      case 2: return march_launch<DEPTH, NV, S, T, LW, 2>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+      case 1: return march_launch<DEPTH, NV, S, T, LW, 1>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+      default: return march_launch<DEPTH, NV, S, T, LW, 0>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+    }
   }
 }
 
@@ -1077,7 +1196,8 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
   const int r = (p + c.y + c.z + c.t) & 1;
 
-  u32x4 r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  constexpr int RN = RowRegs<NV, S>::N;
+  u32x4 r0[RN], r1[RN], r2[RN], r3[RN], r4[RN], r5[RN], r6[RN];
 #define DSL_ISSUE(K)                                                                   \
   do {                                                                                 \
     if constexpr (K == 0) row_issue<1, +1, NV, S>(g, c, Ui, in, xl, v, tid, r0);       \
@@ -1255,9 +1375,6 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
   return hipGetLastError();
 }
 
-// Row-staged D_W for N_v = 12 with FP32 arithmetic (C64, BF16, F16 storage).
-// Returns hipErrorNotSupported when the configuration is not covered (the
-// caller then uses the direct-load kernel).  DSLASH_ROWS=0 disables it.
 // Compute units of the current device (cached per device).
 static int device_cus() {
   static int cus[64] = {0};
@@ -1271,6 +1388,29 @@ static int device_cus() {
   return cus[dev];
 }
 
+// Row-staged D_W with FP32 arithmetic (C64, BF16, F16 storage) for N_v = 4, 8,
+// 12, 16, 24.  Returns hipErrorNotSupported when the configuration is not
+// covered (the caller then uses the direct-load kernel).  DSLASH_ROWS=0
+// disables it.
+//
+// Other block sizes than 12 take the t-marching kernel in the
+// default form of each storage: FP32 with half-spinor neighbour rows, BF16
+// with the own-row buffer, FP16 with one buffer; full links, no fused epilogue.
+template <int NV>
+static hipError_t wilson_march_nv(bool adj, int dtype, const Geom& g, int R, int tsteps, bool xcd, const void* U,
+                                  const void* in, void* out, double mass, hipStream_t st) {
+  EpiArgs none;
+  switch (dtype) {
+    case DT_C64:
+      return wilson_march_t<3, NV, C64, float, 9, 3>(adj, g, R, tsteps, 3, xcd, U, in, out, mass, st, EPI_STORE, none);
+    case DT_BF16:
+      return wilson_march_t<2, NV, BF16, float, 9, 2>(adj, g, R, tsteps, 2, xcd, U, in, out, mass, st, EPI_STORE, none);
+    case DT_F16:
+      return wilson_march_t<2, NV, F16, float, 9, 0>(adj, g, R, tsteps, 0, xcd, U, in, out, mass, st, EPI_STORE, none);
+  }
+  return hipErrorNotSupported;
+}
+
 hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                               double mass, hipStream_t st, const void* clover, bool compressed, int epi,
                               EpiArgs* ea) {
@@ -1278,15 +1418,17 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   if (epi != EPI_STORE && (!ea || clover || compressed)) return hipErrorNotSupported;
   EpiArgs none;
   EpiArgs& e = ea ? *ea : none;
-  if (g.nv != 12) return hipErrorNotSupported;
-  int R = row_sites_default(g.n[0], g.nv);
+  const int nv = g.nv;
+  if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
+  if (nv != 12 && (clover || compressed || epi != EPI_STORE)) return hipErrorNotSupported;
+  int R = row_sites_default(g.n[0], nv);
   R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
-  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
-  // the own row's two halo sites (2 * 12 N_v words) must be at most one
-  // 16-byte piece per thread
+  if (R < 1 || R * nv > 256 || R * nv < 64) return hipErrorNotSupported;
+  // the own row's two halo sites (2 * 12 N_v words) must fit the extra
+  // register groups of the workgroup's R N_v threads
   const int word_bytes = int(dtype_bytes(dtype));
-  if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
+  if (R * 16 * row_extra_groups(nv, word_bytes) < 2 * 12 * word_bytes) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   bool xcd = true;
@@ -1315,6 +1457,16 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
       const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
       if (wgs <= 2u * uint32_t(device_cus())) tsteps = 16;
     }
+  }
+  if (nv != 12) {
+    if (tsteps <= 0 || clover) return hipErrorNotSupported;
+    switch (nv) {
+      case 4: return wilson_march_nv<4>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 8: return wilson_march_nv<8>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 16: return wilson_march_nv<16>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 24: return wilson_march_nv<24>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+    }
+    return hipErrorNotSupported;
   }
   pp = knobs().march_pp.get(pp);
   if (pp == 3 && dtype != DT_C64) pp = 2;

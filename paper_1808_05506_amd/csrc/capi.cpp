@@ -80,7 +80,12 @@ const char* dslash_status_string(int status) {
 
 const char* dslash_last_error(void) { return g_err; }
 
-int dslash_version(void) { return 200; }
+int dslash_version(void) { return 201; }
+
+int dslash_reload_tuning(void) {
+  dsl::knob_store() = dsl::read_knobs();
+  return DSLASH_OK;
+}
 
 static int apply_common(bool adj, int op, const void* U, const void* in, void* out, const int dims[4], int Nc,
                         int Nv, double mass, int dtype, void* stream, const void* C = nullptr,

@@ -11,8 +11,9 @@
 namespace dsl {
 
 // Tuning knobs: the environment variables DSLASH_<NAME>, read once per process
-// (at the first launch that consults them), so the kernel choice does not change
-// during a run and launches pay no lookups.  A knob that is not set leaves the
+// (at the first launch that consults them) and again only on an explicit
+// reload (dslash_reload_tuning), so the kernel choice does not change during a
+// run and launches pay no lookups.  A knob that is not set leaves the
 // launcher's default.
 struct Knob {
   bool set = false;
@@ -30,23 +31,25 @@ inline Knob read_knob(const char* name) {
   }
   return k;
 }
-inline const Knobs& knobs() {
-  static const Knobs k = [] {
-    Knobs r;
-    r.sites_per_block = read_knob("DSLASH_SITES_PER_BLOCK");
-    r.tband = read_knob("DSLASH_TBAND");
-    r.xcd = read_knob("DSLASH_XCD");
-    r.row_sites = read_knob("DSLASH_ROW_SITES");
-    r.row_depth = read_knob("DSLASH_ROW_DEPTH");
-    r.tsteps = read_knob("DSLASH_TSTEPS");
-    r.march_pp = read_knob("DSLASH_MARCH_PP");
-    r.rows = read_knob("DSLASH_ROWS");
-    r.row_lds_extra = read_knob("DSLASH_ROW_LDS_EXTRA");
-    r.cg_fuse = read_knob("DSLASH_CG_FUSE");
-    return r;
-  }();
+inline Knobs read_knobs() {
+  Knobs r;
+  r.sites_per_block = read_knob("DSLASH_SITES_PER_BLOCK");
+  r.tband = read_knob("DSLASH_TBAND");
+  r.xcd = read_knob("DSLASH_XCD");
+  r.row_sites = read_knob("DSLASH_ROW_SITES");
+  r.row_depth = read_knob("DSLASH_ROW_DEPTH");
+  r.tsteps = read_knob("DSLASH_TSTEPS");
+  r.march_pp = read_knob("DSLASH_MARCH_PP");
+  r.rows = read_knob("DSLASH_ROWS");
+  r.row_lds_extra = read_knob("DSLASH_ROW_LDS_EXTRA");
+  r.cg_fuse = read_knob("DSLASH_CG_FUSE");
+  return r;
+}
+inline Knobs& knob_store() {
+  static Knobs k = read_knobs();
   return k;
 }
+inline const Knobs& knobs() { return knob_store(); }
 
 enum Op { OP_STAGGERED = 0, OP_WILSON = 1, OP_BRILLOUIN = 2 };
 enum Dtype { DT_C64 = 0, DT_C128 = 1, DT_BF16 = 2, DT_F16 = 3 };

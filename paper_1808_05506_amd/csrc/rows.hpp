@@ -49,12 +49,15 @@ DSL_HD uint32_t row_base_shift(const Geom& g, const RowChunk& c, int mu, int sgn
 }
 
 // Default chunk length: split an x-row into the fewest chunks of at most 16
-// sites, evenly (24 -> 12 + 12 rather than 16 + 8), but keep at least 128
-// threads per workgroup.
+// sites (more where fewer than 128 threads would result) and at most 256
+// threads (R N_v), evenly (24 -> 12 + 12 rather than 16 + 8), but keep at least
+// 128 threads per workgroup where the row and the 256-thread limit allow.
 inline int row_sites_default(int nx, int nv) {
-  const int k = (nx + 15) / 16;
+  const int want = (128 + nv - 1) / nv, lim = 256 / nv;
+  const int cap = want > 16 ? (want < lim ? want : lim) : (16 < lim ? 16 : lim);
+  const int k = (nx + cap - 1) / cap;
   int r = (nx + k - 1) / k;
-  const int rmin = (128 + nv - 1) / nv;
+  const int rmin = want < cap ? want : cap;
   if (r < rmin) r = nx < rmin ? nx : rmin;
   return r;
 }

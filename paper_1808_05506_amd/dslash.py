@@ -24,7 +24,7 @@ __all__ = [
     "STAGGERED", "WILSON", "BRILLOUIN", "DslashError", "library_path", "apply", "apply_adjoint",
     "backward", "brillouin_links", "convert", "solve", "dslash", "op_code", "clover_field", "eo_pack", "eo_unpack",
     "eo_hop", "compress_links", "apply_compressed", "brillouin_links_backward", "brillouin_links_autograd",
-    "apply_brillouin_fly",
+    "apply_brillouin_fly", "reload_tuning",
 ]
 
 STAGGERED, WILSON, BRILLOUIN = 0, 1, 2
@@ -74,7 +74,8 @@ def _load():
     for name in ("dslash_apply", "dslash_apply_adjoint", "dslash_backward", "dslash_brillouin_links",
                  "dslash_convert", "dslash_solve", "dslash_solve_op", "dslash_version", "dslash_eo_pack",
                  "dslash_eo_unpack", "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
-                 "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward", "dslash_apply_brillouin_fly"):
+                 "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward", "dslash_apply_brillouin_fly",
+                 "dslash_reload_tuning"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -93,6 +94,12 @@ class DslashError(RuntimeError):
 def _check(rc: int, where: str):
     if rc != 0:
         raise DslashError(rc, where)
+
+
+def reload_tuning() -> None:
+    """Re-read the DSLASH_* tuning variables from the environment (the
+    library reads them once per process, at its first launch)."""
+    _check(_lib.dslash_reload_tuning(), "dslash_reload_tuning")
 
 
 def op_code(op) -> int:

@@ -18,6 +18,19 @@ UNIT = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
 TOL = {"c64": 1e-5, "c128": 1e-12}
 
 
+def set_knob(monkeypatch, name: str, value):
+    """Set (value None: unset) a DSLASH_* tuning variable for the rest of the
+    test and have the library read it again (it reads them once per process
+    otherwise).  monkeypatch restores the variable when the test ends, and the
+    tests' conftest has the library read it once more after that."""
+    from paper_1808_05506_amd import dslash as D
+    if value is None:
+        monkeypatch.delenv(name, raising=False)
+    else:
+        monkeypatch.setenv(name, value)
+    D.reload_tuning()
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

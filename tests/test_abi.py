@@ -55,10 +55,18 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 24
+    assert len(declared) == 25
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.dslash_version() == 200
+    assert lib.dslash_version() == 201
+
+
+def test_reload_tuning_reads_the_environment_again(lib, monkeypatch):
+    # host only: re-reading the knobs touches no device
+    monkeypatch.setenv("DSLASH_TSTEPS", "4")
+    assert lib.dslash_reload_tuning() == 0
+    monkeypatch.delenv("DSLASH_TSTEPS")
+    assert lib.dslash_reload_tuning() == 0
 
 
 def test_solve_signatures_follow_the_header():

@@ -1,0 +1,134 @@
+"""D_W at other block sizes N_v (the number of right-hand sides is the method's
+free parameter, Sec. 2): the row-staged t-marching kernel at N_v = 4, 8, 16
+and 24 against the FP64 oracle through the C ABI.
+
+Where the library's launch rule covers a shape, the test runs it with
+DSLASH_ROWS=2 (the row-staged kernel or an error), so that a fall back to the
+direct kernel cannot pass; where it does not, that setting must fail and the
+default must still give the oracle's result through the direct kernel."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import wilson
+from tests.gpu_util import compare, down, rounded, say, set_knob, up
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1808_05506_amd import dslash as D  # noqa: E402
+
+WORD_BYTES = {"c64": 8, "bf16": 4, "f16": 4}
+
+
+def _row_sites(nx, nv):
+    # the launcher's default chunk length (fewest chunks of at most 16 sites,
+    # more where fewer than 128 threads would result, at most 256 threads)
+    want, lim = -(-128 // nv), 256 // nv
+    cap = min(want, lim) if want > 16 else min(16, lim)
+    k = -(-nx // cap)
+    r = -(-nx // k)
+    rmin = min(want, cap)
+    if r < rmin:
+        r = nx if nx < rmin else rmin
+    return min(r, nx)
+
+
+def _extra_groups(nv, wb):
+    links = (-(-9 // nv) * wb + 15) // 16
+    halo = (24 * wb // 16 + 7) // 8 if nv > 16 else 1
+    return max(links, halo)
+
+
+def _rows_cover(nx, nv, dt):
+    # 64 .. 256 threads, and the own row's two halo sites in the extra
+    # register groups of the workgroup
+    r, wb = _row_sites(nx, nv), WORD_BYTES[dt]
+    return 64 <= r * nv <= 256 and r * 16 * _extra_groups(nv, wb) >= 24 * wb
+
+
+def _fields(dims, nv, dt, seed):
+    u = rounded(synthetic.gauge_links(dims, "haar", seed), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, seed + 1), dt)
+    return u, p
+
+
+# one chunk (16), chunks of 12 or 8 (24), 32 in one to four chunks, 40 with a
+# partial chunk (14 + 14 + 12 at N_v = 8 and 16), two t segments (N_t = 11 at
+# 8 steps), and 20 sites, which 8-byte storage at N_v = 8 and 16 does not cover
+SHAPES = [(16, 4, 2, 6), (24, 3, 2, 5), (32, 2, 3, 3), (40, 2, 2, 3), (16, 2, 2, 11), (20, 3, 2, 5)]
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16", "f16"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("nv", [4, 8, 16, 24])
+@pytest.mark.parametrize("dims", SHAPES)
+def test_wilson_rows_other_block_sizes(dims, nv, adj, dt, monkeypatch):
+    covered = _rows_cover(dims[0], nv, dt)
+    say(f"case wilson block size {dims} nv={nv} {dt} adj={adj} rows={covered}")
+    u, p = _fields(dims, nv, dt, 500 + nv)
+    U, P = up(u, dt), up(p, dt)
+    ref = wilson.apply(u, p, 0.1, adj)
+    if covered:
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
+        out = D.apply("wilson", U, P, 0.1, adjoint=adj)
+    else:
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
+        with pytest.raises(D.DslashError):
+            D.apply("wilson", U, P, 0.1, adjoint=adj)
+        set_knob(monkeypatch, "DSLASH_ROWS", None)
+        out = D.apply("wilson", U, P, 0.1, adjoint=adj)
+    compare(down(out), ref, dt, f"D_W nv={nv}")
+
+
+def test_the_row_rule_covers_the_benchmark_block_sizes():
+    # 16^3 x 32: every block size of the benchmark rows takes the row-staged
+    # kernel in each storage
+    for nv in (4, 8, 12, 16, 24):
+        for dt in WORD_BYTES:
+            assert _rows_cover(16, nv, dt), (nv, dt)
+
+
+@pytest.mark.parametrize("nv", [4, 24])
+def test_wilson_16cube32_other_block_sizes(nv, monkeypatch):
+    # the benchmark's D_W lattice, 16^3 x 32, m0 = 0.1, exp(0.3 i H) links
+    # (seed 1), FP32, at N_v = 4 and 24 through the row-staged kernel
+    dims, dt = (16, 16, 16, 32), "c64"
+    say(f"case wilson 16^3x32 nv={nv}")
+    u = rounded(synthetic.gauge_links(dims, "smooth", 1), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 101), dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    out = D.apply("wilson", up(u, dt), up(p, dt), 0.1)
+    compare(down(out), wilson.apply_hop(u, p, 0.1), dt, f"D_W 16^3x32 nv={nv}")
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16"])
+@pytest.mark.parametrize("adj", [False, True])
+def test_columns_do_not_depend_on_the_block_size(dt, adj, monkeypatch):
+    # every column is computed with the same arithmetic in the same order
+    # whatever the block holds, so D applied to a block of 24 columns equals,
+    # bit for bit, D applied to each of its blocks of 4, 8 and 12 columns, at
+    # a fixed t-segment length (the -t hop of a segment's first step is added
+    # in another order than the carried one) and in the buffer scheme that the
+    # other block sizes take (half-spinor rows for FP32, the own-row buffer for
+    # BF16; N_v = 12 takes it from DSLASH_MARCH_PP once DSLASH_TSTEPS is set)
+    dims = (16, 4, 4, 16)
+    say(f"case block-size invariance {dt} adj={adj}")
+    u, p = _fields(dims, 24, dt, 520)
+    U = up(u, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "8")
+    set_knob(monkeypatch, "DSLASH_MARCH_PP", "3" if dt == "c64" else "2")
+    P = up(p, dt)
+    full = D.apply("wilson", U, P, 0.1, adjoint=adj)
+    axis = -1 if dt == "c64" else -2
+    for k in (4, 8, 12):
+        for c0 in range(0, 24, k):
+            sl = [slice(None)] * full.dim()
+            sl[axis] = slice(c0, c0 + k)
+            part = D.apply("wilson", U, P[tuple(sl)].contiguous(), 0.1, adjoint=adj)
+            torch.cuda.synchronize()
+            assert torch.equal(part, full[tuple(sl)]), (k, c0)

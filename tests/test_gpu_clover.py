@@ -5,7 +5,7 @@ import pytest
 
 import synthetic
 from oracle import brillouin, clover, wilson
-from tests.gpu_util import compare, down, rounded, say, up
+from tests.gpu_util import compare, down, rounded, say, up, set_knob
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +91,7 @@ def test_row_staged_clover_equals_direct(monkeypatch):
     P = up(synthetic.wilson_spinor(dims, nv, 90), dt)
     C = D.clover_field(V, C_SW)
     rows = D.apply("wilson", V, P, 0.1, clover=C)
-    monkeypatch.setenv("DSLASH_ROWS", "0")
+    set_knob(monkeypatch, "DSLASH_ROWS", "0")
     direct = D.apply("wilson", V, P, 0.1, clover=C)
     torch.cuda.synchronize()
     compare(down(rows), down(direct), dt, "rows vs direct")

@@ -5,7 +5,7 @@ import pytest
 
 import synthetic
 from oracle import compress
-from tests.gpu_util import compare, down, rounded, say, up
+from tests.gpu_util import compare, down, rounded, say, up, set_knob
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,8 @@ def test_wilson_compressed_march_modes(pp, adj, monkeypatch):
     # FP32 D_W on compressed links through the t-marching kernel over three
     # t segments (8 + 8 + 4) with one row buffer and with half-spinor rows
     dims, nv, dt = (16, 2, 4, 20), 12, "c64"
-    monkeypatch.setenv("DSLASH_TSTEPS", "8")
-    monkeypatch.setenv("DSLASH_MARCH_PP", pp)
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "8")
+    set_knob(monkeypatch, "DSLASH_MARCH_PP", pp)
     say(f"case wilson compressed march pp={pp} adj={adj}")
     vc = rounded(compress.compress(synthetic.gauge_links(dims, "haar", 80)), dt)
     p = rounded(synthetic.wilson_spinor(dims, nv, 81), dt)

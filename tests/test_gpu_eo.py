@@ -5,7 +5,7 @@ import pytest
 
 import synthetic
 from oracle import evenodd, solver, wilson
-from tests.gpu_util import compare, down, rounded, say, up
+from tests.gpu_util import compare, down, rounded, say, up, set_knob
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def test_eo_hop_row_staged_equals_direct_kernel(monkeypatch):
     Ue, Uo = D.eo_pack(U)
     Pe, _ = D.eo_pack(P)
     rows = D.eo_hop(Ue, Uo, Pe, 1)
-    monkeypatch.setenv("DSLASH_ROWS", "0")
+    set_knob(monkeypatch, "DSLASH_ROWS", "0")
     direct = D.eo_hop(Ue, Uo, Pe, 1)
     torch.cuda.synchronize()
     compare(down(rows), down(direct).astype(np.complex128), dt, "eo hop rows vs direct")

@@ -5,7 +5,7 @@ import pytest
 
 import synthetic
 from oracle import grad, local, staggered, wilson
-from tests.gpu_util import compare, down, rounded, say, up
+from tests.gpu_util import compare, down, rounded, say, set_knob, up
 
 pytestmark = pytest.mark.gpu
 
@@ -114,24 +114,15 @@ def test_link_grad_row_staged_path(op, dt, dims):
 
 
 @pytest.mark.parametrize("op", ["wilson", "staggered"])
-def test_link_grad_rows_determinism_across_chunk_sizes(op):
-    import os
-
+def test_link_grad_rows_determinism_across_chunk_sizes(op, monkeypatch):
     dims, nv, dt = (22, 4, 2, 4), 12, "c64"
     u, chi, psi = _fields(op, dims, nv, 410, dt)
     U, C, P = up(u, dt), up(chi, dt), up(psi, dt)
     outs = []
-    old = os.environ.get("DSLASH_ROW_SITES")
-    try:
-        for r in ("12", "16", "21"):
-            os.environ["DSLASH_ROW_SITES"] = r
-            say(f"case link grad rows determinism {op} R={r}")
-            outs.append(D.backward(op, U, C, P, 0.0, need_grad_in=False)[0].cpu())
-    finally:
-        if old is None:
-            os.environ.pop("DSLASH_ROW_SITES", None)
-        else:
-            os.environ["DSLASH_ROW_SITES"] = old
+    for r in ("12", "16", "21"):
+        set_knob(monkeypatch, "DSLASH_ROW_SITES", r)
+        say(f"case link grad rows determinism {op} R={r}")
+        outs.append(D.backward(op, U, C, P, 0.0, need_grad_in=False)[0].cpu())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), grad.link_grad(op, chi, psi), dt, f"grad_U rows R sweep {op}")

@@ -1,13 +1,12 @@
 """GPU parity of D_S, D_W, D_B (and adjoints), the W construction and the
 precision conversions against the FP64 oracle, through the C ABI."""
-import os
 
 import numpy as np
 import pytest
 
 import synthetic
 from oracle import brillouin, local, staggered, wilson
-from tests.gpu_util import compare, down, rounded, say, up
+from tests.gpu_util import compare, down, rounded, say, up, set_knob
 
 pytestmark = pytest.mark.gpu
 
@@ -141,29 +140,19 @@ def test_low_precision_storage(dt, op, adj):
     compare(down(out), ref, dt, f"{op} {dt}")
 
 
-def test_bitwise_determinism_across_launch_shapes():
+def test_bitwise_determinism_across_launch_shapes(monkeypatch):
     # every output element has one writer summing in a fixed order, so the
     # result must not depend on the number of sites per workgroup
     dims, nv = (8, 6, 8, 8), 12
     u, p = _wil_fields(dims, nv, 61, 62, "c64")
     U, P = up(u, "c64"), up(p, "c64")
     outs = {}
-    old = os.environ.get("DSLASH_SITES_PER_BLOCK")
-    try:
-        for sb in (None, "1", "5", "16", "21"):
-            if sb is None:
-                os.environ.pop("DSLASH_SITES_PER_BLOCK", None)
-            else:
-                os.environ["DSLASH_SITES_PER_BLOCK"] = sb
-            say(f"case determinism sites_per_block={sb}")
-            for op, uu in (("wilson", U),):
-                outs[(op, sb, 0)] = D.apply(op, uu, P, 0.1).cpu()
-                outs[(op, sb, 1)] = D.apply(op, uu, P, 0.1).cpu()
-    finally:
-        if old is None:
-            os.environ.pop("DSLASH_SITES_PER_BLOCK", None)
-        else:
-            os.environ["DSLASH_SITES_PER_BLOCK"] = old
+    for sb in (None, "1", "5", "16", "21"):
+        set_knob(monkeypatch, "DSLASH_SITES_PER_BLOCK", sb)
+        say(f"case determinism sites_per_block={sb}")
+        for op, uu in (("wilson", U),):
+            outs[(op, sb, 0)] = D.apply(op, uu, P, 0.1).cpu()
+            outs[(op, sb, 1)] = D.apply(op, uu, P, 0.1).cpu()
     ref = outs[("wilson", None, 0)]
     for k, v in outs.items():
         assert torch.equal(v, ref), k
@@ -202,7 +191,7 @@ def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
     # one output row per workgroup), shorter rows the direct kernel; 20 and 32
     # sites split into chunks (a partial one for 20)
     nv = 12
-    monkeypatch.setenv("DSLASH_TSTEPS", "8" if kernel == "march" else "0")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "8" if kernel == "march" else "0")
     say(f"case wilson {kernel} {dims} nv={nv} {dt} adj={adj}")
     u, p = _wil_fields(dims, nv, 81, 82, dt, "haar")
     out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
@@ -219,8 +208,8 @@ def test_wilson_march_segments(dims, tsteps, adj, pp, monkeypatch):
     # with one row buffer, two used in turn, an own-row buffer plus two, and
     # the same with half-spinor neighbour rows
     nv, dt = 12, "c64"
-    monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
-    monkeypatch.setenv("DSLASH_MARCH_PP", pp)
+    set_knob(monkeypatch, "DSLASH_TSTEPS", tsteps)
+    set_knob(monkeypatch, "DSLASH_MARCH_PP", pp)
     say(f"case wilson march segments {dims} T={tsteps} pp={pp} adj={adj}")
     u, p = _wil_fields(dims, nv, 83, 84, dt, "haar")
     out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
@@ -241,10 +230,10 @@ def test_march_buffer_modes_on_the_headline_lattice(monkeypatch):
     ref = wilson.apply(u, p, 0.1)
     default = D.apply("wilson", U, P, 0.1)
     compare(down(default), ref, dt, "D_W 16^3x32 default launch")
-    monkeypatch.setenv("DSLASH_TSTEPS", "16")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "16")
     outs = {}
     for mode in ("0", "1", "2", "3"):
-        monkeypatch.setenv("DSLASH_MARCH_PP", mode)
+        set_knob(monkeypatch, "DSLASH_MARCH_PP", mode)
         outs[mode] = D.apply("wilson", U, P, 0.1)
         compare(down(outs[mode]), ref, dt, f"D_W 16^3x32 buffers mode {mode}")
     torch.cuda.synchronize()
@@ -256,12 +245,12 @@ def test_march_buffer_modes_on_the_headline_lattice(monkeypatch):
 @pytest.mark.parametrize("kernel", ["march", "rows"])
 def test_row_staged_determinism_across_chunk_sizes(kernel, monkeypatch):
     dims, nv = (22, 4, 4, 4), 12
-    monkeypatch.setenv("DSLASH_TSTEPS", "8" if kernel == "march" else "0")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "8" if kernel == "march" else "0")
     u, p = _wil_fields(dims, nv, 91, 92, "c64")
     U, P = up(u, "c64"), up(p, "c64")
     outs = []
     for r in ("12", "16", "21"):
-        monkeypatch.setenv("DSLASH_ROW_SITES", r)
+        set_knob(monkeypatch, "DSLASH_ROW_SITES", r)
         say(f"case {kernel} determinism R={r}")
         outs.append(D.apply("wilson", U, P, 0.1).cpu())
     for o in outs[1:]:
@@ -282,9 +271,9 @@ def test_staggered_row_staged_path(kernel, dt, adj, dims, monkeypatch):
     # (DSLASH_ROWS=0 forces the direct kernel); 20 sites split into 11 + 9,
     # 24 into 12 + 12, 32 into 16 + 16, 12 to 16 fill one chunk
     nv = 12
-    monkeypatch.setenv("DSLASH_ROWS", "0" if kernel == "direct" else "1")
+    set_knob(monkeypatch, "DSLASH_ROWS", "0" if kernel == "direct" else "1")
     if kernel == "rows":
-        monkeypatch.setenv("DSLASH_TSTEPS", "0")
+        set_knob(monkeypatch, "DSLASH_TSTEPS", "0")
     say(f"case staggered {kernel} {dims} nv={nv} {dt} adj={adj}")
     u, p = _stag_fields(dims, nv, 71, 72, dt)
     out = D.apply("staggered", up(u, dt), up(p, dt), 0.15, adjoint=adj)
@@ -294,13 +283,13 @@ def test_staggered_row_staged_path(kernel, dt, adj, dims, monkeypatch):
 @pytest.mark.parametrize("kernel,depth", [("rows", "3"), ("rows", "7"), ("march", "2"), ("march", "3"), ("march", "4")])
 def test_staggered_rows_determinism_across_chunk_sizes(kernel, depth, monkeypatch):
     dims, nv = (22, 4, 2, 4), 12
-    monkeypatch.setenv("DSLASH_ROW_DEPTH", depth)
-    monkeypatch.setenv("DSLASH_TSTEPS", "0" if kernel == "rows" else "3")
+    set_knob(monkeypatch, "DSLASH_ROW_DEPTH", depth)
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "0" if kernel == "rows" else "3")
     u, p = _stag_fields(dims, nv, 73, 74, "c64")
     U, P = up(u, "c64"), up(p, "c64")
     outs = []
     for r in ("12", "16", "21"):
-        monkeypatch.setenv("DSLASH_ROW_SITES", r)
+        set_knob(monkeypatch, "DSLASH_ROW_SITES", r)
         say(f"case staggered {kernel} determinism R={r} depth={depth}")
         outs.append(D.apply("staggered", U, P, 0.0).cpu())
     for o in outs[1:]:
@@ -317,7 +306,7 @@ def test_staggered_march_segments(dims, tsteps, adj, dt, monkeypatch):
     # segments, a partial last one, one step per workgroup (no carried -t hop),
     # a segment longer than N_t, and chunks of 11 + 9 sites
     nv = 12
-    monkeypatch.setenv("DSLASH_TSTEPS", tsteps)
+    set_knob(monkeypatch, "DSLASH_TSTEPS", tsteps)
     say(f"case staggered march segments {dims} T={tsteps} {dt} adj={adj}")
     u, p = _stag_fields(dims, nv, 75, 76, dt)
     out = D.apply("staggered", up(u, dt), up(p, dt), 0.1, adjoint=adj)
@@ -351,7 +340,7 @@ def test_brillouin_row_staged_path(kernel, adj, dims, monkeypatch):
     # 24 sites split into 12 + 12, 20 sites fall back to the direct kernel
     # (the even split 10 + 10 is below 12 sites); DSLASH_ROWS=0 forces the direct one
     nv, dt = 12, "c64"
-    monkeypatch.setenv("DSLASH_ROWS", "1" if kernel == "rows" else "0")
+    set_knob(monkeypatch, "DSLASH_ROWS", "1" if kernel == "rows" else "0")
     say(f"case brillouin {kernel} {dims} nv={nv} {dt} adj={adj}")
     v = synthetic.gauge_links(dims, "haar", 33)
     w = rounded(brillouin.build(v), dt)
