@@ -2,8 +2,10 @@
 
 Every source under ``csrc/`` is compiled with hipcc (HIP mode, -O3, packed
 FP32 instructions disabled) into an object file under ``_build/``, and the
-objects are linked into ``paper_1808_05506_amd/libdslash.so``.  Always
-rebuilds everything; sources are compiled in parallel.
+objects are linked into ``paper_1808_05506_amd/libdslash.so``.  The
+microbenchmarks under ``microbench/`` (stand-alone programs, not part of the
+library) are built beside their sources.  Always rebuilds everything; sources
+are compiled in parallel.
 """
 from __future__ import annotations
 
@@ -45,12 +47,26 @@ def _compile(hipcc: str, src: str, extra) -> str:
     return obj
 
 
+MICROBENCH = os.path.join(HERE, "microbench")
+MICROBENCH_SOURCES = ["fp32_contraction.hip"]
+
+
+def _microbench(hipcc: str, src: str) -> str:
+    exe = os.path.join(MICROBENCH, os.path.splitext(src)[0])
+    cmd = [hipcc, *FLAGS, os.path.join(MICROBENCH, src), "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return exe
+
+
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(hipcc, s, list(extra)), SOURCES))
+        exes = list(ex.map(lambda s: _microbench(hipcc, s), MICROBENCH_SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,6 +75,8 @@ def build(verbose: bool = False, extra=()) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+        for exe in exes:
+            print(f"built {exe}")
     return LIB
 
 
