@@ -309,7 +309,8 @@ def staggered_rows_bench(torch, D, np, synthetic, steps, warmup):
 def block_size_rows_bench(torch, D, np, synthetic, steps, warmup):
     """D_W on the headline lattice (16^3 x 32, FP32, smooth links seed 1, rhs
     seed 101) at other block sizes N_v: 4, 8, 16 and 24 take the row-staged
-    t-marching kernel, N_v = 1 the direct one."""
+    t-marching kernel, N_v = 1 the direct one; D_S on 32^4 (FP32, Haar links
+    seed 0, rhs seed 100) at N_v = 4 and 24."""
     rows = {}
     dev = torch.device("cuda:0")
     dims = (16, 16, 16, 32)
@@ -318,6 +319,14 @@ def block_size_rows_bench(torch, D, np, synthetic, steps, warmup):
         P = torch.from_numpy(synthetic.wilson_spinor(dims, nv, 101).astype(np.complex64)).to(dev)
         rows[f"wilson_16^3x32_nv{nv}_fp32"], _ = bench_apply(torch, D, "wilson", U, P, 0.1, steps, warmup, 4, 8,
                                                              f"D_W 16^3x32 nv{nv} fp32")
+        del P
+    del U
+    dims = (32, 32, 32, 32)
+    U = torch.from_numpy(synthetic.gauge_links(dims, "haar", 0).astype(np.complex64)).to(dev)
+    for nv in (4, 24):
+        P = torch.from_numpy(synthetic.staggered_spinor(dims, nv, 100).astype(np.complex64)).to(dev)
+        rows[f"staggered_32^4_nv{nv}_fp32"], _ = bench_apply(torch, D, "staggered", U, P, 0.0, steps, warmup, 1, 8,
+                                                             f"D_S 32^4 nv{nv} fp32")
         del P
     del U
     torch.cuda.empty_cache()

@@ -34,13 +34,21 @@ template <int NV, class S>
 using SPiece = typename Stage<3, NV, S>::P;
 template <int NV, class S>
 constexpr int kSCH = Stage<3, NV, S>::CH;
+// Slots after the CH spinor pieces of a staged row: the ceil(9 / N_v) words of
+// the backward links a thread moves (one word per slot), or, on the own row,
+// one piece of the halo sites.
+template <int NV>
+constexpr int kSE = (9 + NV - 1) / NV;
+template <int NV, class S>
+using SRowBuf = SPiece<NV, S>[kSCH<NV, S> + kSE<NV>];
 
 // Neighbour row (MU, SGN): lane (x, v) takes pieces j N_v + v of its site;
-// slot CH carries one word of V_mu(x - mu) for a backward row.
+// for a backward row, slots CH .. carry the thread's words tid + i nth of the
+// row's V_mu(x - mu) (clamped to the last).
 template <int MU, int SGN, int NV, class S, int LW>
 __device__ __forceinline__ void srow_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                            const typename S::word* __restrict__ in, int xl, int v, int tid,
-                                           SPiece<NV, S> (&r)[kSCH<NV, S> + 1]) {
+                                           SRowBuf<NV, S>& r) {
   using W = typename S::word;
   using P = SPiece<NV, S>;
   static_assert(sizeof(P) == sizeof(W), "one link word per piece slot");
@@ -51,14 +59,20 @@ __device__ __forceinline__ void srow_issue(const Geom& g, const RowChunk& c, con
 #pragma unroll
   for (int j = 0; j < CH; ++j) r[j] = src[j * NV + v];
   if (SGN < 0) {
-    const int w = tid < c.n * LW ? tid : c.n * LW - 1;
-    const int k = w / LW, e = w - k * LW;
-    r[CH] = reinterpret_cast<const P*>(U)[(size_t(nrow + k) * 4 + MU) * LW + e];
+    constexpr int KW = (LW + NV - 1) / NV;
+    const int nth = KW > 1 ? int(blockDim.x * blockDim.y) : 0;
+    const int lim = c.n * LW - 1;
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      const int q = tid + i * nth, w = q < lim ? q : lim;
+      const int k = w / LW, e = w - k * LW;
+      r[CH + i] = reinterpret_cast<const P*>(U)[(size_t(nrow + k) * 4 + MU) * LW + e];
+    }
   }
 }
 
 template <int SGN, int NV, class S, int LW>
-__device__ __forceinline__ void srow_commit(const RowChunk& c, const SPiece<NV, S> (&r)[kSCH<NV, S> + 1],
+__device__ __forceinline__ void srow_commit(const RowChunk& c, const SRowBuf<NV, S>& r,
                                             typename S::word* row, typename S::word* lnb, int xl, int v, int tid) {
   using P = SPiece<NV, S>;
   constexpr int CH = kSCH<NV, S>, SSP = Stage<3, NV, S>::SSP;
@@ -66,14 +80,23 @@ __device__ __forceinline__ void srow_commit(const RowChunk& c, const SPiece<NV, 
   P* dst = reinterpret_cast<P*>(row) + xc * SSP;
 #pragma unroll
   for (int j = 0; j < CH; ++j) dst[j * NV + v] = r[j];
-  if (SGN < 0) reinterpret_cast<P*>(lnb)[tid < c.n * LW ? tid : c.n * LW - 1] = r[CH];
+  if (SGN < 0) {
+    constexpr int KW = (LW + NV - 1) / NV;
+    const int nth = KW > 1 ? int(blockDim.x * blockDim.y) : 0;
+    const int lim = c.n * LW - 1;
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      const int q = tid + i * nth;
+      reinterpret_cast<P*>(lnb)[q < lim ? q : lim] = r[CH + i];
+    }
+  }
 }
 
 // Own row: CH pieces of site x and, in slot CH, one piece of the halo sites
 // x0 - 1, x0 + n (2 * 3 N_v words; the launcher checks there are enough threads).
 template <int NV, class S>
 __device__ __forceinline__ void sown_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm, int xp,
-                                           int xl, int v, int tid, SPiece<NV, S> (&r)[kSCH<NV, S> + 1]) {
+                                           int xl, int v, int tid, SRowBuf<NV, S>& r) {
   using P = SPiece<NV, S>;
   constexpr int SW = 3 * NV, CH = kSCH<NV, S>, SP = CH * NV;
   const int xc = xl < c.n ? xl : c.n - 1;
@@ -83,10 +106,12 @@ __device__ __forceinline__ void sown_issue(const RowChunk& c, const typename S::
   const int h = tid < 2 * SP ? tid : 2 * SP - 1;
   const int hs = h < SP ? xm : xp;
   r[CH] = reinterpret_cast<const P*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+#pragma unroll
+  for (int i = 1; i < kSE<NV>; ++i) r[CH + i] = P{};
 }
 
 template <int NV, class S>
-__device__ __forceinline__ void sown_commit(const RowChunk& c, const SPiece<NV, S> (&r)[kSCH<NV, S> + 1],
+__device__ __forceinline__ void sown_commit(const RowChunk& c, const SRowBuf<NV, S>& r,
                                             typename S::word* buf, int xl, int v, int tid) {
   using P = SPiece<NV, S>;
   constexpr int CH = kSCH<NV, S>, SP = CH * NV, SSP = Stage<3, NV, S>::SSP;
@@ -103,7 +128,7 @@ __device__ __forceinline__ void sown_commit(const RowChunk& c, const SPiece<NV, 
 // CH; the other slots are cleared so every call site writes the whole array.
 template <int NV, class S>
 __device__ __forceinline__ void sown_halo_issue(const RowChunk& c, const typename S::word* __restrict__ in, int xm,
-                                                int xp, int tid, SPiece<NV, S> (&r)[kSCH<NV, S> + 1]) {
+                                                int xp, int tid, SRowBuf<NV, S>& r) {
   using P = SPiece<NV, S>;
   constexpr int SW = 3 * NV, CH = kSCH<NV, S>, SP = CH * NV;
 #pragma unroll
@@ -111,10 +136,12 @@ __device__ __forceinline__ void sown_halo_issue(const RowChunk& c, const typenam
   const int h = tid < 2 * SP ? tid : 2 * SP - 1;
   const int hs = h < SP ? xm : xp;
   r[CH] = reinterpret_cast<const P*>(in + size_t(c.row_base + hs) * SW)[h < SP ? h : h - SP];
+#pragma unroll
+  for (int i = 1; i < kSE<NV>; ++i) r[CH + i] = P{};
 }
 
 template <int NV, class S>
-__device__ __forceinline__ void sown_halo_commit(const RowChunk& c, const SPiece<NV, S> (&r)[kSCH<NV, S> + 1],
+__device__ __forceinline__ void sown_halo_commit(const RowChunk& c, const SRowBuf<NV, S>& r,
                                                  typename S::word* buf, int tid) {
   using P = SPiece<NV, S>;
   constexpr int CH = kSCH<NV, S>, SP = CH * NV, SSP = Stage<3, NV, S>::SSP;
@@ -182,7 +209,7 @@ __global__ void __launch_bounds__(256, SRowsWaves<DEPTH>::value)
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
 
-  P r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  SRowBuf<NV, S> r0, r1, r2, r3, r4, r5, r6;
 #define DSL_SISSUE(K)                                                                   \
   do {                                                                                  \
     if constexpr (K == 0) srow_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);        \
@@ -293,10 +320,10 @@ template <bool FIRST> struct SMarchSeq {
 template <int K, int NV, class S, int LW>
 __device__ __forceinline__ void smarch_issue(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ U,
                                              const typename S::word* __restrict__ in, int xm, int xp, int xl, int v,
-                                             int tid, SPiece<NV, S> (&r0)[kSCH<NV, S> + 1],
-                                             SPiece<NV, S> (&r1)[kSCH<NV, S> + 1], SPiece<NV, S> (&r2)[kSCH<NV, S> + 1],
-                                             SPiece<NV, S> (&r3)[kSCH<NV, S> + 1], SPiece<NV, S> (&r4)[kSCH<NV, S> + 1],
-                                             SPiece<NV, S> (&r5)[kSCH<NV, S> + 1], SPiece<NV, S> (&r6)[kSCH<NV, S> + 1]) {
+                                             int tid, SRowBuf<NV, S>& r0,
+                                             SRowBuf<NV, S>& r1, SRowBuf<NV, S>& r2,
+                                             SRowBuf<NV, S>& r3, SRowBuf<NV, S>& r4,
+                                             SRowBuf<NV, S>& r5, SRowBuf<NV, S>& r6) {
   if constexpr (K == 0) srow_issue<1, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r0);
   if constexpr (K == 1) srow_issue<1, -1, NV, S, LW>(g, c, U, in, xl, v, tid, r1);
   if constexpr (K == 2) srow_issue<2, +1, NV, S, LW>(g, c, U, in, xl, v, tid, r2);
@@ -364,10 +391,10 @@ __device__ __forceinline__ void smarch_step(const Geom& g, const RowChunk& c, co
                                             typename S::word* bo, typename S::word* ba, typename S::word* bb,
                                             typename S::word* lown, typename S::word* lnba, typename S::word* lnbb,
                                             int xm, int xp, int xl, int v, int tid, int nth, T mass, T ey, T ez, T et,
-                                            SPiece<NV, S> (&r0)[kSCH<NV, S> + 1], SPiece<NV, S> (&r1)[kSCH<NV, S> + 1],
-                                            SPiece<NV, S> (&r2)[kSCH<NV, S> + 1], SPiece<NV, S> (&r3)[kSCH<NV, S> + 1],
-                                            SPiece<NV, S> (&r4)[kSCH<NV, S> + 1], SPiece<NV, S> (&r5)[kSCH<NV, S> + 1],
-                                            SPiece<NV, S> (&r6)[kSCH<NV, S> + 1],
+                                            SRowBuf<NV, S>& r0, SRowBuf<NV, S>& r1,
+                                            SRowBuf<NV, S>& r2, SRowBuf<NV, S>& r3,
+                                            SRowBuf<NV, S>& r4, SRowBuf<NV, S>& r5,
+                                            SRowBuf<NV, S>& r6,
                                             u32x4 (&lr)[SLinks<S, NV, LW>::K + 1], cpx<T> (&carry)[3]) {
   using W = typename S::word;
   using Q = SMarchSeq<FIRST>;
@@ -484,7 +511,7 @@ __global__ void __launch_bounds__(256, SMarchWaves<S>::value)
   const T ez = ((x + c.y) & 1) ? T(-1) : T(1);
   const T et = ((x + c.y + c.z) & 1) ? T(-1) : T(1);
 
-  P r0[CH + 1], r1[CH + 1], r2[CH + 1], r3[CH + 1], r4[CH + 1], r5[CH + 1], r6[CH + 1];
+  SRowBuf<NV, S> r0, r1, r2, r3, r4, r5, r6;
   u32x4 lr[SLinks<S, NV, LW>::K + 1];
   cpx<T> carry[3];
   using Q0 = SMarchSeq<true>;
@@ -540,19 +567,32 @@ static hipError_t staggered_rows_t(bool adj, const Geom& g, int R, int bt, bool 
   return hipGetLastError();
 }
 
-// Row-staged D_S for N_v = 12 in C64 and C128.  Returns hipErrorNotSupported
-// when the configuration is not covered (the caller then uses the direct
-// kernel).  DSLASH_ROWS=0 disables it.
+// Other block sizes than N_v = 12 take the t-marching kernel with three rows
+// in flight and full links.
+template <int NV>
+static hipError_t staggered_march_nv(bool adj, int dtype, const Geom& g, int R, int tsteps, bool xcd, const void* U,
+                                     const void* in, void* out, double mass, hipStream_t st) {
+  if (dtype == DT_C64) return staggered_march_t<3, NV, C64, float, 9>(adj, g, R, tsteps, xcd, U, in, out, mass, st);
+  return staggered_march_t<3, NV, C128, double, 9>(adj, g, R, tsteps, xcd, U, in, out, mass, st);
+}
+
+// Row-staged D_S in C64 and C128 for N_v = 4, 8, 12, 16, 24.  Returns
+// hipErrorNotSupported when the configuration is not covered (the caller then
+// uses the direct kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_staggered_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st, bool compressed) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
-  if (g.nv != 12 || (dtype != DT_C64 && dtype != DT_C128)) return hipErrorNotSupported;
-  int R = row_sites_default(g.n[0], g.nv);
+  const int nv = g.nv;
+  if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
+  if (dtype != DT_C64 && dtype != DT_C128) return hipErrorNotSupported;
+  if (nv != 12 && compressed) return hipErrorNotSupported;
+  int R = row_sites_default(g.n[0], nv);
   R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
-  // R >= 11 also gives every thread at most one piece of the own row's halo
-  // (2 sites of 3 N_v words) and one word of a row's backward links (9 n words)
-  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  // 64 .. 256 threads; R >= 6 gives every thread at most one piece of the own
+  // row's halo (2 sites of 3 N_v words); a row's backward links (9 n words)
+  // take ceil(9 / N_v) words a thread
+  if (R < 6 || R * nv > 256 || R * nv < 64) return hipErrorNotSupported;
   int bt = 4;
   bt = knobs().tband.get(bt);
   bool xcd = true;
@@ -563,6 +603,16 @@ hipError_t launch_staggered_rows(bool adj, int dtype, const Geom& g, const void*
   // 0 selects the kernel with one output row per workgroup)
   int tsteps = 8;
   tsteps = knobs().tsteps.get(tsteps);
+  if (nv != 12) {
+    if (tsteps <= 0) return hipErrorNotSupported;
+    switch (nv) {
+      case 4: return staggered_march_nv<4>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 8: return staggered_march_nv<8>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 16: return staggered_march_nv<16>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+      case 24: return staggered_march_nv<24>(adj, dtype, g, R, tsteps, xcd, U, in, out, mass, st);
+    }
+    return hipErrorNotSupported;
+  }
   if (tsteps > 0) {
 #define DSL_SMT(D, LW)                                                                                          \
   return dtype == DT_C64 ? staggered_march_t<D, 12, C64, float, LW>(adj, g, R, tsteps, xcd, U, in, out, mass, st) \

@@ -62,3 +62,43 @@ def f16_pairs(a):
 def from_f16_pairs(h):
     h = h.astype(np.float64)
     return h[..., 0] + 1j * h[..., 1]
+
+
+# The library's launch rule for its row-staged kernels, restated so that a test
+# can require them (DSLASH_ROWS=2) exactly where they apply.
+WORD_BYTES = {"c64": 8, "c128": 16, "bf16": 4, "f16": 4}
+
+
+def row_sites(nx, nv):
+    """Default chunk length: fewest chunks of at most 16 sites (more where
+    fewer than 128 threads would result), at most 256 threads, split evenly."""
+    want, lim = -(-128 // nv), 256 // nv
+    cap = min(want, lim) if want > 16 else min(16, lim)
+    k = -(-nx // cap)
+    r = -(-nx // k)
+    rmin = min(want, cap)
+    if r < rmin:
+        r = nx if nx < rmin else rmin
+    return min(r, nx)
+
+
+def wilson_rows_cover(nx, nv, dt):
+    """D_W t-marching kernel (FP32 arithmetic storages): N_v in 4, 8, 12, 16,
+    24, 64 .. 256 threads, and the own row's two halo sites in the extra
+    register groups (one, or two at N_v > 16 with 8-byte words or where the
+    link words need them)."""
+    if dt not in ("c64", "bf16", "f16") or nv not in (4, 8, 12, 16, 24):
+        return False
+    r, wb = row_sites(nx, nv), WORD_BYTES[dt]
+    links = (-(-9 // nv) * wb + 15) // 16
+    halo = (24 * wb // 16 + 7) // 8 if nv > 16 else 1
+    return 64 <= r * nv <= 256 and r * 16 * max(links, halo) >= 24 * wb
+
+
+def staggered_rows_cover(nx, nv, dt):
+    """D_S t-marching kernel (C64, C128): N_v in 4, 8, 12, 16, 24, 64 .. 256
+    threads and at least 6 sites per chunk."""
+    if dt not in ("c64", "c128") or nv not in (4, 8, 12, 16, 24):
+        return False
+    r = row_sites(nx, nv)
+    return r >= 6 and 64 <= r * nv <= 256

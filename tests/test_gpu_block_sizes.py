@@ -1,16 +1,15 @@
-"""D_W at other block sizes N_v (the number of right-hand sides is the method's
-free parameter, Sec. 2): the row-staged t-marching kernel at N_v = 4, 8, 16
-and 24 against the FP64 oracle through the C ABI.
+"""D_W and D_S at other block sizes N_v (the number of right-hand sides is the
+method's free parameter, Sec. 2): the row-staged t-marching kernels at N_v = 4,
+8, 16 and 24 against the FP64 oracle through the C ABI.
 
 Where the library's launch rule covers a shape, the test runs it with
 DSLASH_ROWS=2 (the row-staged kernel or an error), so that a fall back to the
 direct kernel cannot pass; where it does not, that setting must fail and the
 default must still give the oracle's result through the direct kernel."""
-import numpy as np
 import pytest
 
 import synthetic
-from oracle import wilson
+from oracle import staggered, wilson
 from tests.gpu_util import compare, down, rounded, say, set_knob, up
 
 pytestmark = pytest.mark.gpu
@@ -21,33 +20,7 @@ if not torch.cuda.is_available():
 
 from paper_1808_05506_amd import dslash as D  # noqa: E402
 
-WORD_BYTES = {"c64": 8, "bf16": 4, "f16": 4}
-
-
-def _row_sites(nx, nv):
-    # the launcher's default chunk length (fewest chunks of at most 16 sites,
-    # more where fewer than 128 threads would result, at most 256 threads)
-    want, lim = -(-128 // nv), 256 // nv
-    cap = min(want, lim) if want > 16 else min(16, lim)
-    k = -(-nx // cap)
-    r = -(-nx // k)
-    rmin = min(want, cap)
-    if r < rmin:
-        r = nx if nx < rmin else rmin
-    return min(r, nx)
-
-
-def _extra_groups(nv, wb):
-    links = (-(-9 // nv) * wb + 15) // 16
-    halo = (24 * wb // 16 + 7) // 8 if nv > 16 else 1
-    return max(links, halo)
-
-
-def _rows_cover(nx, nv, dt):
-    # 64 .. 256 threads, and the own row's two halo sites in the extra
-    # register groups of the workgroup
-    r, wb = _row_sites(nx, nv), WORD_BYTES[dt]
-    return 64 <= r * nv <= 256 and r * 16 * _extra_groups(nv, wb) >= 24 * wb
+from tests.helpers import staggered_rows_cover, wilson_rows_cover  # noqa: E402
 
 
 def _fields(dims, nv, dt, seed):
@@ -67,7 +40,7 @@ SHAPES = [(16, 4, 2, 6), (24, 3, 2, 5), (32, 2, 3, 3), (40, 2, 2, 3), (16, 2, 2,
 @pytest.mark.parametrize("nv", [4, 8, 16, 24])
 @pytest.mark.parametrize("dims", SHAPES)
 def test_wilson_rows_other_block_sizes(dims, nv, adj, dt, monkeypatch):
-    covered = _rows_cover(dims[0], nv, dt)
+    covered = wilson_rows_cover(dims[0], nv, dt)
     say(f"case wilson block size {dims} nv={nv} {dt} adj={adj} rows={covered}")
     u, p = _fields(dims, nv, dt, 500 + nv)
     U, P = up(u, dt), up(p, dt)
@@ -85,11 +58,12 @@ def test_wilson_rows_other_block_sizes(dims, nv, adj, dt, monkeypatch):
 
 
 def test_the_row_rule_covers_the_benchmark_block_sizes():
-    # 16^3 x 32: every block size of the benchmark rows takes the row-staged
-    # kernel in each storage
+    # 16^3 x 32 (D_W) and 32^4 (D_S): every block size of the benchmark rows
+    # takes the row-staged kernel in each storage
     for nv in (4, 8, 12, 16, 24):
-        for dt in WORD_BYTES:
-            assert _rows_cover(16, nv, dt), (nv, dt)
+        for dt in ("c64", "bf16", "f16"):
+            assert wilson_rows_cover(16, nv, dt), (nv, dt)
+        assert staggered_rows_cover(32, nv, "c64"), nv
 
 
 @pytest.mark.parametrize("nv", [4, 24])
@@ -132,3 +106,51 @@ def test_columns_do_not_depend_on_the_block_size(dt, adj, monkeypatch):
             part = D.apply("wilson", U, P[tuple(sl)].contiguous(), 0.1, adjoint=adj)
             torch.cuda.synchronize()
             assert torch.equal(part, full[tuple(sl)]), (k, c0)
+
+
+# (D_S takes even extents) one chunk (16), 8 sites (a single chunk at
+# N_v >= 8 only), chunks of 12 or 8 (24), 40 with a partial chunk, two t
+# segments (N_t = 12 at 8 steps)
+STAG_SHAPES = [(16, 4, 2, 6), (8, 4, 2, 4), (24, 4, 2, 6), (40, 2, 2, 4), (16, 2, 2, 12)]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("nv", [4, 8, 16, 24])
+@pytest.mark.parametrize("dims", STAG_SHAPES)
+def test_staggered_rows_other_block_sizes(dims, nv, adj, dt, monkeypatch):
+    covered = staggered_rows_cover(dims[0], nv, dt)
+    say(f"case staggered block size {dims} nv={nv} {dt} adj={adj} rows={covered}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 600 + nv), dt)
+    p = rounded(synthetic.staggered_spinor(dims, nv, 601 + nv), dt)
+    U, P = up(u, dt), up(p, dt)
+    ref = staggered.apply(u, p, 0.15, adj)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    if covered:
+        out = D.apply("staggered", U, P, 0.15, adjoint=adj)
+    else:
+        with pytest.raises(D.DslashError):
+            D.apply("staggered", U, P, 0.15, adjoint=adj)
+        set_knob(monkeypatch, "DSLASH_ROWS", None)
+        out = D.apply("staggered", U, P, 0.15, adjoint=adj)
+    compare(down(out), ref, dt, f"D_S nv={nv}")
+
+
+@pytest.mark.parametrize("adj", [False, True])
+def test_staggered_columns_do_not_depend_on_the_block_size(adj, monkeypatch):
+    # as for D_W: a block of 24 columns equals its blocks of 4, 8 and 12
+    # columns bit for bit at a fixed t-segment length and prefetch depth
+    dims, dt = (16, 4, 4, 16), "c64"
+    say(f"case D_S block-size invariance adj={adj}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 620), dt)
+    p = rounded(synthetic.staggered_spinor(dims, 24, 621), dt)
+    U, P = up(u, dt), up(p, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "8")
+    set_knob(monkeypatch, "DSLASH_ROW_DEPTH", "3")
+    full = D.apply("staggered", U, P, 0.15, adjoint=adj)
+    for k in (4, 8, 12):
+        for c0 in range(0, 24, k):
+            part = D.apply("staggered", U, P[..., c0:c0 + k].contiguous(), 0.15, adjoint=adj)
+            torch.cuda.synchronize()
+            assert torch.equal(part, full[..., c0:c0 + k]), (k, c0)

@@ -7,6 +7,7 @@ import pytest
 import synthetic
 from oracle import brillouin, local, staggered, wilson
 from tests.gpu_util import compare, down, rounded, say, up, set_knob
+from tests.helpers import wilson_rows_cover
 
 pytestmark = pytest.mark.gpu
 
@@ -186,12 +187,15 @@ def test_errors_raise():
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("dims", [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (12, 2, 2, 3), (32, 2, 3, 2)])
 def test_wilson_row_staged_path(kernel, dt, adj, dims, monkeypatch):
-    # N_v = 12 with rows of >= 12 sites (>= 11 in 16-bit storage) runs an LDS
-    # row-staged kernel (by default the t-marching one; DSLASH_TSTEPS=0 selects
-    # one output row per workgroup), shorter rows the direct kernel; 20 and 32
-    # sites split into chunks (a partial one for 20)
+    # N_v = 12 runs an LDS row-staged kernel where the launch rule covers the
+    # row (by default the t-marching one; DSLASH_TSTEPS=0 selects one output
+    # row per workgroup; DSLASH_ROWS=2 then requires it), the direct kernel
+    # elsewhere (11 and 20 sites in FP32 storage); 20 and 32 sites split into
+    # chunks (a partial one for 20)
     nv = 12
     set_knob(monkeypatch, "DSLASH_TSTEPS", "8" if kernel == "march" else "0")
+    if wilson_rows_cover(dims[0], nv, dt):
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
     say(f"case wilson {kernel} {dims} nv={nv} {dt} adj={adj}")
     u, p = _wil_fields(dims, nv, 81, 82, dt, "haar")
     out = D.apply("wilson", up(u, dt), up(p, dt), 0.1, adjoint=adj)
@@ -266,12 +270,13 @@ _SROW_DIMS = [(16, 4, 2, 6), (20, 2, 4, 6), (12, 2, 2, 4), (14, 2, 2, 2), (32, 2
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("dims", _SROW_DIMS)
 def test_staggered_row_staged_path(kernel, dt, adj, dims, monkeypatch):
-    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged D_S kernels:
+    # N_v = 12 with rows of >= 6 sites runs the LDS row-staged D_S kernels:
     # t-marching by default, one output row per workgroup with DSLASH_TSTEPS=0
-    # (DSLASH_ROWS=0 forces the direct kernel); 20 sites split into 11 + 9,
-    # 24 into 12 + 12, 32 into 16 + 16, 12 to 16 fill one chunk
+    # (DSLASH_ROWS=0 forces the direct kernel, 2 the row-staged one or an
+    # error); 20 sites split into 11 + 9, 24 into 12 + 12, 32 into 16 + 16, 12
+    # to 16 fill one chunk
     nv = 12
-    set_knob(monkeypatch, "DSLASH_ROWS", "0" if kernel == "direct" else "1")
+    set_knob(monkeypatch, "DSLASH_ROWS", "0" if kernel == "direct" else "2")
     if kernel == "rows":
         set_knob(monkeypatch, "DSLASH_TSTEPS", "0")
     say(f"case staggered {kernel} {dims} nv={nv} {dt} adj={adj}")
