@@ -45,8 +45,10 @@ struct BriStage {
   static constexpr int SP = SW * int(sizeof(W)) / 16; // 16-byte pieces per site
   static constexpr int CH = SP / NV;                  // pieces per lane
   static constexpr int KW = (27 + NV - 1) / NV;       // link words per thread (27 n words per row)
-  // halo pieces per thread for a chunk of at least 12 sites (the launcher checks)
-  static constexpr int HK = (2 * SP + 12 * NV - 1) / (12 * NV);
+  // halo pieces per thread (2 SP = 12 N_v of them over R N_v threads): one
+  // for chunks of at least 12 sites, two for the chunks of 6 .. 11 sites
+  // taken at N_v > 16 (the launcher checks R HK >= 12)
+  static constexpr int HK = NV > 16 ? 2 : 1;
 };
 
 // A staged row in flight: the lane's pieces of its site, one piece of the halo
@@ -261,11 +263,15 @@ __device__ __forceinline__ void bri_row_compute(int r, const typename S::word* b
 
 }  // namespace
 
+// Waves per SIMD: three (168 VGPRs); two below N_v = 8, where a thread moves
+// ceil(27 / N_v) link words of every staged row.
+template <int NV> struct BriWaves { static constexpr int value = NV < 8 ? 2 : 3; };
+
 // CLOV: adds the site-local clover term (packed, 36 words per site, staged
 // in LDS after the link columns).  FLY: Wl holds the one-hop links V and the
 // off-axis links are built on the fly for every row.
 template <bool ADJ, bool CLOV, bool FLY, int NV, class S, class T>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, BriWaves<NV>::value)
     brillouin_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ Wl,
                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                           const typename S::word* __restrict__ C, T diag) {
@@ -328,7 +334,8 @@ __global__ void __launch_bounds__(256, 3)
   }
 }
 
-template <int NV, class S, class T, bool FLY>
+// CLOVER_OK = false builds the form without the clover term only (C must be null).
+template <int NV, class S, class T, bool FLY, bool CLOVER_OK = true>
 static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* Wl, const void* in,
                                    void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
@@ -340,9 +347,14 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 #define DSL_BK(A, CL)                                                                                        \
   hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, FLY, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl, \
                      (const W*)in, (W*)out, (const W*)C, diag)
-  if (C) {
-    if (adj) DSL_BK(true, true); else DSL_BK(false, true);
+  if constexpr (CLOVER_OK) {
+    if (C) {
+      if (adj) DSL_BK(true, true); else DSL_BK(false, true);
+    } else {
+      if (adj) DSL_BK(true, false); else DSL_BK(false, false);
+    }
   } else {
+    if (C) return hipErrorInvalidValue;
     if (adj) DSL_BK(true, false); else DSL_BK(false, false);
   }
 #undef DSL_BK
@@ -541,21 +553,24 @@ __global__ void __launch_bounds__(kDmaSites * NV, 3)
   }
 }
 
-// Chunk length of the row-staged D_B for N_v = 12 in C64, or 0 when the
-// configuration is not covered.
+// Chunk length of the register-staged D_B (C64; N_v = 4, 8, 12, 16, 24), or 0
+// when the configuration is not covered.
 static int brillouin_rows_sites(int dtype, const Geom& g) {
   // FP32 only: the FP64 variant would not fit in registers
-  if (g.nv != 12 || dtype != DT_C64) return 0;
-  int R = row_sites_default(g.n[0], g.nv);
+  const int nv = g.nv;
+  if (dtype != DT_C64 || (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24)) return 0;
+  int R = row_sites_default(g.n[0], nv);
   R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
-  // at least 12 sites: the halo sites (2 * 12 N_v words) take at most one
-  // 16-byte piece per thread
-  if (R < 12 || R * g.nv > 256) return 0;
+  // the halo sites (2 * 12 N_v words) take HK 16-byte pieces per thread:
+  // R HK >= 12; 64 .. 256 threads
+  const int hk = nv > 16 ? 2 : 1;
+  if (R * hk < 12 || R * nv > 256 || R * nv < 64) return 0;
   return R;
 }
 
-// Row-staged D_B for N_v = 12 in C64.  Returns hipErrorNotSupported
+// Row-staged D_B: FP32 storage for N_v = 4, 8, 12, 16, 24 (the clover term for
+// N_v = 12 only), FP64 storage for N_v = 12.  Returns hipErrorNotSupported
 // when the configuration is not covered (the caller then uses the direct
 // kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
@@ -575,21 +590,27 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
     return hipGetLastError();
   }
   const int R = brillouin_rows_sites(dtype, g);
-  if (R == 0) return hipErrorNotSupported;
+  if (R == 0 || (clover && g.nv != 12)) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
+  switch (g.nv) {
+    case 4: return brillouin_rows_t<4, C64, float, false, false>(adj, g, R, bt, xcd, Wl, in, out, nullptr, mass, st);
+    case 8: return brillouin_rows_t<8, C64, float, false, false>(adj, g, R, bt, xcd, Wl, in, out, nullptr, mass, st);
+    case 16: return brillouin_rows_t<16, C64, float, false, false>(adj, g, R, bt, xcd, Wl, in, out, nullptr, mass, st);
+    case 24: return brillouin_rows_t<24, C64, float, false, false>(adj, g, R, bt, xcd, Wl, in, out, nullptr, mass, st);
+  }
   return brillouin_rows_t<12, C64, float, false>(adj, g, R, bt, xcd, Wl, in, out, clover, mass, st);
 }
 
 // D_B with the off-axis links built from V inside the row-staged kernel (no W
-// array).  Same configurations as launch_brillouin_rows; hipErrorNotSupported
-// otherwise.
+// array).  The FP32 configurations of launch_brillouin_rows at N_v = 12;
+// hipErrorNotSupported otherwise.
 hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* V, const void* in, void* out,
                                 double mass, hipStream_t st, const void* clover) {
   const int R = brillouin_rows_sites(dtype, g);
-  if (R == 0) return hipErrorNotSupported;
+  if (R == 0 || g.nv != 12) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   bool xcd = true;

@@ -102,3 +102,16 @@ def staggered_rows_cover(nx, nv, dt):
         return False
     r = row_sites(nx, nv)
     return r >= 6 and 64 <= r * nv <= 256
+
+
+def brillouin_rows_cover(nx, nv, dt):
+    """D_B row-staged kernels: FP32 storage at N_v in 4, 8, 12, 16, 24 with
+    64 .. 256 threads and the halo in HK pieces a thread (R HK >= 12, HK = 2
+    above N_v = 16); FP64 storage at N_v = 12 (chunks of 16 sites)."""
+    if dt == "c128":
+        return nv == 12
+    if dt != "c64" or nv not in (4, 8, 12, 16, 24):
+        return False
+    r = row_sites(nx, nv)
+    hk = 2 if nv > 16 else 1
+    return r * hk >= 12 and 64 <= r * nv <= 256

@@ -1,6 +1,6 @@
-"""D_W and D_S at other block sizes N_v (the number of right-hand sides is the
-method's free parameter, Sec. 2): the row-staged t-marching kernels at N_v = 4,
-8, 16 and 24 against the FP64 oracle through the C ABI.
+"""D_W, D_S and D_B at other block sizes N_v (the number of right-hand sides is
+the method's free parameter, Sec. 2): the row-staged kernels at N_v = 4, 8, 16
+and 24 against the FP64 oracle through the C ABI.
 
 Where the library's launch rule covers a shape, the test runs it with
 DSLASH_ROWS=2 (the row-staged kernel or an error), so that a fall back to the
@@ -9,7 +9,7 @@ default must still give the oracle's result through the direct kernel."""
 import pytest
 
 import synthetic
-from oracle import staggered, wilson
+from oracle import brillouin, staggered, wilson
 from tests.gpu_util import compare, down, rounded, say, set_knob, up
 
 pytestmark = pytest.mark.gpu
@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
 
 from paper_1808_05506_amd import dslash as D  # noqa: E402
 
-from tests.helpers import staggered_rows_cover, wilson_rows_cover  # noqa: E402
+from tests.helpers import brillouin_rows_cover, staggered_rows_cover, wilson_rows_cover  # noqa: E402
 
 
 def _fields(dims, nv, dt, seed):
@@ -154,3 +154,31 @@ def test_staggered_columns_do_not_depend_on_the_block_size(adj, monkeypatch):
             part = D.apply("staggered", U, P[..., c0:c0 + k].contiguous(), 0.15, adjoint=adj)
             torch.cuda.synchronize()
             assert torch.equal(part, full[..., c0:c0 + k]), (k, c0)
+
+
+# one chunk (16), 20 sites (one chunk at N_v = 4, 10 + 10 below the 12-site
+# minimum at N_v = 8 and 16, two chunks of 10 with two halo pieces a thread at
+# N_v = 24), 24 sites (12 + 12 or three chunks of 8)
+BRI_SHAPES = [(16, 3, 3, 3), (20, 3, 2, 3), (24, 2, 3, 3)]
+
+
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("nv", [4, 8, 16, 24])
+@pytest.mark.parametrize("dims", BRI_SHAPES)
+def test_brillouin_rows_other_block_sizes(dims, nv, adj, monkeypatch):
+    dt = "c64"
+    covered = brillouin_rows_cover(dims[0], nv, dt)
+    say(f"case brillouin block size {dims} nv={nv} adj={adj} rows={covered}")
+    w = rounded(brillouin.build(synthetic.gauge_links(dims, "haar", 640 + nv)), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 641 + nv), dt)
+    W, P = up(w, dt), up(p, dt)
+    ref = brillouin.apply(w, p, 0.1, adj)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    if covered:
+        out = D.apply("brillouin", W, P, 0.1, adjoint=adj)
+    else:
+        with pytest.raises(D.DslashError):
+            D.apply("brillouin", W, P, 0.1, adjoint=adj)
+        set_knob(monkeypatch, "DSLASH_ROWS", None)
+        out = D.apply("brillouin", W, P, 0.1, adjoint=adj)
+    compare(down(out), ref, dt, f"D_B nv={nv}")
