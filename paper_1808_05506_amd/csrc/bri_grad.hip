@@ -476,6 +476,8 @@ hipError_t links_backward_t(const Geom& g, const void* V, const void* Wl, const 
 
 hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
                                   hipStream_t st) {
+  const hipError_t e = launch_brillouin_wgrad_rows(dtype, g, chi, psi, GW, st);
+  if (e != hipErrorNotSupported || knobs().rows.get(1) == 2) return e;
   switch (dtype) {
     case DT_C64: return wgrad_t<C64, float>(g, chi, psi, GW, st);
     case DT_C128: return wgrad_t<C128, double>(g, chi, psi, GW, st);

@@ -361,6 +361,184 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- gradient with respect to W
+// G_{W_d}(x) for the 40 stored directions d (slot n(d) - 41): the derivative
+// of L = Re sum conj(chi) (D_B psi) with each W taken as a free complex matrix.
+// W_d(x) enters the hop of d into out(x) with the spin factor S_d =
+// a_k + b_k d.gamma, and, as W_{-d}(x + d) = W_d(x)^dag, the hop of -d into
+// out(x + d) with S_{-d} = a_k - b_k d.gamma (eqs. def_der, def_lap, Tab. 1).
+// Both factors are Hermitian, so
+//   G_{W_d}(x) = sum_v sum_s [ chi(x)_s (x) conj((S_d psi(x + d))_s)
+//                            + psi(x)_s (x) conj((S_{-d} chi(x + d))_s) ].
+// The stored d reach the 14 rows 13 .. 26 of the 27-row order (the own row
+// for d = +x only, then every row with (dt, dz, dy) lexicographically
+// positive, where all three dx are stored).  A workgroup owns an x-row chunk;
+// each row's chi and psi runs, with the halo sites x0 - 1 and x0 + n, pass
+// through LDS.  Lane (x, v) keeps chi(x), psi(x) of its right-hand side in
+// registers and accumulates the row's three directions.  The N_v shares of a
+// site are then summed in LDS in lane order (deterministic, no atomics) and
+// written to G_W.
+
+constexpr int kWgFirstRow = 13;  // the own row; rows 13 .. 26 hold every stored d
+
+// out = (a + sum_mu B_mu gamma_mu) in, B_mu = b d_mu: the spin factor of a
+// hop, in the chiral basis of bri_hop; the d_mu tests are uniform.
+template <class T>
+__device__ __forceinline__ void bri_spin(T a, T B1, T B2, T B3, T B4, int d0, int d1, int d2, int d3,
+                                         const cpx<T> (&in)[4][3], cpx<T> (&out)[4][3]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) out[q][cc] = mk(a * in[q][cc].r, a * in[q][cc].i);
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    if (__builtin_amdgcn_readfirstlane(d3) != 0) {
+      out[0][cc] = rmadd(out[0][cc], B4, in[2][cc]);
+      out[1][cc] = rmadd(out[1][cc], B4, in[3][cc]);
+      out[2][cc] = rmadd(out[2][cc], B4, in[0][cc]);
+      out[3][cc] = rmadd(out[3][cc], B4, in[1][cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d2) != 0) {
+      out[0][cc] = cmadd_i(out[0][cc], -B3, in[2][cc]);
+      out[1][cc] = cmadd_i(out[1][cc], B3, in[3][cc]);
+      out[2][cc] = cmadd_i(out[2][cc], B3, in[0][cc]);
+      out[3][cc] = cmadd_i(out[3][cc], -B3, in[1][cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d1) != 0) {
+      out[0][cc] = rmadd(out[0][cc], -B2, in[3][cc]);
+      out[1][cc] = rmadd(out[1][cc], B2, in[2][cc]);
+      out[2][cc] = rmadd(out[2][cc], B2, in[1][cc]);
+      out[3][cc] = rmadd(out[3][cc], -B2, in[0][cc]);
+    }
+    if (__builtin_amdgcn_readfirstlane(d0) != 0) {
+      out[0][cc] = cmadd_i(out[0][cc], -B1, in[3][cc]);
+      out[1][cc] = cmadd_i(out[1][cc], -B1, in[2][cc]);
+      out[2][cc] = cmadd_i(out[2][cc], B1, in[1][cc]);
+      out[3][cc] = cmadd_i(out[3][cc], B1, in[0][cc]);
+    }
+  }
+}
+
+// gm += sum_s l_s (x) conj(r_s)
+template <class T>
+__device__ __forceinline__ void bri_outer(const cpx<T> (&l)[4][3], const cpx<T> (&r)[4][3], cpx<T> (&gm)[3][3]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gm[a][b] = cmaddj(gm[a][b], l[s][a], r[s][b]);
+}
+
+template <int NV, class S, class T>
+__device__ __forceinline__ void bri_lds_spinor(const typename S::word* site, int v, cpx<T> (&p)[4][3]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) p[q][cc] = S::template load<T>(site + (q * 3 + cc) * NV + v);
+}
+
+template <int NV, class S, class T>
+__global__ void __launch_bounds__(256, 2)
+    bri_wgrad_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ chi,
+                          const typename S::word* __restrict__ psi, typename S::word* __restrict__ GW) {
+  using W = typename S::word;
+  constexpr int SSW = SiteStride<NV, S>::WORDS;
+  extern __shared__ uint4 smem_wg[];
+  const int R = int(tr.sb);
+  W* bc = reinterpret_cast<W*>(smem_wg);  // chi row, (R + 2) sites
+  W* bp = bc + (R + 2) * SSW;            // psi row
+  T* red = reinterpret_cast<T*>(smem_wg);  // [3][R][18][NV], over bc and bp once a row is used
+
+  const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
+  const RowChunk c = row_chunk(g, tr, L);
+  const int v = threadIdx.x, xl = threadIdx.y;
+  const int tid = xl * NV + v, nth = R * NV;
+  const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+
+  cpx<T> ox[4][3], op[4][3];  // chi(x), psi(x) of the lane
+  BriRowRegs<NV, S> qc, qp;
+  bri_issue<true, NV, S>(g, c, nullptr, chi, kWgFirstRow, xm, xp, xl, v, tid, nth, qc);
+  bri_issue<true, NV, S>(g, c, nullptr, psi, kWgFirstRow, xm, xp, xl, v, tid, nth, qp);
+#pragma nounroll
+  for (int r = kWgFirstRow; r < kBriRows; ++r) {
+    if (r > kWgFirstRow) __syncthreads();  // the previous row's sums are read
+    bri_commit<true, NV, S>(c, qc, bc, nullptr, R, xl, v, tid, nth);
+    bri_commit<true, NV, S>(c, qp, bp, nullptr, R, xl, v, tid, nth);
+    __syncthreads();
+    const int rn = r + 1 < kBriRows ? r + 1 : kBriRows - 1;  // the last request repeats, unused
+    bri_issue<true, NV, S>(g, c, nullptr, chi, rn, xm, xp, xl, v, tid, nth, qc);
+    bri_issue<true, NV, S>(g, c, nullptr, psi, rn, xm, xp, xl, v, tid, nth, qp);
+    if (r == kWgFirstRow) {
+      bri_lds_spinor<NV, S, T>(bc + (xl + 1) * SSW, v, ox);
+      bri_lds_spinor<NV, S, T>(bp + (xl + 1) * SSW, v, op);
+    }
+    int dy, dz, dt;
+    bri_row_offset(r, dy, dz, dt);
+    cpx<T> gm[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gm[k][a][b] = zero<T>();
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (r == kWgFirstRow && dx != 1) continue;  // the own row: d = +x only
+      const int k = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
+      const T a = T(-0.5) * bri_lambda<T>(k), b = bri_rho<T>(k);
+      cpx<T> f[4][3], sf[4][3];
+      // chi(x) (x) conj(S_d psi(x + d))
+      bri_lds_spinor<NV, S, T>(bp + (xl + 1 + dx) * SSW, v, f);
+      bri_spin<T>(a, b * T(dx), b * T(dy), b * T(dz), b * T(dt), dx, dy, dz, dt, f, sf);
+      bri_outer<T>(ox, sf, gm[dx + 1]);
+      // psi(x) (x) conj(S_{-d} chi(x + d))
+      bri_lds_spinor<NV, S, T>(bc + (xl + 1 + dx) * SSW, v, f);
+      bri_spin<T>(a, -b * T(dx), -b * T(dy), -b * T(dz), -b * T(dt), dx, dy, dz, dt, f, sf);
+      bri_outer<T>(op, sf, gm[dx + 1]);
+    }
+    __syncthreads();  // the row is used: its LDS takes the shares
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        red[((k * R + xl) * 18 + 2 * e) * NV + v] = gm[k][e / 3][e % 3].r;
+        red[((k * R + xl) * 18 + 2 * e + 1) * NV + v] = gm[k][e / 3][e % 3].i;
+      }
+    __syncthreads();
+    // sums over the N_v lanes of each (direction, site, element), in lane order
+    const int k0 = r == kWgFirstRow ? 2 : 0;
+    const int nout = (3 - k0) * c.n * 9;
+    for (int o = tid; o < nout; o += nth) {
+      const int k = k0 + o / (c.n * 9), rem = o - (k - k0) * c.n * 9;
+      const int site = rem / 9, e = rem - site * 9;
+      const T* src = red + ((k * R + site) * 18 + 2 * e) * NV;
+      T re = T(0), im = T(0);
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        re += src[l];
+        im += src[NV + l];
+      }
+      const int slot = bri_code(k - 1, dy, dz, dt) - 41;
+      S::template store<T>(GW + (size_t(c.row_base + c.x0 + site) * 40 + slot) * 9 + e, mk(re, im));
+    }
+  }
+}
+
+template <int NV, class S, class T>
+static hipError_t brillouin_wgrad_rows_t(const Geom& g, int R, int bt, bool xcd, const void* chi, const void* psi,
+                                         void* GW, hipStream_t st) {
+  using W = typename S::word;
+  const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
+  const size_t stage = size_t(2 * (R + 2)) * SiteStride<NV, S>::WORDS * sizeof(W);
+  const size_t sums = size_t(3 * R) * 18 * NV * sizeof(T);
+  const size_t lds = stage > sums ? stage : sums;
+  hipLaunchKernelGGL((bri_wgrad_rows_kernel<NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)chi,
+                     (const W*)psi, (W*)GW);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- FP64, staged straight into LDS
 // The FP64 D_B keeps the row staging of brillouin_rows_kernel, but its rows
 // are copied from global memory into LDS by the direct-to-LDS load path
@@ -616,6 +794,21 @@ hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* 
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
   return brillouin_rows_t<12, C64, float, true>(adj, g, R, bt, xcd, V, in, out, clover, mass, st);
+}
+
+// Row-staged gradient with respect to W (FP32 storage, N_v = 12, chunks of at
+// least 12 sites); hipErrorNotSupported otherwise (the caller then uses the
+// per-direction kernel).  DSLASH_ROWS=0 disables it.
+hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
+                                       hipStream_t st) {
+  if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (dtype != DT_C64 || g.nv != 12) return hipErrorNotSupported;
+  const int R = brillouin_rows_sites(dtype, g);
+  if (R == 0) return hipErrorNotSupported;
+  int bt = 2;
+  bt = knobs().tband.get(bt);
+  const bool xcd = knobs().xcd.get(1) != 0;
+  return brillouin_wgrad_rows_t<12, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
 }
 
 }  // namespace dsl

@@ -88,6 +88,8 @@ hipError_t launch_brillouin_fly(bool adjoint, int dtype, const Geom& g, const vo
 hipError_t launch_clover_field(int dtype, const Geom& g, const void* V, void* C, double c_sw, hipStream_t st);
 hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
                                   hipStream_t st);
+hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
+                                       hipStream_t st);
 // W (nullable): the stored off-axis links of V; with it the adjoint uses the
 // path averages of W instead of walking every ordering through V
 hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* W, const void* GW,

@@ -5,7 +5,8 @@ import pytest
 
 import synthetic
 from oracle import brillouin, grad
-from tests.gpu_util import compare, down, say, up
+from tests.gpu_util import compare, down, rounded, say, set_knob, up
+from tests.helpers import brillouin_rows_cover
 
 pytestmark = pytest.mark.gpu
 
@@ -31,9 +32,24 @@ def test_wgrad_matches_oracle(dt, dims, nv):
     w = brillouin.build(v)
     W = up(w, dt)
     gW, gi = D.backward("brillouin", W, up(chi, dt), up(psi, dt), 0.1)
-    ref = grad.link_grad_brillouin_W(down(up(chi, dt)), down(up(psi, dt)))
+    ref = grad.link_grad_brillouin_W(rounded(chi, dt), rounded(psi, dt))
     compare(down(gW), ref, dt, "G_W")
-    compare(down(gi), brillouin.apply(down(W), down(up(chi, dt)), 0.1, True), dt, "grad_in")
+    compare(down(gi), brillouin.apply(rounded(w, dt), rounded(chi, dt), 0.1, True), dt, "grad_in")
+
+
+@pytest.mark.parametrize("dims", [(16, 3, 3, 3), (13, 2, 3, 4), (24, 2, 3, 3), (28, 2, 2, 3)])
+def test_wgrad_rows_matches_oracle(dims, monkeypatch):
+    # FP32, N_v = 12: the row-staged gradient kernel (required: DSLASH_ROWS=2)
+    # on one chunk (16, 13 sites), two chunks of 12 and of 14
+    dt, nv = "c64", 12
+    assert brillouin_rows_cover(dims[0], nv, dt)
+    say(f"case brillouin W gradient rows {dims}")
+    v, chi, psi = _fields(dims, nv, 115)
+    W = up(brillouin.build(v), dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    gW, _ = D.backward("brillouin", W, up(chi, dt), up(psi, dt), 0.1, need_grad_in=False)
+    ref = grad.link_grad_brillouin_W(rounded(chi, dt), rounded(psi, dt))
+    compare(down(gW), ref, dt, "G_W rows")
 
 
 @pytest.mark.parametrize("with_w", [False, True])
