@@ -373,11 +373,13 @@ static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool 
 // The stored d reach the 14 rows 13 .. 26 of the 27-row order (the own row
 // for d = +x only, then every row with (dt, dz, dy) lexicographically
 // positive, where all three dx are stored).  A workgroup owns an x-row chunk;
-// each row's chi and psi runs, with the halo sites x0 - 1 and x0 + n, pass
-// through LDS.  Lane (x, v) keeps chi(x), psi(x) of its right-hand side in
-// registers and accumulates the row's three directions.  The N_v shares of a
-// site are then summed in LDS in lane order (deterministic, no atomics) and
-// written to G_W.
+// each row's psi run, then its chi run, with the halo sites x0 - 1 and x0 + n,
+// pass through one LDS buffer.  Lane (x, v) keeps chi(x), psi(x) of its
+// right-hand side in registers; it forms the first term of each of the row's
+// directions from the psi run and adds the second from the chi run, in its own
+// LDS slots.  The N_v shares of a site are then summed in lane order
+// (deterministic, no atomics) and written to G_W.  One run at a time keeps the
+// kernel at 160 VGPRs, three waves per SIMD.
 
 constexpr int kWgFirstRow = 13;  // the own row; rows 13 .. 26 hold every stored d
 
@@ -439,72 +441,78 @@ __device__ __forceinline__ void bri_lds_spinor(const typename S::word* site, int
 }
 
 template <int NV, class S, class T>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, 3)
     bri_wgrad_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ chi,
                           const typename S::word* __restrict__ psi, typename S::word* __restrict__ GW) {
   using W = typename S::word;
   constexpr int SSW = SiteStride<NV, S>::WORDS;
   extern __shared__ uint4 smem_wg[];
   const int R = int(tr.sb);
-  W* bc = reinterpret_cast<W*>(smem_wg);  // chi row, (R + 2) sites
-  W* bp = bc + (R + 2) * SSW;            // psi row
-  T* red = reinterpret_cast<T*>(smem_wg);  // [3][R][18][NV], over bc and bp once a row is used
+  W* bs = reinterpret_cast<W*>(smem_wg);              // one staged run, (R + 2) sites
+  T* red = reinterpret_cast<T*>(bs + (R + 2) * SSW);  // [3][R][18][NV]
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
   const RowChunk c = row_chunk(g, tr, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
+  const int xc = xl < c.n ? xl : c.n - 1;
 
-  cpx<T> ox[4][3], op[4][3];  // chi(x), psi(x) of the lane
-  BriRowRegs<NV, S> qc, qp;
-  bri_issue<true, NV, S>(g, c, nullptr, chi, kWgFirstRow, xm, xp, xl, v, tid, nth, qc);
-  bri_issue<true, NV, S>(g, c, nullptr, psi, kWgFirstRow, xm, xp, xl, v, tid, nth, qp);
+  cpx<T> ox[4][3], op[4][3];  // chi(x), psi(x) of the lane, read once from global memory
+  {
+    const size_t base = size_t(c.row_base + c.x0 + xc) * 12 * NV + v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        ox[q][cc] = S::template load<T>(chi + base + (q * 3 + cc) * NV);
+        op[q][cc] = S::template load<T>(psi + base + (q * 3 + cc) * NV);
+      }
+  }
+  BriRowRegs<NV, S> qr;
+  bri_issue<true, NV, S>(g, c, nullptr, psi, kWgFirstRow, xm, xp, xl, v, tid, nth, qr);
 #pragma nounroll
   for (int r = kWgFirstRow; r < kBriRows; ++r) {
-    if (r > kWgFirstRow) __syncthreads();  // the previous row's sums are read
-    bri_commit<true, NV, S>(c, qc, bc, nullptr, R, xl, v, tid, nth);
-    bri_commit<true, NV, S>(c, qp, bp, nullptr, R, xl, v, tid, nth);
-    __syncthreads();
-    const int rn = r + 1 < kBriRows ? r + 1 : kBriRows - 1;  // the last request repeats, unused
-    bri_issue<true, NV, S>(g, c, nullptr, chi, rn, xm, xp, xl, v, tid, nth, qc);
-    bri_issue<true, NV, S>(g, c, nullptr, psi, rn, xm, xp, xl, v, tid, nth, qp);
-    if (r == kWgFirstRow) {
-      bri_lds_spinor<NV, S, T>(bc + (xl + 1) * SSW, v, ox);
-      bri_lds_spinor<NV, S, T>(bp + (xl + 1) * SSW, v, op);
-    }
     int dy, dz, dt;
     bri_row_offset(r, dy, dz, dt);
-    cpx<T> gm[3][3][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int phase = 0; phase < 2; ++phase) {
+      // phase 0 stages psi of the row, phase 1 chi; each requests the next run
+      __syncthreads();  // the staged run and the sums of the previous phase or row are read
+      bri_commit<true, NV, S>(c, qr, bs, nullptr, R, xl, v, tid, nth);
+      __syncthreads();
+      const int rn = phase == 0 ? r : (r + 1 < kBriRows ? r + 1 : kBriRows - 1);
+      bri_issue<true, NV, S>(g, c, nullptr, phase == 0 ? chi : psi, rn, xm, xp, xl, v, tid, nth, qr);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (r == kWgFirstRow && dx != 1) continue;
+        const int k = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
+        const T a = T(-0.5) * bri_lambda<T>(k), b = (phase == 0 ? T(1) : T(-1)) * bri_rho<T>(k);
+        cpx<T> gm[3][3];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) gm[k][a][b] = zero<T>();
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      if (r == kWgFirstRow && dx != 1) continue;  // the own row: d = +x only
-      const int k = (dx != 0) + (dy != 0) + (dz != 0) + (dt != 0);
-      const T a = T(-0.5) * bri_lambda<T>(k), b = bri_rho<T>(k);
-      cpx<T> f[4][3], sf[4][3];
-      // chi(x) (x) conj(S_d psi(x + d))
-      bri_lds_spinor<NV, S, T>(bp + (xl + 1 + dx) * SSW, v, f);
-      bri_spin<T>(a, b * T(dx), b * T(dy), b * T(dz), b * T(dt), dx, dy, dz, dt, f, sf);
-      bri_outer<T>(ox, sf, gm[dx + 1]);
-      // psi(x) (x) conj(S_{-d} chi(x + d))
-      bri_lds_spinor<NV, S, T>(bc + (xl + 1 + dx) * SSW, v, f);
-      bri_spin<T>(a, -b * T(dx), -b * T(dy), -b * T(dz), -b * T(dt), dx, dy, dz, dt, f, sf);
-      bri_outer<T>(op, sf, gm[dx + 1]);
-    }
-    __syncthreads();  // the row is used: its LDS takes the shares
+          for (int j = 0; j < 3; ++j) gm[i][j] = zero<T>();
+        cpx<T> f[4][3], sf[4][3];
+        bri_lds_spinor<NV, S, T>(bs + (xl + 1 + dx) * SSW, v, f);
+        bri_spin<T>(a, b * T(dx), b * T(dy), b * T(dz), b * T(dt), dx, dy, dz, dt, f, sf);
+        // phase 0: chi(x) (x) conj(S_d psi(x + d)); phase 1: psi(x) (x) conj(S_{-d} chi(x + d))
+        if (phase == 0) bri_outer<T>(ox, sf, gm);
+        else bri_outer<T>(op, sf, gm);
+        // the lane's own slots of the row's sums: written in phase 0, added to in phase 1
+        T* mine = red + ((dx + 1) * R + xl) * 18 * NV + v;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        red[((k * R + xl) * 18 + 2 * e) * NV + v] = gm[k][e / 3][e % 3].r;
-        red[((k * R + xl) * 18 + 2 * e + 1) * NV + v] = gm[k][e / 3][e % 3].i;
+        for (int e = 0; e < 9; ++e) {
+          if (phase == 0) {
+            mine[(2 * e) * NV] = gm[e / 3][e % 3].r;
+            mine[(2 * e + 1) * NV] = gm[e / 3][e % 3].i;
+          } else {
+            mine[(2 * e) * NV] += gm[e / 3][e % 3].r;
+            mine[(2 * e + 1) * NV] += gm[e / 3][e % 3].i;
+          }
+        }
       }
+    }
     __syncthreads();
     // sums over the N_v lanes of each (direction, site, element), in lane order
     const int k0 = r == kWgFirstRow ? 2 : 0;
@@ -531,9 +539,7 @@ static hipError_t brillouin_wgrad_rows_t(const Geom& g, int R, int bt, bool xcd,
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
-  const size_t stage = size_t(2 * (R + 2)) * SiteStride<NV, S>::WORDS * sizeof(W);
-  const size_t sums = size_t(3 * R) * 18 * NV * sizeof(T);
-  const size_t lds = stage > sums ? stage : sums;
+  const size_t lds = size_t(R + 2) * SiteStride<NV, S>::WORDS * sizeof(W) + size_t(3 * R) * 18 * NV * sizeof(T);
   hipLaunchKernelGGL((bri_wgrad_rows_kernel<NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)chi,
                      (const W*)psi, (W*)GW);
   return hipGetLastError();
