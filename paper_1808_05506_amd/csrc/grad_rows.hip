@@ -214,29 +214,43 @@ static hipError_t grad_rows_t(const Geom& g, int R, int bt, bool xcd, const void
   return hipGetLastError();
 }
 
-// Row-staged link gradient for N_v = 12: D_W in C64, D_S in C64 and C128 (the
-// D_W C128 variant would not fit in registers).  Returns
+template <int NV>
+static hipError_t grad_rows_nv(int op, int dtype, const Geom& g, int R, int bt, bool xcd, const void* chi,
+                               const void* psi, void* G, hipStream_t st) {
+  if (op == OP_WILSON) return grad_rows_t<OP_WILSON, NV, C64, float>(g, R, bt, xcd, chi, psi, G, st);
+  if (dtype == DT_C64) return grad_rows_t<OP_STAGGERED, NV, C64, float>(g, R, bt, xcd, chi, psi, G, st);
+  return grad_rows_t<OP_STAGGERED, NV, C128, double>(g, R, bt, xcd, chi, psi, G, st);
+}
+
+// Row-staged link gradient for N_v = 4, 8, 12, 16, 24: D_W in C64, D_S in C64
+// and C128 (the D_W C128 variant would not fit in registers).  Returns
 // hipErrorNotSupported when the configuration is not covered (the caller then
 // uses the direct kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
-  if (g.nv != 12 || (op != OP_WILSON && op != OP_STAGGERED)) return hipErrorNotSupported;
+  const int nv = g.nv;
+  if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
+  if (op != OP_WILSON && op != OP_STAGGERED) return hipErrorNotSupported;
   if (dtype != DT_C64 && !(dtype == DT_C128 && op == OP_STAGGERED)) return hipErrorNotSupported;
-  int R = row_sites_default(g.n[0], g.nv);
+  int R = row_sites_default(g.n[0], nv);
   R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
-  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  // 64 .. 256 threads; the +x halo site (CH N_v pieces, CH <= 6) takes one
+  // piece per thread at R >= 6
+  if (R < 6 || R * nv > 256 || R * nv < 64) return hipErrorNotSupported;
   // t-band of the row traversal: 4 (2: 587 against 578 us for D_W at 24^3 x 48)
   int bt = 4;
   bt = knobs().tband.get(bt);
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
-  if (op == OP_WILSON) {
-    return grad_rows_t<OP_WILSON, 12, C64, float>(g, R, bt, xcd, chi, psi, G, st);
+  switch (nv) {
+    case 4: return grad_rows_nv<4>(op, dtype, g, R, bt, xcd, chi, psi, G, st);
+    case 8: return grad_rows_nv<8>(op, dtype, g, R, bt, xcd, chi, psi, G, st);
+    case 16: return grad_rows_nv<16>(op, dtype, g, R, bt, xcd, chi, psi, G, st);
+    case 24: return grad_rows_nv<24>(op, dtype, g, R, bt, xcd, chi, psi, G, st);
   }
-  if (dtype == DT_C64) return grad_rows_t<OP_STAGGERED, 12, C64, float>(g, R, bt, xcd, chi, psi, G, st);
-  return grad_rows_t<OP_STAGGERED, 12, C128, double>(g, R, bt, xcd, chi, psi, G, st);
+  return grad_rows_nv<12>(op, dtype, g, R, bt, xcd, chi, psi, G, st);
 }
 
 }  // namespace dsl

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) link_grad_kernel(Geom g, const typename S
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st) {
   const hipError_t rows = launch_grad_rows(op, dtype, g, chi, psi, G, st);
-  if (rows != hipErrorNotSupported) return rows;
+  if (rows != hipErrorNotSupported || knobs().rows.get(1) == 2) return rows;
   Shape sh = site_v_shape(g.vol, g.nv);
   sh.grid.y = 1;  // one block covers every right-hand side of its sites
   const size_t csz = dtype == DT_C128 ? 16 : 8;

@@ -115,3 +115,14 @@ def brillouin_rows_cover(nx, nv, dt):
     r = row_sites(nx, nv)
     hk = 2 if nv > 16 else 1
     return r * hk >= 12 and 64 <= r * nv <= 256
+
+
+def grad_rows_cover(nx, nv, op, dt):
+    """Link-gradient row kernel: D_W in C64, D_S in C64 and C128; N_v in 4, 8,
+    12, 16, 24, 64 .. 256 threads and at least 6 sites per chunk."""
+    if nv not in (4, 8, 12, 16, 24):
+        return False
+    if not (dt == "c64" or (dt == "c128" and op == "staggered")):
+        return False
+    r = row_sites(nx, nv)
+    return r >= 6 and 64 <= r * nv <= 256

@@ -6,6 +6,7 @@ import pytest
 import synthetic
 from oracle import grad, local, staggered, wilson
 from tests.gpu_util import compare, down, rounded, say, set_knob, up
+from tests.helpers import grad_rows_cover
 
 pytestmark = pytest.mark.gpu
 
@@ -100,15 +101,20 @@ _ROW_DIMS_W = [(16, 4, 2, 6), (20, 3, 4, 5), (11, 2, 2, 3), (12, 2, 2, 3), (32, 
 _ROW_DIMS_S = [(16, 4, 2, 6), (20, 2, 4, 6), (12, 2, 2, 4), (14, 2, 2, 2), (32, 2, 2, 2)]  # D_S: even extents
 
 
+@pytest.mark.parametrize("nv", [4, 8, 12, 16, 24])
 @pytest.mark.parametrize("op,dt,dims", [("wilson", "c64", d) for d in _ROW_DIMS_W]
                          + [("staggered", dt, d) for dt in ("c64", "c128") for d in _ROW_DIMS_S])
-def test_link_grad_row_staged_path(op, dt, dims):
-    # N_v = 12 with rows of >= 11 sites runs the LDS row-staged gradient kernel
-    # (D_W in C64, D_S in C64 and C128); 20 sites split into chunks of 11 + 9,
-    # 32 into 16 + 16, 11 to 16 fill one chunk with the wrap-around halo
-    nv = 12
-    say(f"case link grad rows {op} {dims} nv={nv} {dt}")
+def test_link_grad_row_staged_path(op, dt, dims, nv, monkeypatch):
+    # the LDS row-staged gradient kernel (D_W in C64, D_S in C64 and C128) at
+    # every block size it is built for, required (DSLASH_ROWS=2) where the
+    # launch rule covers the row: 20 sites split into 11 + 9 (N_v = 12) or
+    # 10 + 10, 32 into 16 + 16 or 32 at N_v = 4, 11 to 16 fill one chunk with
+    # the wrap-around halo; rows the rule leaves out take the direct kernel
+    covered = grad_rows_cover(dims[0], nv, op, dt)
+    say(f"case link grad rows {op} {dims} nv={nv} {dt} rows={covered}")
     u, chi, psi = _fields(op, dims, nv, 400, dt)
+    if covered:
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
     gU, _ = D.backward(op, up(u, dt), up(chi, dt), up(psi, dt), 0.2, need_grad_in=False)
     compare(down(gU), grad.link_grad(op, chi, psi), dt, f"grad_U rows {op}")
 
