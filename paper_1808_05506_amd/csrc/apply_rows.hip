@@ -485,12 +485,13 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   if constexpr (DEPTH > 4) DSL_ISSUE(4);
   if constexpr (DEPTH > 5) DSL_ISSUE(5);
   if constexpr (DEPTH > 6) DSL_ISSUE(6);
-  // links of the chunk's sites and of the halo site x0 - 1 (at most 3 pieces
-  // per thread: a site's links are 36 words)
-  constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16;
-  copy_pieces<3>(lown + 36, U + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
+  // links of the chunk's sites and of the halo site x0 - 1: a site's links
+  // are LINK_PIECES 16-byte pieces, so the R N_v threads move ceil(LINK_PIECES /
+  // N_v) pieces each (the halo site's, one piece each)
+  constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16, LK = (LINK_PIECES + NV - 1) / NV;
+  copy_pieces<LK>(lown + 36, U + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
   copy_pieces<1>(lown, U + size_t(c.row_base + xm) * 36, LINK_PIECES, tid, nth);
-  if constexpr (CLOV) copy_pieces<3>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
+  if constexpr (CLOV) copy_pieces<LK>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
 
   cpx<T> acc[4][3];
 #pragma unroll
@@ -1218,11 +1219,15 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   {
     // links of the chunk's own sites (forward hops) and V_x(x - 1) of the x - 1
     // neighbours, which live in the other parity's row
-    constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16;
-    copy_pieces<3>(lown + 36, Uo + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
-    const int w = tid < c.n * 9 ? tid : c.n * 9 - 1;
-    const int k = w / 9, e = w - k * 9;
-    lxb[w] = Ui[size_t(c.row_base + wrap_x(g, c.x0 + k - 1 + r)) * 36 + e];
+    constexpr int LINK_PIECES = 36 * int(sizeof(W)) / 16, LK = (LINK_PIECES + NV - 1) / NV;
+    copy_pieces<LK>(lown + 36, Uo + size_t(c.row_base + c.x0) * 36, c.n * LINK_PIECES, tid, nth);
+    constexpr int KX = (9 + NV - 1) / NV;  // words of V_x(x - 1) per thread
+#pragma unroll
+    for (int i = 0; i < KX; ++i) {
+      const int q = tid + i * nth, w = q < c.n * 9 ? q : c.n * 9 - 1;
+      const int k = w / 9, e = w - k * 9;
+      lxb[w] = Ui[size_t(c.row_base + wrap_x(g, c.x0 + k - 1 + r)) * 36 + e];
+    }
   }
 
   cpx<T> acc[4][3];
@@ -1319,9 +1324,25 @@ static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool 
   return hipGetLastError();
 }
 
-// Row-staged even-odd hop for N_v = 12 (C64, BF16, F16 storage) on rows of
-// at least 11 packed sites; hipErrorNotSupported otherwise (the caller then
-// uses the direct kernel).  DSLASH_ROWS=0 disables it.
+template <int NV>
+static hipError_t wilson_eo_rows_nv(bool adj, int dtype, const Geom& g, int R, int bt, bool xcd, int parity,
+                                    const void* Uo, const void* Ui, const void* in, void* out, const void* add,
+                                    double c_add, double c_hop, hipStream_t st, int epi, EpiArgs& ep) {
+  switch (dtype) {
+    case DT_C64: return wilson_eo_rows_t<NV, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
+                                                      st, epi, ep);
+    case DT_BF16: return wilson_eo_rows_t<NV, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add,
+                                                       c_hop, st, epi, ep);
+    case DT_F16: return wilson_eo_rows_t<NV, F16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
+                                                      st, epi, ep);
+  }
+  return hipErrorNotSupported;
+}
+
+// Row-staged even-odd hop for N_v = 4, 8, 12, 16, 24 (C64, BF16, F16
+// storage), with the chunk rule of the full-lattice kernels on the packed
+// rows; hipErrorNotSupported otherwise (the caller then uses the direct
+// kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parity, const void* Uo, const void* Ui,
                                  const void* in, void* out, const void* add, double c_add, double c_hop,
                                  hipStream_t st, int epi, EpiArgs* ea) {
@@ -1329,28 +1350,30 @@ hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parit
   if (epi != EPI_STORE && !ea) return hipErrorNotSupported;
   EpiArgs none;
   EpiArgs& ep = ea ? *ea : none;
-  if (e.nv != 12) return hipErrorNotSupported;
+  const int nv = e.nv;
+  if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
   const int pdims[4] = {e.nh, e.n[1], e.n[2], e.n[3]};
-  const Geom g = make_geom(pdims, e.nv);
-  int R = row_sites_default(g.n[0], g.nv);
+  const Geom g = make_geom(pdims, nv);
+  int R = row_sites_default(g.n[0], nv);
   R = knobs().row_sites.get(R);
   if (R > g.n[0]) R = g.n[0];
-  if (R < 1 || R * g.nv > 256 || R * g.nv < 128) return hipErrorNotSupported;
+  if (R < 1 || R * nv > 256 || R * nv < 64) return hipErrorNotSupported;
+  // the own row's two halo sites in the extra register groups
   const int word_bytes = int(dtype_bytes(dtype));
-  if (R * g.nv * 16 < 2 * 12 * g.nv * word_bytes) return hipErrorNotSupported;
+  if (R * 16 * row_extra_groups(nv, word_bytes) < 2 * 12 * word_bytes) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
-  switch (dtype) {
-    case DT_C64: return wilson_eo_rows_t<12, C64, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
-                                                      st, epi, ep);
-    case DT_BF16: return wilson_eo_rows_t<12, BF16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
-                                                      st, epi, ep);
-    case DT_F16: return wilson_eo_rows_t<12, F16, float>(adj, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop,
-                                                      st, epi, ep);
+  switch (nv) {
+    case 4: return wilson_eo_rows_nv<4>(adj, dtype, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ep);
+    case 8: return wilson_eo_rows_nv<8>(adj, dtype, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ep);
+    case 16:
+      return wilson_eo_rows_nv<16>(adj, dtype, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ep);
+    case 24:
+      return wilson_eo_rows_nv<24>(adj, dtype, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ep);
   }
-  return hipErrorNotSupported;
+  return wilson_eo_rows_nv<12>(adj, dtype, g, R, bt, xcd, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ep);
 }
 
 template <int DEPTH, int NV, class S, class T>

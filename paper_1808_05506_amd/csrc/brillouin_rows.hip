@@ -300,8 +300,8 @@ __global__ void __launch_bounds__(256, BriWaves<NV>::value)
   // about a thousand instructions per lane hide the load latency); the
   // request after the last row repeats it, unused, so every load is
   // unconditional and in bounds
-  if constexpr (CLOV)
-    copy_pieces<3>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * (36 * int(sizeof(W)) / 16), tid, nth);
+  constexpr int CLP = 36 * int(sizeof(W)) / 16;  // 16-byte pieces of a site's clover term
+  if constexpr (CLOV) copy_pieces<(CLP + NV - 1) / NV>(lcl, C + size_t(c.row_base + c.x0) * 36, c.n * CLP, tid, nth);
   BriRowRegs<NV, S> q;
   bri_issue<FLY, NV, S>(g, c, Wl, in, 0, xm, xp, xl, v, tid, nth, q);
 #pragma nounroll

@@ -191,7 +191,7 @@ hipError_t launch_wilson_eo_hop(bool adj, int dtype, const EoGeom& e, int parity
                                 hipStream_t st, int epi, EpiArgs* ea) {
   const hipError_t rows =
       launch_wilson_eo_rows(adj, dtype, e, parity, Uo, Ui, in, out, add, c_add, c_hop, st, epi, ea);
-  if (rows != hipErrorNotSupported || epi != EPI_STORE) return rows;
+  if (rows != hipErrorNotSupported || epi != EPI_STORE || knobs().rows.get(1) == 2) return rows;
   Shape sh = site_v_shape(e.hvol, e.nv);
 #define DSL_EO(SS, TT)                                                                                          \
   do {                                                                                                           \

@@ -6,6 +6,7 @@ import pytest
 import synthetic
 from oracle import evenodd, solver, wilson
 from tests.gpu_util import compare, down, rounded, say, up, set_knob
+from tests.helpers import wilson_rows_cover
 
 pytestmark = pytest.mark.gpu
 
@@ -47,14 +48,35 @@ def test_eo_hop_matches_oracle(dt, adj, parity, dims, nv):
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("parity", [0, 1])
 @pytest.mark.parametrize("dims", [(24, 2, 2, 2), (54, 2, 4, 2), (64, 2, 2, 4)])
-def test_eo_hop_row_staged_matches_oracle(dt, adj, parity, dims):
+def test_eo_hop_row_staged_matches_oracle(dt, adj, parity, dims, monkeypatch):
     say(f"case eo hop rows {dims} nv=12 {dt} parity={parity} adj={adj}")
     u = rounded(synthetic.gauge_links(dims, "haar", 68), dt)
     p = rounded(synthetic.wilson_spinor(dims, 12, 69), dt)
     pin = evenodd.pack(p, 1 - parity)
     ue, uo = evenodd.pack(u, 0), evenodd.pack(u, 1)
+    if wilson_rows_cover(dims[0] // 2, 12, dt):
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
     out = D.eo_hop(up(ue, dt), up(uo, dt), up(pin, dt), parity, adjoint=adj)
     compare(down(out), evenodd.hop_eo(u, pin, parity, adj), dt, "eo hop rows")
+
+
+# Other block sizes: packed rows of 8, 16, 24 and 32 sites (one to three
+# chunks), the row-staged hop required wherever the launch rule covers it
+@pytest.mark.parametrize("dt", ["c64", "bf16"])
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("nv", [4, 8, 16, 24])
+@pytest.mark.parametrize("dims", [(16, 2, 2, 2), (32, 2, 2, 4), (48, 2, 2, 2), (64, 2, 2, 2)])
+def test_eo_hop_rows_other_block_sizes(dt, adj, nv, dims, monkeypatch):
+    covered = wilson_rows_cover(dims[0] // 2, nv, dt)
+    say(f"case eo hop rows {dims} nv={nv} {dt} adj={adj} rows={covered}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 72), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 73), dt)
+    pin = evenodd.pack(p, 0)
+    ue, uo = evenodd.pack(u, 0), evenodd.pack(u, 1)
+    if covered:
+        set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    out = D.eo_hop(up(ue, dt), up(uo, dt), up(pin, dt), 1, adjoint=adj)
+    compare(down(out), evenodd.hop_eo(u, pin, 1, adj), dt, f"eo hop rows nv={nv}")
 
 
 def test_eo_hop_row_staged_equals_direct_kernel(monkeypatch):
@@ -87,7 +109,8 @@ def test_eo_hop_split_reproduces_full_operator():
 
 
 @pytest.mark.parametrize("inner,itol", [("c64", 1e-5), ("bf16", 0.05), ("f16", 5e-3)])
-@pytest.mark.parametrize("dims,nv", [((4, 4, 4, 4), 3), ((12, 4, 2, 4), 12), ((24, 4, 2, 4), 12)])
+@pytest.mark.parametrize("dims,nv", [((4, 4, 4, 4), 3), ((12, 4, 2, 4), 12), ((24, 4, 2, 4), 12),
+                                     ((32, 4, 2, 4), 4), ((32, 2, 2, 4), 24)])
 def test_solve_eo(inner, itol, dims, nv):
     m0 = 0.05
     say(f"case solve eo {dims} nv={nv} inner={inner}")
