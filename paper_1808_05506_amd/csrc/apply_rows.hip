@@ -1347,6 +1347,8 @@ hipError_t launch_wilson_eo_rows(bool adj, int dtype, const EoGeom& e, int parit
                                  const void* in, void* out, const void* add, double c_add, double c_hop,
                                  hipStream_t st, int epi, EpiArgs* ea) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(Uo) || !aligned16(Ui) || !aligned16(in) || !aligned16(out) || !aligned16(add))
+    return hipErrorNotSupported;
   if (epi != EPI_STORE && !ea) return hipErrorNotSupported;
   EpiArgs none;
   EpiArgs& ep = ea ? *ea : none;
@@ -1438,6 +1440,7 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
                               double mass, hipStream_t st, const void* clover, bool compressed, int epi,
                               EpiArgs* ea) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(U) || !aligned16(in) || !aligned16(out) || !aligned16(clover)) return hipErrorNotSupported;
   if (epi != EPI_STORE && (!ea || clover || compressed)) return hipErrorNotSupported;
   EpiArgs none;
   EpiArgs& e = ea ? *ea : none;

@@ -760,6 +760,7 @@ static int brillouin_rows_sites(int dtype, const Geom& g) {
 hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void* Wl, const void* in, void* out,
                                  double mass, hipStream_t st, const void* clover) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(Wl) || !aligned16(in) || !aligned16(out) || !aligned16(clover)) return hipErrorNotSupported;
   if (dtype == DT_C128 && g.nv == 12 && !clover) {
     // FP64: the direct-to-LDS staged kernel, chunks of 16 sites
     const RowTraversal tr = make_row_traversal(g, uint32_t(kDmaSites), uint32_t(knobs().tband.get(2)));
@@ -793,6 +794,7 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
 // hipErrorNotSupported otherwise.
 hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* V, const void* in, void* out,
                                 double mass, hipStream_t st, const void* clover) {
+  if (!aligned16(V) || !aligned16(in) || !aligned16(out) || !aligned16(clover)) return hipErrorNotSupported;
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0 || g.nv != 12) return hipErrorNotSupported;
   int bt = 2;
@@ -808,6 +810,7 @@ hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* 
 hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
                                        hipStream_t st) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(chi) || !aligned16(psi) || !aligned16(GW)) return hipErrorNotSupported;
   if (dtype != DT_C64 || g.nv != 12) return hipErrorNotSupported;
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0) return hipErrorNotSupported;

@@ -229,6 +229,7 @@ static hipError_t grad_rows_nv(int op, int dtype, const Geom& g, int R, int bt, 
 hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(chi) || !aligned16(psi) || !aligned16(G)) return hipErrorNotSupported;
   const int nv = g.nv;
   if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
   if (op != OP_WILSON && op != OP_STAGGERED) return hipErrorNotSupported;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
 #include <stdlib.h>
 
 #include "dslash_common.hpp"
@@ -53,6 +54,10 @@ inline const Knobs& knobs() { return knob_store(); }
 
 enum Op { OP_STAGGERED = 0, OP_WILSON = 1, OP_BRILLOUIN = 2 };
 enum Dtype { DT_C64 = 0, DT_C128 = 1, DT_BF16 = 2, DT_F16 = 3 };
+
+// Field pointers of the kernels that move 16-byte pieces must be 16-byte
+// aligned (every torch allocation is); others take the per-word kernels.
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 inline size_t dtype_bytes(int dt) { return dt == DT_C128 ? 16 : dt == DT_C64 ? 8 : 4; }
 inline int spinor_comps(int op) { return op == OP_STAGGERED ? 3 : 12; }

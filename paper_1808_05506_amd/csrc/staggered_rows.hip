@@ -582,6 +582,7 @@ static hipError_t staggered_march_nv(bool adj, int dtype, const Geom& g, int R, 
 hipError_t launch_staggered_rows(bool adj, int dtype, const Geom& g, const void* U, const void* in, void* out,
                                  double mass, hipStream_t st, bool compressed) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
+  if (!aligned16(U) || !aligned16(in) || !aligned16(out)) return hipErrorNotSupported;
   const int nv = g.nv;
   if (nv != 4 && nv != 8 && nv != 12 && nv != 16 && nv != 24) return hipErrorNotSupported;
   if (dtype != DT_C64 && dtype != DT_C128) return hipErrorNotSupported;

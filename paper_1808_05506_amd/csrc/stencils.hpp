@@ -194,13 +194,13 @@ DSL_HD void wilson_hop(const typename S::word* __restrict__ U, const typename S:
 //                                       + (1 + gamma_mu) V_mu(x-mu)^dag in(x-mu)]
 // ADJ: gamma_5 D_W gamma_5, i.e. gamma_mu -> -gamma_mu.  LW: words per stored
 // link (9, or 6 for compressed links).
-template <bool ADJ, class S, class T, int LW = 9>
+template <bool ADJ, class S, class T, int LW = 9, int NVC = 0>
 DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                         const typename S::word* __restrict__ C, uint32_t s, const SiteNbr& nb, int v, T diag) {
   constexpr int CF = ADJ ? +1 : -1;  // forward projector 1 + CF gamma
   constexpr int CB = -CF;            // backward projector 1 + CB gamma
-  const int nv = g.nv;
+  const int nv = NVC ? NVC : g.nv;   // NVC: N_v known at compile time
   const size_t sps = size_t(12) * nv;  // complex numbers per site of a spinor block
   cpx<T> acc[4][3];
 #pragma unroll
@@ -226,11 +226,11 @@ DSL_HD void wilson_site(const Geom& g, const typename S::word* __restrict__ U,
 
 // D_S (Sec. 3): out(x) = m in(x) + sum_mu eta_mu(x)/2 [V_mu(x) in(x+mu) - V_mu(x-mu)^dag in(x-mu)],
 // eta_1 = 1, eta_2 = (-1)^x, eta_3 = (-1)^(x+y), eta_4 = (-1)^(x+y+z).  ADJ negates the hop term.
-template <bool ADJ, class S, class T, int LW = 9>
+template <bool ADJ, class S, class T, int LW = 9, int NVC = 0>
 DSL_HD void staggered_site(const Geom& g, const typename S::word* __restrict__ U,
                            const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                            uint32_t s, const SiteNbr& nb, int v, T mass) {
-  const int nv = g.nv;
+  const int nv = NVC ? NVC : g.nv;  // NVC: N_v known at compile time
   const size_t sps = size_t(3) * nv;
   cpx<T> acc[3] = {zero<T>(), zero<T>(), zero<T>()};
   int par = 0;  // x_1 + ... + x_{mu-1}

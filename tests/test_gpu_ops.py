@@ -352,3 +352,56 @@ def test_brillouin_row_staged_path(kernel, adj, dims, monkeypatch):
     p = rounded(synthetic.wilson_spinor(dims, nv, 34), dt)
     out = D.apply("brillouin", up(w, dt), up(p, dt), 0.1, adjoint=adj)
     compare(down(out), brillouin.apply(w, p, 0.1, adj), dt, f"D_B {kernel}")
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128", "bf16", "f16"])
+@pytest.mark.parametrize("op", ["wilson", "staggered"])
+@pytest.mark.parametrize("compressed", [False, True])
+@pytest.mark.parametrize("adj", [False, True])
+def test_single_rhs_contiguous_loads(dt, op, compressed, adj):
+    # N_v = 1: a site's spinor and links are contiguous runs, which the
+    # N_v = 1 form of the direct kernels loads as 16-byte pieces (fields
+    # 16-byte aligned, as every torch allocation is)
+    if compressed and dt in ("bf16", "f16"):
+        pytest.skip("compressed links are stored in C64 and C128")
+    dims = (8, 6, 4, 6)
+    say(f"case single rhs {op} {dt} compressed={compressed} adj={adj}")
+    if op == "wilson":
+        u, p = _wil_fields(dims, 1, 93, 94, dt, "haar")
+    else:
+        u, p = _stag_fields(dims, 1, 93, 94, dt)
+    U, P = up(u, dt), up(p, dt)
+    mass = 0.1 if op == "wilson" else 0.2
+    if compressed:
+        ref = (wilson if op == "wilson" else staggered).apply(u, p, mass, adj)
+        out = D.apply_compressed(op, D.compress_links(U), P, mass, adjoint=adj)
+    else:
+        ref = (wilson if op == "wilson" else staggered).apply(u, p, mass, adj)
+        out = D.apply(op, U, P, mass, adjoint=adj)
+    compare(down(out), ref, dt, f"{op} N_v=1")
+
+
+@pytest.mark.parametrize("op", ["wilson", "staggered"])
+def test_fields_off_16_byte_alignment(op):
+    # a field that starts 8 bytes into an allocation takes the per-word
+    # kernels (the 16-byte forms require aligned fields) and gives the same
+    # result as the aligned field
+    dims, dt = (16, 4, 2, 4), "c64"
+    say(f"case misaligned fields {op}")
+    for nv in (1, 12):
+        if op == "wilson":
+            u, p = _wil_fields(dims, nv, 95, 96, dt, "haar")
+        else:
+            u, p = _stag_fields(dims, nv, 95, 96, dt)
+        U, P = up(u, dt), up(p, dt)
+        flatP = torch.empty(P.numel() + 1, dtype=P.dtype, device=P.device)
+        Pm = flatP[1:].view(P.shape)
+        Pm.copy_(P)
+        flatO = torch.empty_like(flatP)
+        Om = flatO[1:].view(P.shape)
+        assert Pm.data_ptr() % 16 == 8 and Om.data_ptr() % 16 == 8
+        aligned = D.apply(op, U, P, 0.1)
+        D.apply(op, U, Pm, 0.1, out=Om)
+        ref = (wilson if op == "wilson" else staggered).apply(u, p, 0.1)
+        compare(down(Om), ref, dt, f"{op} misaligned nv={nv}")
+        compare(down(aligned), ref, dt, f"{op} aligned nv={nv}")
