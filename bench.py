@@ -483,7 +483,9 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
         del U, C, P, sets
     torch.cuda.empty_cache()
     # Brillouin link gradient at 24^3 x 48, N_v = 12, FP32: with respect to the stored W
-    # (dslash_backward), then through the W construction to V (dslash_brillouin_links_backward)
+    # (dslash_backward), then through the W construction to V: by the first-hop recursion of
+    # the path averages (dslash_brillouin_links_backward_ws, the default) and by the sums over
+    # the orderings through W (dslash_brillouin_links_backward)
     V = up(synthetic.gauge_links(dims, "haar", 6), np.complex64)
     W = D.brillouin_links(V)
     C = up(synthetic.wilson_spinor(dims, 12, 104), np.complex64)
@@ -495,17 +497,26 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
         if lib.dslash_backward(2, vp(W), vp(C), vp(P), vp(gW), None, dims_c, 3, 12, 0.0, 0, stream):
             raise RuntimeError("dslash_backward failed")
 
+    nws = lib.dslash_brillouin_links_backward_workspace_bytes(dims_c, 3, 0)
+    ws = torch.empty(nws, dtype=torch.uint8, device=V.device)
+
     def vgrad(i):
+        if lib.dslash_brillouin_links_backward_ws(vp(V), vp(W), vp(gW), vp(gV), vp(ws), nws, dims_c, 3, 0, stream):
+            raise RuntimeError("dslash_brillouin_links_backward_ws failed")
+
+    def vgrad_subsets(i):
         if lib.dslash_brillouin_links_backward(vp(V), vp(W), vp(gW), vp(gV), dims_c, 3, 0, stream):
             raise RuntimeError("dslash_brillouin_links_backward failed")
     nsteps = max(3, steps // 20)
     bw = (2 * 12 * 12 * 8 + 360 * 8) * vol   # chi and psi read, G_W written
-    bv = (360 * 8 + 360 * 8 + 36 * 8) * vol   # W and G_W read, G_V written
+    bv = (360 * 8 + 360 * 8 + 36 * 8 + 36 * 8) * vol   # W, G_W and V read, G_V written
     rows["link_grad_brillouin_W_24^3x48_nv12_fp32"] = launch_row(torch, wgrad, nsteps, 1, bw, 1,
                                                                  "Brillouin link grad (W)", single=10)
     rows["brillouin_links_backward_24^3x48_fp32"] = launch_row(torch, vgrad, nsteps, 1, bv, 1,
-                                                               "Brillouin links backward (V)", single=10)
-    del V, W, C, P, gW, gV
+                                                               "Brillouin links backward (V), levels", single=10)
+    rows["brillouin_links_backward_subsets_24^3x48_fp32"] = launch_row(
+        torch, vgrad_subsets, nsteps, 1, bv, 1, "Brillouin links backward (V), sums over orderings", single=5)
+    del V, W, C, P, gW, gV, ws
     torch.cuda.empty_cache()
     rows.update(solve_rows_bench(torch, D, np, synthetic))
     return rows

@@ -155,6 +155,35 @@ int dslash_brillouin_links_backward(const void* V, const void* W, const void* gr
                                     int Nc, int dtype, void* stream);
 
 /*
+ * Workspace bytes dslash_brillouin_links_backward_ws needs: vol * 756
+ * complex words of dtype (grad_W and W, 360 words a site each, and V, 36, as
+ * structures of arrays); 0 on bad arguments.
+ */
+size_t dslash_brillouin_links_backward_workspace_bytes(const int dims[4], int Nc, int dtype);
+
+/*
+ * The gradient of dslash_brillouin_links_backward, computed through the
+ * recursion of the path averages by their first hop (Tab. 1):
+ *   W_d(x) = (1/k) sum_{mu: d_mu != 0} A(x) W_{d - d_mu mu}(x + d_mu mu),
+ * A = V_mu(x) for d_mu = +1, V_mu(x - mu)^dag for d_mu = -1, W_0 = 1.
+ * Reverse mode runs from the four-hop directions down: the total gradient of
+ * each stored direction with one to three hops (its grad_W entry plus what the
+ * directions with one more hop pass to it) goes to `workspace`, then every
+ * link gathers its share from the totals and the path averages in W.  The
+ * workspace holds these arrays with word e of slot j at [(j * 9 + e) * vol +
+ * site], so consecutive sites read consecutive words.  Same
+ * result as dslash_brillouin_links_backward up to rounding order, with about a
+ * fifth of the matrix products; deterministic (gathers in a fixed order, no
+ * atomics).  V, grad_W, grad_V as there; W: dslash_brillouin_links(V),
+ * required; workspace: device memory of ws_bytes >=
+ * dslash_brillouin_links_backward_workspace_bytes (else E_ARG), overwritten,
+ * owned by the caller, must not overlap any other argument (E_ALIAS).  C64
+ * and C128 only.  Asynchronous on `stream`.
+ */
+int dslash_brillouin_links_backward_ws(const void* V, const void* W, const void* grad_W, void* grad_V, void* workspace,
+                                       size_t ws_bytes, const int dims[4], int Nc, int dtype, void* stream);
+
+/*
  * out = D_B in (adjoint == 0) or D_B^dag in, with the off-axis links W_d(x)
  * built from the one-hop links V inside the kernel for every hop (Tab. 1; the
  * paper's variant without a precomputed W, Sec. 5): no W array is read or

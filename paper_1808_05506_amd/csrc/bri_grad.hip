@@ -447,6 +447,265 @@ __global__ void __launch_bounds__(128) bri_links_backward_w_kernel(Geom g, const
     for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
 }
 
+// ---------------------------------------------------------------- adjoint of the W construction by levels
+// Grouping the k! orderings of a path by their first hop gives the recursion
+//   W_d(x) = (1/k) sum_{mu: d_mu != 0} A_{s mu}(x) W_{d - s mu}(x + s mu),   s = d_mu,
+// with W_0 = 1 and A_{+mu}(x) = V_mu(x), A_{-mu}(x) = V_mu(x - mu)^dag (Tab. 1).
+// Reverse mode through it, from the four-hop directions down: the total
+// gradient T_e of a stored direction e (k hops) is its operator gradient plus
+// what the stored (k + 1)-hop directions pass down to it:
+//   d = e + s mu stored, at x = x' - s mu:   (1/(k+1)) A_{s mu}(x)^dag T_d(x)
+//   d = -e + s mu stored, at x = x' - d:     (1/(k+1)) T_d(x)^dag A_{s mu}(x)
+// (the second because d's sub-direction -e is not stored: W_{-e}(x' + e) =
+// W_e(x')^dag).  Then
+//   G_V(y, mu) = sum_{stored d, d_mu = +1} (1/k) T_d(y) W_{d - mu}(y + mu)^dag
+//              + sum_{stored d, d_mu = -1} [(1/k) T_d(y + mu) W_{d + mu}(y)^dag]^dag.
+// Every sum is a gather in a fixed order (deterministic, no atomics); about
+// 210 matrix products per site against about 1000 for the sums over orderings.
+
+namespace {
+
+// The workspace holds the totals, W and V as structures of arrays: word e of
+// slot j at site x sits at [(j * 9 + e) * vol + x], so the lanes of a wave
+// (consecutive sites) read consecutive words and the shifted gathers of the
+// recursion stay contiguous; the inputs' [site][slot][9] layout would put each
+// lane's matrix in other cache lines.
+
+// The stored slots j of one level k (number of non-zero components).
+struct LevelSlots {
+  int n;
+  int j[16];
+};
+
+constexpr int kSoaBlock = 256;
+
+// dst[w * vol + x] = src[x * wps + w] for the wps words of every site: a block
+// reads the contiguous words of its sites (16-byte loads, four in flight per
+// lane, when VEC) and writes runs of consecutive sites through LDS (row stride
+// wps + 1 words against bank conflicts).
+template <class S, bool VEC>
+__global__ void __launch_bounds__(kSoaBlock) bri_aos_to_soa_kernel(const typename S::word* __restrict__ src,
+                                                                   typename S::word* __restrict__ dst, uint32_t vol,
+                                                                   int wps, int sb) {
+  using W = typename S::word;
+  constexpr int WPC = VEC ? 16 / int(sizeof(W)) : 1;  // words a load
+  extern __shared__ unsigned char smem_soa[];
+  W* tile = reinterpret_cast<W*>(smem_soa);
+  const uint32_t x0 = blockIdx.x * uint32_t(sb);
+  const int ns = int(min(uint32_t(sb), vol - x0));
+  const int tid = int(threadIdx.x);
+  const W* in = src + size_t(x0) * wps;
+  const int nch = ns * wps / WPC;  // wps * sizeof(W) is a multiple of 16 when VEC
+  for (int t0 = 0; t0 < nch; t0 += 4 * kSoaBlock) {
+    W r[4][WPC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kSoaBlock + tid;
+      if (t < nch) {
+        if constexpr (VEC) {
+          const uint4 q = reinterpret_cast<const uint4*>(in)[t];
+          __builtin_memcpy(&r[u][0], &q, 16);
+        } else {
+          r[u][0] = in[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kSoaBlock + tid;
+      if (t < nch) {
+#pragma unroll
+        for (int h = 0; h < WPC; ++h) {
+          const int wi = t * WPC + h, xl = wi / wps, w = wi - xl * wps;
+          tile[xl * (wps + 1) + w] = r[u][h];
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int t = tid; t < sb * wps; t += kSoaBlock) {
+    const int w = t / sb, xl = t - w * sb;
+    if (xl < ns) dst[size_t(w) * vol + x0 + xl] = tile[xl * (wps + 1) + w];
+  }
+}
+
+template <class S, class T>
+__device__ __forceinline__ void soa_load(const typename S::word* __restrict__ p, uint32_t vol, uint32_t x,
+                                         cpx<T> (&m)[3][3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[r][c] = S::template load<T>(p + size_t(r * 3 + c) * vol + x);
+}
+
+template <class T>
+__device__ __forceinline__ void dagger_in_place(cpx<T> (&m)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m[a][a] = conj(m[a][a]);
+#pragma unroll
+    for (int b = a + 1; b < 3; ++b) {
+      const cpx<T> u = m[a][b], v = m[b][a];
+      m[a][b] = conj(v);
+      m[b][a] = conj(u);
+    }
+  }
+}
+
+// A_{s mu}(x): V_mu(x) for s = +1, V_mu(x - mu)^dag for s = -1 (Vs: V as
+// structure of arrays, word mu * 9 + e)
+template <class S, class T>
+__device__ __forceinline__ void hop_link(const Geom& g, const typename S::word* __restrict__ Vs, const int (&x)[4],
+                                         int mu, int s, cpx<T> (&a)[3][3]) {
+  int p[4] = {x[0], x[1], x[2], x[3]};
+  if (s < 0) p[mu] = wrap(p[mu] - 1, g.n[mu]);
+  soa_load<S, T>(Vs + size_t(mu) * 9 * g.vol, g.vol, site_of(g, p), a);
+  if (s < 0) dagger_in_place(a);
+}
+
+// W_{dd}(x) for any dd != 0 from W as structure of arrays (stored, or
+// W_{-dd}(x + dd)^dag), 1 for dd = 0
+template <class S, class T>
+__device__ __forceinline__ void soa_w_any(const Geom& g, const typename S::word* __restrict__ Ws, const int (&x)[4],
+                                          const int (&dd)[4], cpx<T> (&w)[3][3]) {
+  const int n = (dd[0] + 1) + 3 * (dd[1] + 1) + 9 * (dd[2] + 1) + 27 * (dd[3] + 1);
+  if (n == 40) {
+    m3_identity(w);
+  } else if (n > 40) {
+    soa_load<S, T>(Ws + size_t(n - 41) * 9 * g.vol, g.vol, site_of(g, x), w);
+  } else {
+    int y[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) y[mu] = wrap(x[mu] + dd[mu], g.n[mu]);
+    soa_load<S, T>(Ws + size_t(39 - n) * 9 * g.vol, g.vol, site_of(g, y), w);
+    dagger_in_place(w);
+  }
+}
+
+DSL_HD int dir_code(const int (&d)[4]) { return (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1) + 27 * (d[3] + 1); }
+
+// T_e for the stored directions of level L < 4 (thread per (site, slot of
+// the level)), in place in Ts: the slot starts as grad_W and receives the
+// level-(L + 1) totals, which no thread of this launch writes.
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_wlevel_kernel(Geom g, LevelSlots ls, int L,
+                                                         const typename S::word* __restrict__ Vs,
+                                                         typename S::word* Ts) {
+  const uint32_t xs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (xs >= g.vol || int(blockIdx.y) >= ls.n) return;
+  const int jt = ls.j[blockIdx.y];  // uniform over the block
+  const uint32_t vol = g.vol;
+  int e[4];
+  stored_direction(jt, e);
+  const SiteNbr nb = site_nbr(g, xs);
+  const int xp[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+  const T w = T(1) / T(L + 1);
+  cpx<T> h[3][3];
+  soa_load<S, T>(Ts + size_t(jt) * 9 * vol, vol, xs, h);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    if (e[mu] != 0) continue;
+#pragma unroll 1
+    for (int s = 1; s >= -1; s -= 2) {
+      cpx<T> a[3][3], tm[3][3], r[3][3];
+      int d[4] = {e[0], e[1], e[2], e[3]};
+      d[mu] = s;
+      int n = dir_code(d);
+      if (n > 40) {  // d = e + s mu stored, at x = x' - s mu
+        int x[4] = {xp[0], xp[1], xp[2], xp[3]};
+        x[mu] = wrap(x[mu] - s, g.n[mu]);
+        hop_link<S, T>(g, Vs, x, mu, s, a);
+        soa_load<S, T>(Ts + size_t(n - 41) * 9 * vol, vol, site_of(g, x), tm);
+        m3_adj_mul(a, tm, r);  // A^dag T_d
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) h[i][c] = rmadd(h[i][c], w, r[i][c]);
+      }
+#pragma unroll
+      for (int nu = 0; nu < 4; ++nu) d[nu] = nu == mu ? s : -e[nu];
+      n = dir_code(d);
+      if (n > 40) {  // d = -e + s mu stored, at x = x' - d
+        int x[4];
+#pragma unroll
+        for (int nu = 0; nu < 4; ++nu) x[nu] = wrap(xp[nu] - d[nu], g.n[nu]);
+        hop_link<S, T>(g, Vs, x, mu, s, a);
+        soa_load<S, T>(Ts + size_t(n - 41) * 9 * vol, vol, site_of(g, x), tm);
+        m3_adj_mul(tm, a, r);  // T_d^dag A
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) h[i][c] = rmadd(h[i][c], w, r[i][c]);
+      }
+    }
+  }
+  typename S::word* o = Ts + size_t(jt) * 9 * vol + xs;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + size_t(i * 3 + c) * vol, h[i][c]);
+}
+
+// G_V from the totals Ts (all 40 slots) and W as structure of arrays
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_wlevel_gv_kernel(Geom g, const typename S::word* __restrict__ Ws,
+                                                            const typename S::word* __restrict__ Ts,
+                                                            typename S::word* __restrict__ GV) {
+  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = int(blockIdx.y);  // uniform over the block
+  if (y >= g.vol) return;
+  const uint32_t vol = g.vol;
+  const SiteNbr nb = site_nbr(g, y);
+  const int yc[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+  int yp[4] = {yc[0], yc[1], yc[2], yc[3]};
+  yp[mu] = wrap(yp[mu] + 1, g.n[mu]);
+  const uint32_t syp = site_of(g, yp);
+  cpx<T> acc[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = zero<T>();
+#pragma unroll 1
+  for (int j = 0; j < 40; ++j) {
+    int d[4];
+    stored_direction(j, d);
+    const int s = d[mu];
+    if (s == 0) continue;  // uniform: j and mu are the same for the whole wave
+    const int k = (d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0);
+    const T w = T(1) / T(k);
+    cpx<T> tm[3][3], ws[3][3], r[3][3];
+    int sub[4] = {d[0], d[1], d[2], d[3]};
+    sub[mu] = 0;
+    if (s > 0) {
+      // A = V_mu(y), the rest of the path from y + mu
+      soa_load<S, T>(Ts + size_t(j) * 9 * vol, vol, y, tm);
+      soa_w_any<S, T>(g, Ws, yp, sub, ws);
+      m3_mul_adj(tm, ws, r);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = rmadd(acc[i][c], w, r[i][c]);
+    } else {
+      // A = V_mu(y)^dag as the first hop from y + mu, the rest from y
+      soa_load<S, T>(Ts + size_t(j) * 9 * vol, vol, syp, tm);
+      soa_w_any<S, T>(g, Ws, yc, sub, ws);
+      m3_mul_adj(tm, ws, r);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = rmadd(acc[i][c], w, conj(r[c][i]));
+    }
+  }
+  typename S::word* o = GV + (size_t(y) * 4 + mu) * 9;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
+}
+
+}  // namespace
+
 namespace {
 
 template <class S, class T>
@@ -481,6 +740,59 @@ hipError_t launch_brillouin_wgrad(int dtype, const Geom& g, const void* chi, con
   switch (dtype) {
     case DT_C64: return wgrad_t<C64, float>(g, chi, psi, GW, st);
     case DT_C128: return wgrad_t<C128, double>(g, chi, psi, GW, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <class S, class T>
+hipError_t links_backward_levels_t(const Geom& g, const void* V, const void* Wl, const void* GW, void* GV, void* ws,
+                                   hipStream_t st) {
+  using W = typename S::word;
+  const uint32_t vol = g.vol;
+  W* Ts = (W*)ws;                      // totals, 40 slots
+  W* Ws = Ts + size_t(360) * vol;      // W, 40 slots
+  W* Vs = Ws + size_t(360) * vol;      // V, 4 links
+  // G_W, W and V as structures of arrays
+  const int tile_words = 5760 * 8 / int(sizeof(W));
+  const struct { const void* src; W* dst; int wps; } cp[3] = {{GW, Ts, 360}, {Wl, Ws, 360}, {V, Vs, 36}};
+  for (const auto& c : cp) {
+    const int sb = tile_words / c.wps;
+    const size_t lds = size_t(sb) * (c.wps + 1) * sizeof(W);
+    if (aligned16(c.src))
+      hipLaunchKernelGGL((bri_aos_to_soa_kernel<S, true>), dim3((vol + sb - 1) / sb), dim3(kSoaBlock), lds, st,
+                         (const W*)c.src, c.dst, vol, c.wps, sb);
+    else
+      hipLaunchKernelGGL((bri_aos_to_soa_kernel<S, false>), dim3((vol + sb - 1) / sb), dim3(kSoaBlock), lds, st,
+                         (const W*)c.src, c.dst, vol, c.wps, sb);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  const uint32_t blocks = (vol + 127) / 128;
+  // levels 3, 2, 1: each adds what the level above passes down to its slots
+  for (int L = 3; L >= 1; --L) {
+    LevelSlots ls{};
+    for (int j = 0; j < 40; ++j) {
+      int d[4];
+      stored_direction(j, d);
+      if ((d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0) == L) ls.j[ls.n++] = j;
+    }
+    hipLaunchKernelGGL((bri_wlevel_kernel<S, T>), dim3(blocks, uint32_t(ls.n)), dim3(128), 0, st, g, ls, L,
+                       (const W*)Vs, Ts);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  hipLaunchKernelGGL((bri_wlevel_gv_kernel<S, T>), dim3(blocks, 4), dim3(128), 0, st, g, (const W*)Ws, (const W*)Ts,
+                     (W*)GV);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_brillouin_links_backward_levels(int dtype, const Geom& g, const void* V, const void* W,
+                                                  const void* GW, void* GV, void* Tw, hipStream_t st) {
+  switch (dtype) {
+    case DT_C64: return links_backward_levels_t<C64, float>(g, V, W, GW, GV, Tw, st);
+    case DT_C128: return links_backward_levels_t<C128, double>(g, V, W, GW, GV, Tw, st);
   }
   return hipErrorInvalidValue;
 }

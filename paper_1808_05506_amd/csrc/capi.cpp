@@ -237,6 +237,37 @@ int dslash_brillouin_links_backward(const void* V, const void* W, const void* gr
   return DSLASH_OK;
 }
 
+size_t dslash_brillouin_links_backward_workspace_bytes(const int dims[4], int Nc, int dtype) {
+  if (check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return 0;
+  if (dtype != DSLASH_C64 && dtype != DSLASH_C128) return 0;
+  return size_t(volume(dims)) * 756 * dsl::dtype_bytes(dtype);
+}
+
+int dslash_brillouin_links_backward_ws(const void* V, const void* W, const void* grad_W, void* grad_V, void* workspace,
+                                       size_t ws_bytes, const int dims[4], int Nc, int dtype, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return rc;
+  if (dtype != DSLASH_C64 && dtype != DSLASH_C128)
+    return fail(DSLASH_E_UNSUPPORTED, "W construction is built for C64 and C128 only (got dtype %d)", dtype);
+  if (!V || !W || !grad_W || !grad_V) return fail(DSLASH_E_ARG, "NULL field pointer");
+  if (!workspace) return fail(DSLASH_E_ARG, "NULL workspace");
+  const uint64_t vol = volume(dims);
+  const size_t eb = dsl::dtype_bytes(dtype);
+  const size_t nv = size_t(vol) * 36 * eb, nw = size_t(vol) * 360 * eb;
+  const size_t nws = size_t(vol) * 756 * eb;
+  if (ws_bytes < nws) return fail(DSLASH_E_ARG, "workspace of %zu bytes, %zu needed", ws_bytes, nws);
+  if (overlap(grad_V, nv, V, nv) || overlap(grad_V, nv, grad_W, nw) || overlap(grad_V, nv, W, nw))
+    return fail(DSLASH_E_ALIAS, "grad_V overlaps an input");
+  if (overlap(workspace, nws, V, nv) || overlap(workspace, nws, W, nw) || overlap(workspace, nws, grad_W, nw) ||
+      overlap(workspace, nws, grad_V, nv))
+    return fail(DSLASH_E_ALIAS, "workspace overlaps another argument");
+  const dsl::Geom g = dsl::make_geom(dims, 1);
+  hipError_t e =
+      dsl::launch_brillouin_links_backward_levels(dtype, g, V, W, grad_W, grad_V, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "dslash_brillouin_links_backward_ws launch");
+  return DSLASH_OK;
+}
+
 int dslash_brillouin_links(const void* V, void* W, const int dims[4], int Nc, int dtype, void* stream) {
   g_err[0] = 0;
   if (int rc = check_geom(DSLASH_BRILLOUIN, dims, Nc, 1)) return rc;

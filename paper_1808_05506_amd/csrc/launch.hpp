@@ -99,6 +99,9 @@ hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi
 // path averages of W instead of walking every ordering through V
 hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* W, const void* GW,
                                            void* GV, hipStream_t st);
+// The same through the level recursion of the path averages; ws: 756 words a site.
+hipError_t launch_brillouin_links_backward_levels(int dtype, const Geom& g, const void* V, const void* W,
+                                                  const void* GW, void* GV, void* ws, hipStream_t st);
 hipError_t launch_link_grad(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,
                             hipStream_t st);
 hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, const void* psi, void* G,

@@ -68,6 +68,9 @@ def _load():
     lib.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     lib.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, vp, ip, i, i, vp]
+    lib.dslash_brillouin_links_backward_workspace_bytes.argtypes = [ip, i, i]
+    lib.dslash_brillouin_links_backward_workspace_bytes.restype = sz
+    lib.dslash_brillouin_links_backward_ws.argtypes = [vp, vp, vp, vp, vp, sz, ip, i, i, vp]
     lib.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     lib.dslash_status_string.restype = ctypes.c_char_p
     lib.dslash_last_error.restype = ctypes.c_char_p
@@ -75,7 +78,7 @@ def _load():
                  "dslash_convert", "dslash_solve", "dslash_solve_op", "dslash_version", "dslash_eo_pack",
                  "dslash_eo_unpack", "dslash_eo_hop", "dslash_solve_eo", "dslash_clover_field", "dslash_apply_clover",
                  "dslash_compress_links", "dslash_apply_compressed", "dslash_brillouin_links_backward", "dslash_apply_brillouin_fly",
-                 "dslash_reload_tuning"):
+                 "dslash_reload_tuning", "dslash_brillouin_links_backward_ws"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -308,10 +311,20 @@ def brillouin_links(V: torch.Tensor) -> torch.Tensor:
     return W
 
 
-def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Tensor | None = None) -> torch.Tensor:
+def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Tensor | None = None,
+                             method: str | None = None) -> torch.Tensor:
     """Gradient with respect to V of Re sum conj(grad_W) W[V] (adjoint of ``brillouin_links``).
-    W: optional ``brillouin_links(V)``; with it the adjoint sums the orderings
-    of each path through the path averages of W (faster)."""
+    W: optional ``brillouin_links(V)``.  method: "walk" walks every hop
+    ordering through V (the only one without W); "subsets" sums the orderings
+    of each path through the path averages of W; "levels" (the default with W)
+    runs the first-hop recursion of the path averages backwards through a
+    grad_W-sized workspace."""
+    if method is None:
+        method = "walk" if W is None else "levels"
+    if method not in ("walk", "subsets", "levels"):
+        raise ValueError(f"method must be 'walk', 'subsets' or 'levels', got {method!r}")
+    if (W is None) != (method == "walk"):
+        raise ValueError(f"method {method!r} {'takes no' if method == 'walk' else 'needs'} W")
     _require(V, "V")
     _require(grad_W, "grad_W")
     vs = _core_shape(V)
@@ -324,8 +337,18 @@ def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Ten
         if W.shape != grad_W.shape or W.dtype != V.dtype or W.device != V.device:
             raise ValueError("W must be brillouin_links(V): [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
     gV = torch.empty_like(V)
+    dims, code = _dims_c(vs), _dtype_code(V)
+    if method == "levels":
+        nbytes = _lib.dslash_brillouin_links_backward_workspace_bytes(dims, 3, code)
+        if nbytes == 0:
+            raise DslashError(f"dslash_brillouin_links_backward_workspace_bytes rejected dims {vs[:4]}")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=V.device)
+        _check(_lib.dslash_brillouin_links_backward_ws(_ptr(V), _ptr(W), _ptr(grad_W), _ptr(gV), _ptr(ws), nbytes,
+                                                       dims, 3, code, _stream(V)),
+               "dslash_brillouin_links_backward_ws")
+        return gV
     _check(_lib.dslash_brillouin_links_backward(_ptr(V), _ptr(W) if W is not None else None, _ptr(grad_W), _ptr(gV),
-                                                _dims_c(vs), 3, _dtype_code(V), _stream(V)),
+                                                dims, 3, code, _stream(V)),
            "dslash_brillouin_links_backward")
     return gV
 

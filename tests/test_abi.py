@@ -44,6 +44,9 @@ def lib():
     l.dslash_compress_links.argtypes = [vp, vp, ip, i, i, vp]
     l.dslash_apply_compressed.argtypes = [i, vp, vp, vp, ip, i, i, d, i, i, vp]
     l.dslash_brillouin_links_backward.argtypes = [vp, vp, vp, vp, ip, i, i, vp]
+    l.dslash_brillouin_links_backward_workspace_bytes.argtypes = [ip, i, i]
+    l.dslash_brillouin_links_backward_workspace_bytes.restype = sz
+    l.dslash_brillouin_links_backward_ws.argtypes = [vp, vp, vp, vp, vp, sz, ip, i, i, vp]
     l.dslash_apply_brillouin_fly.argtypes = [vp, vp, vp, ip, i, i, d, i, i, vp]
     return l
 
@@ -55,7 +58,7 @@ def _dims(*d):
 def test_exports_every_declared_symbol(lib):
     text = open(HEADER).read()
     declared = set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(dslash_\w+)\s*\(", text, re.M))
-    assert len(declared) == 25
+    assert len(declared) == 27
     for name in declared:
         assert hasattr(lib, name), name
     assert lib.dslash_version() == 201
@@ -229,6 +232,28 @@ def test_brillouin_links_backward_validation(lib):
     assert lib.dslash_brillouin_links_backward(A, D, B, D, dims, 3, 0, None) == 3         # grad_V == W
     assert lib.dslash_brillouin_links_backward(A, None, B, C, dims, 3, 2, None) == 2      # BF16
     assert lib.dslash_brillouin_links_backward(A, None, B, C, dims, 2, 0, None) == 2      # Nc != 3
+
+
+def test_brillouin_links_backward_ws_validation(lib):
+    dims = _dims(4, 4, 4, 4)
+    D, E = 0x20000000, 0x30000000
+    nw = lib.dslash_brillouin_links_backward_workspace_bytes(dims, 3, 0)
+    assert nw == 256 * 756 * 8                    # grad_W, W (360 words a site each) and V (36), C64
+    assert lib.dslash_brillouin_links_backward_workspace_bytes(dims, 3, 1) == 2 * nw   # C128
+    assert lib.dslash_brillouin_links_backward_workspace_bytes(dims, 3, 2) == 0        # BF16
+    assert lib.dslash_brillouin_links_backward_workspace_bytes(dims, 2, 0) == 0        # Nc != 3
+    assert lib.dslash_brillouin_links_backward_workspace_bytes(_dims(4, 4, 0, 4), 3, 0) == 0
+    ws = lib.dslash_brillouin_links_backward_ws
+    assert ws(A, None, B, C, E, nw, dims, 3, 0, None) == 1          # W is required
+    assert ws(A, D, B, C, None, nw, dims, 3, 0, None) == 1          # NULL workspace
+    assert ws(A, D, B, C, E, nw - 1, dims, 3, 0, None) == 1         # workspace too small
+    assert ws(A, D, B, A, E, nw, dims, 3, 0, None) == 3             # grad_V == V
+    assert ws(A, D, B, D, E, nw, dims, 3, 0, None) == 3             # grad_V == W
+    assert ws(A, D, B, C, B, nw, dims, 3, 0, None) == 3             # workspace == grad_W
+    assert ws(A, D, B, C, D + 8, nw, dims, 3, 0, None) == 3         # workspace overlaps W
+    assert ws(A, D, B, C, C - 8, nw, dims, 3, 0, None) == 3         # workspace runs into grad_V
+    assert ws(A, D, B, C, E, nw, dims, 3, 2, None) == 2             # BF16
+    assert ws(A, D, B, C, E, nw, dims, 2, 0, None) == 2             # Nc != 3
 
 
 def test_brillouin_fly_validation(lib):

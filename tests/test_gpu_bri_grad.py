@@ -52,20 +52,43 @@ def test_wgrad_rows_matches_oracle(dims, monkeypatch):
     compare(down(gW), ref, dt, "G_W rows")
 
 
-@pytest.mark.parametrize("with_w", [False, True])
+@pytest.mark.parametrize("method", ["walk", "subsets", "levels"])
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("dims", [(3, 3, 2, 3), (4, 3, 3, 5), (5, 4, 3, 4)])
-def test_links_backward_matches_oracle(dt, dims, with_w):
-    # without W every hop ordering is walked through V; with W the orderings
-    # that share the hops before and after the link are summed through the
-    # path averages of W
-    say(f"case brillouin links backward {dims} {dt} with_w={with_w}")
+def test_links_backward_matches_oracle(dt, dims, method):
+    # walk: every hop ordering through V; subsets: the orderings that share
+    # the hops before and after the link summed through the path averages of
+    # W; levels: the first-hop recursion of the path averages run backwards
+    say(f"case brillouin links backward {dims} {dt} method={method}")
     v = synthetic.gauge_links(dims, "haar", 120)
     gw = synthetic.gaussian(v.shape[:4] + (40, 3, 3), 121)
     V, GW = up(v, dt), up(gw, dt)
-    gV = D.brillouin_links_backward(V, GW, D.brillouin_links(V) if with_w else None)
+    W = None if method == "walk" else D.brillouin_links(V)
+    gV = D.brillouin_links_backward(V, GW, W, method=method)
     ref = grad.brillouin_links_backward(down(V), down(GW))
     compare(down(gV), ref, dt, "G_V from G_W")
+
+
+def test_links_backward_levels_off_16_byte_alignment():
+    # fields 8 bytes off a 16-byte boundary take the per-word transposition
+    # into the workspace: the same arithmetic, so the same bits
+    dims = (4, 3, 3, 5)
+    say("case brillouin links backward levels, misaligned fields")
+    v = synthetic.gauge_links(dims, "haar", 122)
+    gw = synthetic.gaussian(v.shape[:4] + (40, 3, 3), 123)
+    V, GW = up(v, "c64"), up(gw, "c64")
+    W = D.brillouin_links(V)
+
+    def off(t):
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        o = buf[1:].view(t.shape)
+        o.copy_(t)
+        return o
+
+    a = D.brillouin_links_backward(V, GW, W, method="levels")
+    b = D.brillouin_links_backward(off(V), off(GW), off(W), method="levels")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
 
 
 def test_link_gradient_wrt_V_end_to_end():
@@ -101,6 +124,7 @@ def test_brillouin_gradients_deterministic():
     ga = D.brillouin_links_backward(V, a)
     gb = D.brillouin_links_backward(V, a)
     assert torch.equal(ga, gb)
-    ga = D.brillouin_links_backward(V, a, W)
-    gb = D.brillouin_links_backward(V, a, W)
-    assert torch.equal(ga, gb)
+    for method in ("subsets", "levels"):
+        ga = D.brillouin_links_backward(V, a, W, method=method)
+        gb = D.brillouin_links_backward(V, a, W, method=method)
+        assert torch.equal(ga, gb), method
