@@ -583,6 +583,16 @@ __device__ __forceinline__ void soa_w_any(const Geom& g, const typename S::word*
   }
 }
 
+// blockIdx.x -> (unit u in [0, n), site block sb in [0, nsb8)), nsb8 the
+// number of site blocks rounded up to a multiple of 8.  Workgroups go to the
+// eight XCDs in turn, so the n units of one site block are placed on the same
+// XCD one after another and share its L2 (the neighbours they gather).
+DSL_HD void xcd_units(uint32_t b, int n, uint32_t& u, uint32_t& sb) {
+  const uint32_t xcd = b & 7u, q = b >> 3;
+  u = q % uint32_t(n);
+  sb = (q / uint32_t(n)) * 8u + xcd;
+}
+
 DSL_HD int dir_code(const int (&d)[4]) { return (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1) + 27 * (d[3] + 1); }
 
 // T_e for the stored directions of level L < 4 (thread per (site, slot of
@@ -592,9 +602,11 @@ template <class S, class T>
 __global__ void __launch_bounds__(128) bri_wlevel_kernel(Geom g, LevelSlots ls, int L,
                                                          const typename S::word* __restrict__ Vs,
                                                          typename S::word* Ts) {
-  const uint32_t xs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (xs >= g.vol || int(blockIdx.y) >= ls.n) return;
-  const int jt = ls.j[blockIdx.y];  // uniform over the block
+  uint32_t u, sbk;
+  xcd_units(blockIdx.x, ls.n, u, sbk);
+  const uint32_t xs = sbk * blockDim.x + threadIdx.x;
+  if (xs >= g.vol) return;
+  const int jt = ls.j[u];  // uniform over the block
   const uint32_t vol = g.vol;
   int e[4];
   stored_direction(jt, e);
@@ -652,8 +664,10 @@ template <class S, class T>
 __global__ void __launch_bounds__(128) bri_wlevel_gv_kernel(Geom g, const typename S::word* __restrict__ Ws,
                                                             const typename S::word* __restrict__ Ts,
                                                             typename S::word* __restrict__ GV) {
-  const uint32_t y = blockIdx.x * blockDim.x + threadIdx.x;
-  const int mu = int(blockIdx.y);  // uniform over the block
+  uint32_t u, sbk;
+  xcd_units(blockIdx.x, 4, u, sbk);
+  const uint32_t y = sbk * blockDim.x + threadIdx.x;
+  const int mu = int(u);  // uniform over the block
   if (y >= g.vol) return;
   const uint32_t vol = g.vol;
   const SiteNbr nb = site_nbr(g, y);
@@ -768,7 +782,7 @@ hipError_t links_backward_levels_t(const Geom& g, const void* V, const void* Wl,
                          (const W*)c.src, c.dst, vol, c.wps, sb);
     if (hipError_t e = hipGetLastError()) return e;
   }
-  const uint32_t blocks = (vol + 127) / 128;
+  const uint32_t blocks8 = ((vol + 127) / 128 + 7) / 8 * 8;
   // levels 3, 2, 1: each adds what the level above passes down to its slots
   for (int L = 3; L >= 1; --L) {
     LevelSlots ls{};
@@ -777,11 +791,11 @@ hipError_t links_backward_levels_t(const Geom& g, const void* V, const void* Wl,
       stored_direction(j, d);
       if ((d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0) == L) ls.j[ls.n++] = j;
     }
-    hipLaunchKernelGGL((bri_wlevel_kernel<S, T>), dim3(blocks, uint32_t(ls.n)), dim3(128), 0, st, g, ls, L,
+    hipLaunchKernelGGL((bri_wlevel_kernel<S, T>), dim3(blocks8 * uint32_t(ls.n)), dim3(128), 0, st, g, ls, L,
                        (const W*)Vs, Ts);
     if (hipError_t e = hipGetLastError()) return e;
   }
-  hipLaunchKernelGGL((bri_wlevel_gv_kernel<S, T>), dim3(blocks, 4), dim3(128), 0, st, g, (const W*)Ws, (const W*)Ts,
+  hipLaunchKernelGGL((bri_wlevel_gv_kernel<S, T>), dim3(blocks8 * 4), dim3(128), 0, st, g, (const W*)Ws, (const W*)Ts,
                      (W*)GV);
   return hipGetLastError();
 }
