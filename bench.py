@@ -514,6 +514,14 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
                                                                  "Brillouin link grad (W)", single=10)
     rows["brillouin_links_backward_24^3x48_fp32"] = launch_row(torch, vgrad, nsteps, 1, bv, 1,
                                                                "Brillouin links backward (V), levels", single=10)
+    Wb = torch.empty_like(W)
+
+    def wbuild(i):
+        if lib.dslash_brillouin_links(vp(V), vp(Wb), dims_c, 3, 0, stream):
+            raise RuntimeError("dslash_brillouin_links failed")
+    rows["brillouin_links_24^3x48_fp32"] = launch_row(torch, wbuild, nsteps, 1, (36 + 360) * 8 * vol, 1,
+                                                      "Brillouin W construction", single=10)
+    del Wb
     rows["brillouin_links_backward_subsets_24^3x48_fp32"] = launch_row(
         torch, vgrad_subsets, nsteps, 1, bv, 1, "Brillouin links backward (V), sums over orderings", single=5)
     del V, W, C, P, gW, gV, ws

@@ -245,7 +245,10 @@ int dslash_backward(int op, const void* U, const void* grad_out, const void* in,
  * with k non-zero components, W_d(x) = (1/k!) sum over the k! orderings of
  * the hops of the ordered product of V along the path from x, with
  * V_{-mu}(y) = V_mu(y - mu)^dag.  V [..][4][Nc][Nc] -> W [..][40][Nc][Nc].
- * C64 or C128.  V == W -> E_ALIAS.
+ * Built level by level from the same mean grouped by the first hop,
+ * W_d(x) = (1/k) sum_{mu: d_mu != 0} V_{d_mu mu}(x) W_{d - d_mu mu}(x + d_mu mu),
+ * each level reading the one below from W (k products for a k-hop direction).
+ * C64 or C128.  V and W must not overlap (E_ALIAS).
  */
 int dslash_brillouin_links(const void* V, void* W, const int dims[4], int Nc, int dtype, void* stream);
 

@@ -718,6 +718,63 @@ __global__ void __launch_bounds__(128) bri_wlevel_gv_kernel(Geom g, const typena
     for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, acc[r][c]);
 }
 
+// ---------------------------------------------------------------- W by levels
+// The same first-hop recursion builds W (Tab. 1) level by level: the stored
+// directions with k hops read those with k - 1 hops, stored or as the adjoint
+// of a stored one at the shifted site, from W itself (one launch per level),
+// so a k-hop direction costs k products instead of k! (k - 1) for the walks
+// over every ordering.  Level 1 is V_mu itself.
+template <class S, class T>
+__global__ void __launch_bounds__(128) bri_links_level_kernel(Geom g, LevelSlots ls, int L,
+                                                              const typename S::word* __restrict__ V,
+                                                              typename S::word* W) {
+  uint32_t u, sbk;
+  xcd_units(blockIdx.x, ls.n, u, sbk);
+  const uint32_t xs = sbk * blockDim.x + threadIdx.x;
+  if (xs >= g.vol) return;
+  const int jt = ls.j[u];  // uniform over the block
+  int d[4];
+  stored_direction(jt, d);
+  const SiteNbr nb = site_nbr(g, xs);
+  const int x[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
+  cpx<T> acc[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = zero<T>();
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int s = d[mu];
+    if (s == 0) continue;  // uniform over the block
+    // A_{s mu}(x); walk_hop leaves p at x + s mu, where the rest of the path starts
+    int p[4] = {x[0], x[1], x[2], x[3]};
+    cpx<T> a[3][3];
+    walk_hop<S, T>(g, V, p, mu, s, a);
+    if (L == 1) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][c] = acc[r][c] + a[r][c];
+    } else {
+      int sub[4] = {d[0], d[1], d[2], d[3]};
+      sub[mu] = 0;
+      cpx<T> w[3][3], r3[3][3];
+      load_w_any<S, T>(g, W, p, sub, w);
+      m3_mul(a, w, r3);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][c] = acc[r][c] + r3[r][c];
+    }
+  }
+  const T inv = T(1) / T(L);
+  typename S::word* o = W + (size_t(xs) * 40 + jt) * 9;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S::template store<T>(o + r * 3 + c, inv * acc[r][c]);
+}
+
 }  // namespace
 
 namespace {
@@ -801,6 +858,36 @@ hipError_t links_backward_levels_t(const Geom& g, const void* V, const void* Wl,
 }
 
 }  // namespace
+
+namespace {
+
+template <class S, class T>
+hipError_t links_levels_t(const Geom& g, const void* V, void* Wout, hipStream_t st) {
+  using W = typename S::word;
+  const uint32_t blocks8 = ((g.vol + 127) / 128 + 7) / 8 * 8;
+  for (int L = 1; L <= 4; ++L) {
+    LevelSlots ls{};
+    for (int j = 0; j < 40; ++j) {
+      int d[4];
+      stored_direction(j, d);
+      if ((d[0] != 0) + (d[1] != 0) + (d[2] != 0) + (d[3] != 0) == L) ls.j[ls.n++] = j;
+    }
+    hipLaunchKernelGGL((bri_links_level_kernel<S, T>), dim3(blocks8 * uint32_t(ls.n)), dim3(128), 0, st, g, ls, L,
+                       (const W*)V, (W*)Wout);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_brillouin_links_levels(int dtype, const Geom& g, const void* V, void* W, hipStream_t st) {
+  switch (dtype) {
+    case DT_C64: return links_levels_t<C64, float>(g, V, W, st);
+    case DT_C128: return links_levels_t<C128, double>(g, V, W, st);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_brillouin_links_backward_levels(int dtype, const Geom& g, const void* V, const void* W,
                                                   const void* GW, void* GV, void* Tw, hipStream_t st) {

@@ -99,6 +99,8 @@ hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi
 // path averages of W instead of walking every ordering through V
 hipError_t launch_brillouin_links_backward(int dtype, const Geom& g, const void* V, const void* W, const void* GW,
                                            void* GV, hipStream_t st);
+// W built level by level from the first-hop recursion of the path averages.
+hipError_t launch_brillouin_links_levels(int dtype, const Geom& g, const void* V, void* W, hipStream_t st);
 // The same through the level recursion of the path averages; ws: 756 words a site.
 hipError_t launch_brillouin_links_backward_levels(int dtype, const Geom& g, const void* V, const void* W,
                                                   const void* GW, void* GV, void* ws, hipStream_t st);

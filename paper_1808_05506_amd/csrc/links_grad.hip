@@ -5,25 +5,10 @@
 namespace dsl {
 
 // ---------------------------------------------------------------- W build
-// grid.y = stored direction slot j, so every wave follows the same path list.
-template <class S, class T>
-__global__ void __launch_bounds__(256) brillouin_links_kernel(Geom g, const typename S::word* __restrict__ V,
-                                                              typename S::word* __restrict__ W) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.vol) return;
-  brillouin_link_site<S, T>(g, V, W, s, int(blockIdx.y));
-}
-
+// Level by level through the first-hop recursion of the path averages (the
+// kernels sit with the adjoint of the same recursion).
 hipError_t launch_brillouin_links(int dtype, const Geom& g, const void* V, void* W, hipStream_t st) {
-  const dim3 block(256), grid((g.vol + 255) / 256, 40);
-  if (dtype == DT_C64)
-    hipLaunchKernelGGL((brillouin_links_kernel<C64, float>), grid, block, 0, st, g, (const float2*)V, (float2*)W);
-  else if (dtype == DT_C128)
-    hipLaunchKernelGGL((brillouin_links_kernel<C128, double>), grid, block, 0, st, g, (const double2*)V,
-                       (double2*)W);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return launch_brillouin_links_levels(dtype, g, V, W, st);
 }
 
 // ---------------------------------------------------------------- link gradient

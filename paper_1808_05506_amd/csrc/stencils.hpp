@@ -521,21 +521,4 @@ DSL_HD void brillouin_path_mean(const Geom& g, const typename S::word* __restric
     for (int b = 0; b < 3; ++b) acc[a][b] = inv * acc[a][b];
 }
 
-// Stored W for slot j (direction n(d) = j + 41) at site s.
-template <class S, class T>
-DSL_HD void brillouin_link_site(const Geom& g, const typename S::word* __restrict__ V,
-                                typename S::word* __restrict__ Wout, uint32_t s, int j) {
-  int d[4];
-  stored_direction(j, d);
-  const SiteNbr nb = site_nbr(g, s);
-  const int x[4] = {nb.c[0], nb.c[1], nb.c[2], nb.c[3]};
-  cpx<T> w[3][3];
-  brillouin_path_mean<S, T>(g, V, x, d, w);
-  const size_t base = (size_t(s) * 40 + j) * 9;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) S::template store<T>(Wout + base + a * 3 + b, w[a][b]);
-}
-
 }  // namespace dsl
