@@ -453,10 +453,23 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
             del P
         del U, Uc
     torch.cuda.empty_cache()
-    # link gradients at 24^3 x 48, N_v = 12, timed like the operator rows
-    # (settle, warmup, mean over the timed launches, median single launch);
-    # D_S rotates two translated (chi, psi, G) sets so the footprint exceeds 1 GB
+    rows.update(gradient_rows_bench(torch, D, np, synthetic, steps, warmup))
+    rows.update(solve_rows_bench(torch, D, np, synthetic))
+    return rows
+
+
+def gradient_rows_bench(torch, D, np, synthetic, steps, warmup):
+    """The link gradients at 24^3 x 48, N_v = 12, FP32, timed like the operator
+    rows (settle, warmup, mean over the timed launches, median single launch);
+    D_S rotates two translated (chi, psi, G) sets so the footprint exceeds 1 GB.
+    Then the Brillouin ones: with respect to W, the W construction, and through
+    it to V."""
     import ctypes
+    rows = {}
+    dev = torch.device("cuda:0")
+
+    def up(a, dt):
+        return torch.from_numpy(a.astype(dt)).to(dev)
     lib = D._lib
     dims = (24, 24, 24, 48)
     vol = int(np.prod(dims))
@@ -526,7 +539,6 @@ def rows_bench(torch, D, np, synthetic, steps, warmup):
         torch, vgrad_subsets, nsteps, 1, bv, 1, "Brillouin links backward (V), sums over orderings", single=5)
     del V, W, C, P, gW, gV, ws
     torch.cuda.empty_cache()
-    rows.update(solve_rows_bench(torch, D, np, synthetic))
     return rows
 
 
@@ -586,9 +598,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=4)
-    ap.add_argument("--rows", choices=["all", "none", "staggered", "solve", "brillouin", "nv"], default="all",
-                    help="the other rows: all, none, or only the D_S ones, the solves, the D_B ones or the D_W "
-                         "ones at other block sizes N_v")
+    ap.add_argument("--rows", choices=["all", "none", "staggered", "solve", "brillouin", "nv", "gradients"],
+                    default="all",
+                    help="the other rows: all, none, or only the D_S ones, the solves, the D_B ones, the D_W "
+                         "ones at other block sizes N_v or the link gradients")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain FP32 complex copy of this many MiB (counter calibration)")
@@ -646,6 +659,8 @@ def main():
         rows = brillouin_rows_bench(torch, D, np, synthetic, args.steps)
     elif args.rows == "nv":
         rows = block_size_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
+    elif args.rows == "gradients":
+        rows = gradient_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
 
     cpu = None if args.no_cpu else cpu_baseline(dims, nv, m0)
     if args.rows == "all" and not args.no_cpu:
