@@ -141,6 +141,86 @@ def link_grad_at(op: str, chi, psi, coords, mu: int) -> np.ndarray:
     raise ValueError(op)
 
 
+def _stored_directions():
+    """The 40 stored displacements in slot order (Tab. 1 caption: slot
+    n(d) - 41, n(d) = sum_mu (d_mu + 1) 3^mu, for the d with n(d) > 40)."""
+    out = []
+    for n in range(41, 81):
+        out.append((n % 3 - 1, (n // 3) % 3 - 1, (n // 9) % 3 - 1, n // 27 - 1))
+    return out
+
+
+def _bri_spin(d):
+    k = sum(1 for s in d if s)
+    return -0.5 * _LAMBDA[k] * IDENTITY + _RHO[k] * sum(d[mu] * GAMMA[mu] for mu in range(4))
+
+
+def brillouin_w_grad_at(chi, psi, coords) -> np.ndarray:
+    """G_{W_d}(x) for x in coords and the 40 stored d, shape (n, 40, Nc, Nc):
+    the gradient of Re<chi, D_B psi> with respect to the stored W (see
+    ``oracle.grad.link_grad_brillouin_W``).  W_d(x) enters out(x) through the
+    hop S_d W_d(x) psi(x + d), S_d = -lambda_k/2 + rho_k d.gamma, and out(x + d)
+    through the hop along -d, S_{-d} W_d(x)^dag psi(x); only chi and psi at x
+    and x + d take part."""
+    nc = psi.shape[-2]
+    G = np.zeros((len(coords), 40, nc, nc), dtype=np.complex128)
+    for j, d in enumerate(_stored_directions()):
+        md = tuple(-c for c in d)
+        a_f = _spin(_dag(_bri_spin(d)), _at(chi, coords))
+        a_b = _spin(_dag(_bri_spin(md)), _at(chi, coords, d))
+        t1 = np.einsum("nsav,nsbv->nab", a_f, np.conj(_at(psi, coords, d)))
+        t2 = np.einsum("nsav,nsbv->nab", _at(psi, coords), np.conj(a_b))
+        G[:, j] = t1 + t2
+    return G
+
+
+def _hop_link_at(V, coords, pos, mu, s):
+    """The link of the hop s mu that starts at x + pos, for x in coords:
+    V_mu(x + pos), or V_mu(x + pos - mu)^dag against the link."""
+    if s > 0:
+        return _at(V, coords, pos)[:, mu]
+    return _dag(_at(V, coords, pos + np.array(_unit(mu, -1)))[:, mu])
+
+
+def brillouin_links_backward_at(V, G_W, coords, mu: int) -> np.ndarray:
+    """G_V(y, mu) for y in coords: the gradient with respect to V_mu(y) of
+    Re sum conj(G_W) W[V] (see ``oracle.grad.brillouin_links_backward``).
+    A path uses the link in its hop along mu.  For every stored d with
+    d_mu != 0, every ordering of its hops and the position i of the mu hop,
+    the path starts at y less the displacement of the hops before i (a hop
+    along the link), or at y + mu less it (a hop against the link, from
+    y + mu to y).  That hop receives P^dag G_{W_d}(start) Q^dag / k!, P and Q
+    the products of the hops before and after it, or the adjoint of that
+    against the link."""
+    nc = V.shape[-1]
+    eye = np.broadcast_to(np.eye(nc, dtype=np.complex128), (len(coords), nc, nc))
+    out = np.zeros((len(coords), nc, nc), dtype=np.complex128)
+    for j, d in enumerate(_stored_directions()):
+        s = d[mu]
+        if s == 0:
+            continue
+        steps = [(m, c) for m, c in enumerate(d) if c]
+        orders = list(itertools.permutations(steps))
+        for order in orders:
+            i = order.index((mu, s))
+            start = np.zeros(4, dtype=int) if s > 0 else np.array(_unit(mu))
+            for m, c in order[:i]:
+                start = start - np.array(_unit(m, c))
+            pos = start.copy()
+            P = eye
+            for m, c in order[:i]:
+                P = P @ _hop_link_at(V, coords, pos, m, c)
+                pos = pos + np.array(_unit(m, c))
+            pos = pos + np.array(_unit(mu, s))
+            Q = eye
+            for m, c in order[i + 1:]:
+                Q = Q @ _hop_link_at(V, coords, pos, m, c)
+                pos = pos + np.array(_unit(m, c))
+            X = _dag(P) @ _at(G_W, coords, start)[:, j] @ _dag(Q) / len(orders)
+            out += X if s > 0 else _dag(X)
+    return out
+
+
 def loss_at(op: str, V, chi, psi, mass, coords) -> float:
     """Re sum over the listed sites of conj(chi(x)) * (D psi)(x)."""
     if op == "staggered":

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synthetic
-from oracle import brillouin, grad
+from oracle import brillouin, grad, local
 from tests.gpu_util import compare, down, rounded, say, set_knob, up
 from tests.helpers import brillouin_rows_cover
 
@@ -89,6 +89,49 @@ def test_links_backward_levels_off_16_byte_alignment():
     b = D.brillouin_links_backward(off(V), off(GW), off(W), method="levels")
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def _sampled(t, sites):
+    it = torch.as_tensor(np.stack((sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0])), device=t.device)
+    return t[it[0], it[1], it[2], it[3]].cpu().numpy().astype(np.complex128)
+
+
+def test_wgrad_24cube48_nv12_sampled(monkeypatch):
+    # the benchmark's workload: 24^3 x 48, N_v = 12, FP32, chi and psi seeds
+    # 104 and 105, through the row-staged kernel (required); the oracle forms
+    # G_W at 32 sampled sites and the 16 corners (G_W does not depend on W)
+    dims, nv, dt = (24, 24, 24, 48), 12, "c64"
+    say(f"case brillouin W gradient {dims} nv={nv} sampled")
+    chi = rounded(synthetic.wilson_spinor(dims, nv, 104), dt)
+    psi = rounded(synthetic.wilson_spinor(dims, nv, 105), dt)
+    W = torch.zeros(tuple(reversed(dims)) + (40, 3, 3), dtype=torch.complex64, device="cuda")
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    gW, _ = D.backward("brillouin", W, up(chi, dt), up(psi, dt), 0.1, need_grad_in=False)
+    sites = local.sample_sites(dims, 32, 12)
+    got = _sampled(gW, sites)
+    del gW, W
+    compare(got, local.brillouin_w_grad_at(chi, psi, sites), dt, "G_W 24^3x48 sampled")
+
+
+def test_links_backward_24cube48_sampled():
+    # the benchmark's workload: 24^3 x 48, FP32, Haar V (seed 6), Gaussian G_W
+    # (seed 7), all three forms of the adjoint (levels through the workspace,
+    # sums over orderings through W, walks through V); the oracle forms G_V on
+    # the four links of 12 sampled sites and the 16 corners
+    dims, dt = (24, 24, 24, 48), "c64"
+    say(f"case brillouin links backward {dims} sampled")
+    v = rounded(synthetic.gauge_links(dims, "haar", 6), dt)
+    gw = rounded(synthetic.gaussian(v.shape[:4] + (40, 3, 3), 7), dt)
+    sites = local.sample_sites(dims, 12, 13)
+    ref = np.stack([local.brillouin_links_backward_at(v, gw, sites, mu) for mu in range(4)], axis=1)
+    V, GW = up(v, dt), up(gw, dt)
+    del gw
+    W = D.brillouin_links(V)
+    for method in ("levels", "subsets", "walk"):
+        say(f"  method={method}")
+        gV = D.brillouin_links_backward(V, GW, None if method == "walk" else W, method=method)
+        compare(_sampled(gV, sites), ref, dt, f"G_V 24^3x48 sampled, {method}")
+        del gV
 
 
 def test_link_gradient_wrt_V_end_to_end():

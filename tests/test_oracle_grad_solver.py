@@ -96,6 +96,21 @@ def test_local_link_grad(op):
         assert np.abs(local.link_grad_at(op, chi, psi, sites, mu) - G[idx][:, mu]).max() < 1e-13
 
 
+def test_local_brillouin_gradients():
+    # the sampled-site forms of the gradient with respect to W and of the
+    # adjoint of the W construction equal the whole-lattice oracle there
+    dims = (4, 3, 3, 4)
+    sites = local.sample_sites(dims, 12, 6)
+    idx = (sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0])
+    chi, psi = synthetic.wilson_spinor(dims, 2, 7), synthetic.wilson_spinor(dims, 2, 8)
+    gw = grad.link_grad_brillouin_W(chi, psi)
+    assert np.abs(local.brillouin_w_grad_at(chi, psi, sites) - gw[idx]).max() < 1e-13
+    v = synthetic.gauge_links(dims, "haar", 9)
+    gv = grad.brillouin_links_backward(v, gw)
+    for mu in range(4):
+        assert np.abs(local.brillouin_links_backward_at(v, gw, sites, mu) - gv[idx][:, mu]).max() < 1e-12
+
+
 @pytest.mark.parametrize("op", ["staggered", "wilson"])
 def test_local_fd_matches_full_fd(op):
     u, chi, psi = _fields(op, 40)
