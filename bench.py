@@ -656,7 +656,7 @@ def main():
     elif args.rows == "solve":
         rows = solve_rows_bench(torch, D, np, synthetic)
     elif args.rows == "brillouin":
-        rows = brillouin_rows_bench(torch, D, np, synthetic, args.steps)
+        rows = brillouin_rows_bench(torch, D, np, synthetic, args.steps, fly=True)
     elif args.rows == "nv":
         rows = block_size_rows_bench(torch, D, np, synthetic, args.steps, args.warmup)
     elif args.rows == "gradients":

@@ -196,25 +196,46 @@ __device__ __forceinline__ void bri_hop(const typename S::word* site, const type
 
 // On-the-fly links: W_d(x) for the three hops (dx = -1, 0, 1; dy, dz, dt) of
 // row r and the chunk's sites, built from V (Tab. 1) straight into the link
-// columns, one (column, site) pair per thread.  Every W_d(x) of the 80
+// columns, four lanes per (column, site) pair.  Every W_d(x) of the 80
 // directions is built where it is used, so no adjoint relation is needed.
 template <class S, class T>
 __device__ __forceinline__ void bri_build(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ V,
                                           int r, typename S::word* wbuf, int R, int tid) {
+  // GL consecutive lanes share one (column, site): each sums every GL-th
+  // ordering of the path, and the partial sums are added in a fixed butterfly
+  // (every lane of the group ends with the same bits).  3 n GL <= R N_v
+  // threads at N_v = 12.
+  constexpr int GL = 4;
   int dy, dz, dt;
   bri_row_offset(r, dy, dz, dt);
-  if (tid >= 3 * c.n) return;
-  const int col = tid / c.n, site = tid - col * c.n;
+  const int item = tid / GL, part = tid - item * GL;
+  if (item >= 3 * c.n) return;  // whole groups of GL lanes
+  const int col = item / c.n, site = item - col * c.n;
   const int d[4] = {col - 1, dy, dz, dt};
-  if ((d[0] | dy | dz | dt) == 0) return;  // no hop
+  if ((d[0] | dy | dz | dt) == 0) return;  // no hop (a whole group)
   const int x[4] = {c.x0 + site, c.y, c.z, c.t};
   cpx<T> w[3][3];
-  brillouin_path_mean<S, T>(g, V, x, d, w);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) w[a][b] = zero<T>();
+  const int nperm = brillouin_path_sum<S, T>(g, V, x, d, part, GL, w);
+#pragma unroll
+  for (int off = 1; off < GL; off *= 2)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        w[a][b].r += __shfl_xor(w[a][b].r, off);
+        w[a][b].i += __shfl_xor(w[a][b].i, off);
+      }
+  if (part != 0) return;
+  const T inv = T(1) / T(nperm);
   typename S::word* o = wbuf + col * R * 9 + site * 9;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) S::template store<T>(o + a * 3 + b, w[a][b]);
+    for (int b = 0; b < 3; ++b) S::template store<T>(o + a * 3 + b, inv * w[a][b]);
 }
 
 // The three hops of staged row r (and the diagonal term, with the clover term

@@ -422,11 +422,13 @@ DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W
 }
 
 // ---------------------------------------------------------------- W build
-// W_d(x) (Tab. 1): the mean over the k! orderings of the hops of d of the
+// W_d(x) (Tab. 1) is the mean over the k! orderings of the hops of d of the
 // ordered product V_{e1}(x) V_{e2}(x+e1) ..., V_{-mu}(y) = V_mu(y-mu)^dag.
+// This sums the products of the orderings o = part, part + nparts, ... of
+// the k! (so nparts lanes can share one W_d(x)) and returns k!.
 template <class S, class T>
-DSL_HD void brillouin_path_mean(const Geom& g, const typename S::word* __restrict__ V, const int (&x)[4],
-                                const int (&d)[4], cpx<T> (&acc)[3][3]) {
+DSL_HD int brillouin_path_sum(const Geom& g, const typename S::word* __restrict__ V, const int (&x)[4],
+                              const int (&d)[4], int part, int nparts, cpx<T> (&acc)[3][3]) {
   int mus[4], sgn[4], k = 0;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
@@ -440,32 +442,28 @@ DSL_HD void brillouin_path_mean(const Geom& g, const typename S::word* __restric
 #pragma unroll
     for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
 
-  int nperm = 0;
-  // all permutations of {0..3}; keep those that fix k..3, i.e. the k! orderings of the first k hops
+  const int kfact = k == 4 ? 24 : (k == 3 ? 6 : (k == 2 ? 2 : 1));
+  // ordering o of the k hops: its digits in the factorial number system pick
+  // the next hop among those left; the lanes of a group take o = part,
+  // part + nparts, ... (each iteration, every lane of the group its own o)
 #pragma unroll 1
-  for (int code = 0; code < 24; ++code) {
+  for (int o = part; o < kfact; o += nparts) {
     int perm[4];
     {
-      // decode the Lehmer code (factorial number system) into a permutation
       int avail[4] = {0, 1, 2, 3};
-      int rem = code;
-      const int fact[4] = {6, 2, 1, 1};
+      int rem = o;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int q = rem / fact[i];
-        rem -= q * fact[i];
+        const int e = k - 1 - i;  // (e)! orderings of the hops after this one
+        const int f = e == 3 ? 6 : (e == 2 ? 2 : 1);
+        const int q = i < k ? rem / f : 0;
+        rem -= q * f;
         perm[i] = avail[q];
 #pragma unroll
         for (int t = 0; t < 3; ++t)
           if (t >= q) avail[t] = avail[t + 1];
       }
     }
-    bool keep = true;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i >= k && perm[i] != i) keep = false;
-    if (!keep) continue;
-    ++nperm;
     int pos[4] = {x[0], x[1], x[2], x[3]};
     cpx<T> m[3][3];
 #pragma unroll 1
@@ -514,11 +512,7 @@ DSL_HD void brillouin_path_mean(const Geom& g, const typename S::word* __restric
 #pragma unroll
       for (int b = 0; b < 3; ++b) acc[a][b] += m[a][b];
   }
-  const T inv = T(1) / T(nperm);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) acc[a][b] = inv * acc[a][b];
+  return kfact;
 }
 
 }  // namespace dsl
