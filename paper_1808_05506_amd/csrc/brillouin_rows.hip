@@ -196,15 +196,15 @@ __device__ __forceinline__ void bri_hop(const typename S::word* site, const type
 
 // On-the-fly links: W_d(x) for the three hops (dx = -1, 0, 1; dy, dz, dt) of
 // row r and the chunk's sites, built from V (Tab. 1) straight into the link
-// columns, four lanes per (column, site) pair.  Every W_d(x) of the 80
+// columns, four lanes per (column, site) pair, one per first hop.  Every W_d(x) of the 80
 // directions is built where it is used, so no adjoint relation is needed.
 template <class S, class T>
 __device__ __forceinline__ void bri_build(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ V,
                                           int r, typename S::word* wbuf, int R, int tid) {
-  // GL consecutive lanes share one (column, site): each sums every GL-th
-  // ordering of the path, and the partial sums are added in a fixed butterfly
-  // (every lane of the group ends with the same bits).  3 n GL <= R N_v
-  // threads at N_v = 12.
+  // GL = 4 consecutive lanes share one (column, site): lane `part` sums the
+  // orderings that begin with hop number `part` of d, and the partial sums
+  // are added in a fixed butterfly (every lane of the group ends with the
+  // same bits).  3 n GL <= R N_v threads at N_v = 12.
   constexpr int GL = 4;
   int dy, dz, dt;
   bri_row_offset(r, dy, dz, dt);
@@ -215,11 +215,7 @@ __device__ __forceinline__ void bri_build(const Geom& g, const RowChunk& c, cons
   if ((d[0] | dy | dz | dt) == 0) return;  // no hop (a whole group)
   const int x[4] = {c.x0 + site, c.y, c.z, c.t};
   cpx<T> w[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) w[a][b] = zero<T>();
-  const int nperm = brillouin_path_sum<S, T>(g, V, x, d, part, GL, w);
+  const int nperm = brillouin_path_tree_sum<S, T>(g, V, x, d, part, w);
 #pragma unroll
   for (int off = 1; off < GL; off *= 2)
 #pragma unroll

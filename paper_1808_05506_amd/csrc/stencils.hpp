@@ -424,11 +424,49 @@ DSL_HD void brillouin_site(const Geom& g, const typename S::word* __restrict__ W
 // ---------------------------------------------------------------- W build
 // W_d(x) (Tab. 1) is the mean over the k! orderings of the hops of d of the
 // ordered product V_{e1}(x) V_{e2}(x+e1) ..., V_{-mu}(y) = V_mu(y-mu)^dag.
-// This sums the products of the orderings o = part, part + nparts, ... of
-// the k! (so nparts lanes can share one W_d(x)) and returns k!.
+
+// Link of the hop sg * mu from pos (V_mu(pos), or V_mu(pos - mu)^dag); pos
+// moves to the end of the hop.
 template <class S, class T>
-DSL_HD int brillouin_path_sum(const Geom& g, const typename S::word* __restrict__ V, const int (&x)[4],
-                              const int (&d)[4], int part, int nparts, cpx<T> (&acc)[3][3]) {
+DSL_HD void path_hop(const Geom& g, const typename S::word* __restrict__ V, int (&pos)[4], int mu, int sg,
+                     cpx<T> (&l)[3][3]) {
+  if (sg < 0) pos[mu] = pos[mu] == 0 ? g.n[mu] - 1 : pos[mu] - 1;
+  const uint32_t ls = uint32_t(pos[0] + g.stride[1] * pos[1] + g.stride[2] * pos[2] + g.stride[3] * pos[3]);
+  load_link<S, T>(V, (size_t(ls) * 4 + mu) * 9, l);
+  if (sg < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b) {
+        const cpx<T> x1 = l[a][b], y1 = l[b][a];
+        l[a][b] = conj(y1);
+        l[b][a] = conj(x1);
+      }
+  } else {
+    pos[mu] = pos[mu] + 1 == g.n[mu] ? 0 : pos[mu] + 1;
+  }
+}
+
+template <class T>
+DSL_HD void path_mul(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cpx<T> z = zero<T>();
+#pragma unroll
+      for (int c = 0; c < 3; ++c) z = cmadd(z, a[i][c], b[c][j]);
+      r[i][j] = z;
+    }
+}
+
+// The sum of the path products of W_d(x) over the (k - 1)! orderings that
+// begin with hop number `first` of d (0 <= first < k; nothing otherwise),
+// each shared prefix multiplied once (15 products for k = 4 instead of 18),
+// in the fixed order of the remaining hops; returns k!.
+template <class S, class T>
+DSL_HD int brillouin_path_tree_sum(const Geom& g, const typename S::word* __restrict__ V, const int (&x)[4],
+                                   const int (&d)[4], int first, cpx<T> (&acc)[3][3]) {
   int mus[4], sgn[4], k = 0;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
@@ -441,76 +479,56 @@ DSL_HD int brillouin_path_sum(const Geom& g, const typename S::word* __restrict_
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) acc[a][b] = zero<T>();
-
   const int kfact = k == 4 ? 24 : (k == 3 ? 6 : (k == 2 ? 2 : 1));
-  // ordering o of the k hops: its digits in the factorial number system pick
-  // the next hop among those left; the lanes of a group take o = part,
-  // part + nparts, ... (each iteration, every lane of the group its own o)
-#pragma unroll 1
-  for (int o = part; o < kfact; o += nparts) {
-    int perm[4];
-    {
-      int avail[4] = {0, 1, 2, 3};
-      int rem = o;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = k - 1 - i;  // (e)! orderings of the hops after this one
-        const int f = e == 3 ? 6 : (e == 2 ? 2 : 1);
-        const int q = i < k ? rem / f : 0;
-        rem -= q * f;
-        perm[i] = avail[q];
-#pragma unroll
-        for (int t = 0; t < 3; ++t)
-          if (t >= q) avail[t] = avail[t + 1];
-      }
-    }
-    int pos[4] = {x[0], x[1], x[2], x[3]};
-    cpx<T> m[3][3];
-#pragma unroll 1
-    for (int i = 0; i < k; ++i) {
-      const int mu = mus[perm[i]], sg = sgn[perm[i]];
-      int q[4] = {pos[0], pos[1], pos[2], pos[3]};
-      if (sg < 0) q[mu] = (q[mu] == 0) ? g.n[mu] - 1 : q[mu] - 1;  // link V_mu(y - mu)^dag
-      const uint32_t ls = uint32_t(q[0] + g.stride[1] * q[1] + g.stride[2] * q[2] + g.stride[3] * q[3]);
-      cpx<T> l[3][3];
-      load_link<S, T>(V, (size_t(ls) * 4 + mu) * 9, l);
-      if (sg < 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = a; b < 3; ++b) {
-            cpx<T> x1 = l[a][b], y1 = l[b][a];
-            l[a][b] = conj(y1);
-            l[b][a] = conj(x1);
-          }
-      }
-      if (i == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) m[a][b] = l[a][b];
-      } else {
-        cpx<T> r[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            cpx<T> z = zero<T>();
-#pragma unroll
-            for (int c = 0; c < 3; ++c) z = cmadd(z, m[a][c], l[c][b]);
-            r[a][b] = z;
-          }
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) m[a][b] = r[a][b];
-      }
-      pos[mu] = sg > 0 ? (pos[mu] + 1 == g.n[mu] ? 0 : pos[mu] + 1) : q[mu];
-    }
+  if (first >= k) return kfact;
+  int p1[4] = {x[0], x[1], x[2], x[3]};
+  cpx<T> a1[3][3];
+  path_hop<S, T>(g, V, p1, mus[first], sgn[first], a1);
+  if (k == 1) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) acc[a][b] += m[a][b];
+      for (int b = 0; b < 3; ++b) acc[a][b] = a1[a][b];
+    return kfact;
+  }
+#pragma unroll 1
+  for (int i2 = 0; i2 < k; ++i2) {
+    if (i2 == first) continue;
+    int p2[4] = {p1[0], p1[1], p1[2], p1[3]};
+    cpx<T> l[3][3], m2[3][3];
+    path_hop<S, T>(g, V, p2, mus[i2], sgn[i2], l);
+    path_mul(a1, l, m2);
+    if (k == 2) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] += m2[a][b];
+      continue;
+    }
+#pragma unroll 1
+    for (int i3 = 0; i3 < k; ++i3) {
+      if (i3 == first || i3 == i2) continue;
+      int p3[4] = {p2[0], p2[1], p2[2], p2[3]};
+      cpx<T> m3[3][3];
+      path_hop<S, T>(g, V, p3, mus[i3], sgn[i3], l);
+      path_mul(m2, l, m3);
+      if (k == 4) {
+        // the one hop left: 0 + 1 + 2 + 3 = 6
+        const int i4 = 6 - first - i2 - i3;
+        cpx<T> m4[3][3];
+        path_hop<S, T>(g, V, p3, mus[i4], sgn[i4], l);
+        path_mul(m3, l, m4);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) acc[a][b] += m4[a][b];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) acc[a][b] += m3[a][b];
+      }
+    }
   }
   return kfact;
 }
