@@ -41,19 +41,6 @@ DSL_HD void dgamma(const int (&d)[4], const cpx<T> (&y)[4][3], cpx<T> (&out)[4][
   }
 }
 
-template <class T>
-DSL_HD void m3_mul(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      cpx<T> z = zero<T>();
-#pragma unroll
-      for (int k = 0; k < 3; ++k) z = cmadd(z, a[i][k], b[k][j]);
-      r[i][j] = z;
-    }
-}
-
 // r = a^dag b
 template <class T>
 DSL_HD void m3_adj_mul(const cpx<T> (&a)[3][3], const cpx<T> (&b)[3][3], cpx<T> (&r)[3][3]) {
@@ -95,26 +82,6 @@ DSL_HD uint32_t site_of(const Geom& g, const int (&p)[4]) {
 }
 
 DSL_HD int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
-
-// Link of the hop sg * mu from pos (V_mu(pos), or V_mu(pos - mu)^dag); pos moves along.
-template <class S, class T>
-DSL_HD void walk_hop(const Geom& g, const typename S::word* __restrict__ V, int (&pos)[4], int mu, int sg,
-                     cpx<T> (&l)[3][3]) {
-  if (sg < 0) pos[mu] = wrap(pos[mu] - 1, g.n[mu]);
-  load_link<S, T>(V, (size_t(site_of(g, pos)) * 4 + mu) * 9, l);
-  if (sg < 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = a; b < 3; ++b) {
-        const cpx<T> x = l[a][b], y = l[b][a];
-        l[a][b] = conj(y);
-        l[b][a] = conj(x);
-      }
-  } else {
-    pos[mu] = wrap(pos[mu] + 1, g.n[mu]);
-  }
-}
 
 // Permutation `code` (0 .. 23, factorial number system) of {0, 1, 2, 3}.
 DSL_HD void decode_perm(int code, int (&perm)[4]) {
@@ -278,8 +245,8 @@ __global__ void __launch_bounds__(128) bri_links_backward_kernel(Geom g, const t
 #pragma unroll 1
       for (int i = 0; i < ih; ++i) {
         const int nu = axes[perm[i]];
-        walk_hop<S, T>(g, V, pos, nu, d[nu], L);
-        m3_mul(P, L, Tm);
+        path_hop<S, T>(g, V, pos, nu, d[nu], L);
+        path_mul(P, L, Tm);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -293,8 +260,8 @@ __global__ void __launch_bounds__(128) bri_links_backward_kernel(Geom g, const t
 #pragma unroll 1
       for (int i = ih + 1; i < k; ++i) {
         const int nu = axes[perm[i]];
-        walk_hop<S, T>(g, V, pos, nu, d[nu], L);
-        m3_mul(Q, L, Tm);
+        path_hop<S, T>(g, V, pos, nu, d[nu], L);
+        path_mul(Q, L, Tm);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -746,10 +713,10 @@ __global__ void __launch_bounds__(128) bri_links_level_kernel(Geom g, LevelSlots
   for (int mu = 0; mu < 4; ++mu) {
     const int s = d[mu];
     if (s == 0) continue;  // uniform over the block
-    // A_{s mu}(x); walk_hop leaves p at x + s mu, where the rest of the path starts
+    // A_{s mu}(x); path_hop leaves p at x + s mu, where the rest of the path starts
     int p[4] = {x[0], x[1], x[2], x[3]};
     cpx<T> a[3][3];
-    walk_hop<S, T>(g, V, p, mu, s, a);
+    path_hop<S, T>(g, V, p, mu, s, a);
     if (L == 1) {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -760,7 +727,7 @@ __global__ void __launch_bounds__(128) bri_links_level_kernel(Geom g, LevelSlots
       sub[mu] = 0;
       cpx<T> w[3][3], r3[3][3];
       load_w_any<S, T>(g, W, p, sub, w);
-      m3_mul(a, w, r3);
+      path_mul(a, w, r3);
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
