@@ -187,9 +187,10 @@ int dslash_brillouin_links_backward_ws(const void* V, const void* W, const void*
  * out = D_B in (adjoint == 0) or D_B^dag in, with the off-axis links W_d(x)
  * built from the one-hop links V inside the kernel for every hop (Tab. 1; the
  * paper's variant without a precomputed W, Sec. 5): no W array is read or
- * stored.  V: [..][4][3][3].  Built for N_v = 12, C64 storage and x-extents
- * that give rows of at least 12 sites (the row-staged kernel);
- * E_UNSUPPORTED otherwise.  Other arguments and errors as dslash_apply.
+ * stored.  V: [..][4][3][3].  Built for N_v = 4, 8, 12, 16 and 24, C64
+ * storage and the x-extents the row-staged FP32 kernel covers (rows of at
+ * least 12 sites at N_v = 12); E_UNSUPPORTED otherwise.  Other arguments and
+ * errors as dslash_apply.
  */
 int dslash_apply_brillouin_fly(const void* V, const void* in, void* out, const int dims[4], int Nc, int Nv,
                                double mass, int adjoint, int dtype, void* stream);

@@ -200,38 +200,41 @@ __device__ __forceinline__ void bri_hop(const typename S::word* site, const type
 // directions is built where it is used, so no adjoint relation is needed.
 template <class S, class T>
 __device__ __forceinline__ void bri_build(const Geom& g, const RowChunk& c, const typename S::word* __restrict__ V,
-                                          int r, typename S::word* wbuf, int R, int tid) {
-  // GL = 4 consecutive lanes share one (column, site): lane `part` sums the
-  // orderings that begin with hop number `part` of d, and the partial sums
-  // are added in a fixed butterfly (every lane of the group ends with the
-  // same bits).  3 n GL <= R N_v threads at N_v = 12.
+                                          int r, typename S::word* wbuf, int R, int tid, int nth) {
+  // GL = 4 consecutive lanes share one (column, site) item: lane `part` sums
+  // the orderings that begin with hop number `part` of d, and the partial
+  // sums are added in a fixed butterfly (every lane of the group ends with
+  // the same bits).  The nth / GL groups step through the 3 n items.
   constexpr int GL = 4;
   int dy, dz, dt;
   bri_row_offset(r, dy, dz, dt);
-  const int item = tid / GL, part = tid - item * GL;
-  if (item >= 3 * c.n) return;  // whole groups of GL lanes
-  const int col = item / c.n, site = item - col * c.n;
-  const int d[4] = {col - 1, dy, dz, dt};
-  if ((d[0] | dy | dz | dt) == 0) return;  // no hop (a whole group)
-  const int x[4] = {c.x0 + site, c.y, c.z, c.t};
-  cpx<T> w[3][3];
-  const int nperm = brillouin_path_tree_sum<S, T>(g, V, x, d, part, w);
+  const int part = tid % GL;
+#pragma unroll 1
+  for (int item = tid / GL; item < 3 * c.n; item += nth / GL) {  // uniform over a group
+    const int col = item / c.n, site = item - col * c.n;
+    const int d[4] = {col - 1, dy, dz, dt};
+    if ((d[0] | dy | dz | dt) == 0) continue;  // no hop (a whole group)
+    const int x[4] = {c.x0 + site, c.y, c.z, c.t};
+    cpx<T> w[3][3];
+    const int nperm = brillouin_path_tree_sum<S, T>(g, V, x, d, part, w);
 #pragma unroll
-  for (int off = 1; off < GL; off *= 2)
+    for (int off = 1; off < GL; off *= 2)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        w[a][b].r += __shfl_xor(w[a][b].r, off);
-        w[a][b].i += __shfl_xor(w[a][b].i, off);
-      }
-  if (part != 0) return;
-  const T inv = T(1) / T(nperm);
-  typename S::word* o = wbuf + col * R * 9 + site * 9;
+        for (int b = 0; b < 3; ++b) {
+          w[a][b].r += __shfl_xor(w[a][b].r, off);
+          w[a][b].i += __shfl_xor(w[a][b].i, off);
+        }
+    if (part == 0) {
+      const T inv = T(1) / T(nperm);
+      typename S::word* o = wbuf + col * R * 9 + site * 9;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) S::template store<T>(o + a * 3 + b, inv * w[a][b]);
+        for (int b = 0; b < 3; ++b) S::template store<T>(o + a * 3 + b, inv * w[a][b]);
+    }
+  }
 }
 
 // The three hops of staged row r (and the diagonal term, with the clover term
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(256, BriWaves<NV>::value)
 #pragma nounroll
   for (int r = 0; r < kBriRows; ++r) {
     bri_commit<FLY, NV, S>(c, q, buf, wbuf, R, xl, v, tid, nth);
-    if constexpr (FLY) bri_build<S, T>(g, c, Wl, r, wbuf, R, tid);
+    if constexpr (FLY) bri_build<S, T>(g, c, Wl, r, wbuf, R, tid, nth);
     __syncthreads();
     bri_issue<FLY, NV, S>(g, c, Wl, in, r + 1 < kBriRows ? r + 1 : kBriRows - 1, xm, xp, xl, v, tid, nth, q);
     bri_row_compute<ADJ, CLOV, FLY, NV, S, T>(r, buf, wbuf, lcl, R, xl, v, diag, acc);
@@ -807,17 +810,23 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
 }
 
 // D_B with the off-axis links built from V inside the row-staged kernel (no W
-// array).  The FP32 configurations of launch_brillouin_rows at N_v = 12;
-// hipErrorNotSupported otherwise.
+// array).  The FP32 configurations of launch_brillouin_rows (N_v = 4, 8, 12,
+// 16, 24; the clover term at N_v = 12); hipErrorNotSupported otherwise.
 hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* V, const void* in, void* out,
                                 double mass, hipStream_t st, const void* clover) {
   if (!aligned16(V) || !aligned16(in) || !aligned16(out) || !aligned16(clover)) return hipErrorNotSupported;
   const int R = brillouin_rows_sites(dtype, g);
-  if (R == 0 || g.nv != 12) return hipErrorNotSupported;
+  if (R == 0 || (clover && g.nv != 12)) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
+  switch (g.nv) {
+    case 4: return brillouin_rows_t<4, C64, float, true, false>(adj, g, R, bt, xcd, V, in, out, nullptr, mass, st);
+    case 8: return brillouin_rows_t<8, C64, float, true, false>(adj, g, R, bt, xcd, V, in, out, nullptr, mass, st);
+    case 16: return brillouin_rows_t<16, C64, float, true, false>(adj, g, R, bt, xcd, V, in, out, nullptr, mass, st);
+    case 24: return brillouin_rows_t<24, C64, float, true, false>(adj, g, R, bt, xcd, V, in, out, nullptr, mass, st);
+  }
   return brillouin_rows_t<12, C64, float, true>(adj, g, R, bt, xcd, V, in, out, clover, mass, st);
 }
 

@@ -176,8 +176,8 @@ int dslash_apply_brillouin_fly(const void* V, const void* in, void* out, const i
   hipError_t e = dsl::launch_brillouin_fly(adjoint != 0, dtype, g, V, in, out, mass, (hipStream_t)stream);
   if (e == hipErrorNotSupported)
     return fail(DSLASH_E_UNSUPPORTED,
-                "on-the-fly links are built for N_v = 12, C64 and rows of at least 12 sites (got N_v = %d, dtype %d, "
-                "Nx = %d)", Nv, dtype, dims[0]);
+                "on-the-fly links are built for N_v = 4, 8, 12, 16, 24, C64 and the rows the row-staged kernel "
+                "covers (got N_v = %d, dtype %d, Nx = %d)", Nv, dtype, dims[0]);
   if (e != hipSuccess) return hip_fail(e, "dslash_apply_brillouin_fly launch");
   return DSLASH_OK;
 }

@@ -261,6 +261,6 @@ def test_brillouin_fly_validation(lib):
     D = 0x20000000
     assert lib.dslash_apply_brillouin_fly(None, C, D, dims, 3, 12, 0.1, 0, 0, None) == 1   # NULL V
     assert lib.dslash_apply_brillouin_fly(A, C, C, dims, 3, 12, 0.1, 0, 0, None) == 3      # in == out
-    assert lib.dslash_apply_brillouin_fly(A, C, D, dims, 3, 4, 0.1, 0, 0, None) == 2       # N_v = 4
+    assert lib.dslash_apply_brillouin_fly(A, C, D, dims, 3, 5, 0.1, 0, 0, None) == 2       # N_v = 5
     assert lib.dslash_apply_brillouin_fly(A, C, D, dims, 3, 12, 0.1, 0, 1, None) == 2      # C128
     assert lib.dslash_apply_brillouin_fly(A, C, D, _dims(8, 4, 4, 4), 3, 12, 0.1, 0, 0, None) == 2  # rows of 8

@@ -27,6 +27,19 @@ def test_fly_matches_oracle(adj, dims):
     compare(down(out), brillouin.apply(brillouin.build(v), p, 0.1, adj), "c64", "D_B fly")
 
 
+# (N_v, rows): one chunk of 16 at N_v = 4, 8, 16; chunks of 8 at N_v = 24;
+# 24-site rows in chunks of 12 or 8
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("nv,dims", [(4, (16, 3, 2, 3)), (8, (16, 2, 3, 3)), (16, (16, 3, 2, 2)),
+                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2))])
+def test_fly_other_block_sizes(nv, dims, adj):
+    say(f"case brillouin fly {dims} nv={nv} adj={adj}")
+    v = rounded(synthetic.gauge_links(dims, "haar", 170 + nv), "c64")
+    p = rounded(synthetic.wilson_spinor(dims, nv, 171 + nv), "c64")
+    out = D.apply_brillouin_fly(up(v, "c64"), up(p, "c64"), 0.1, adjoint=adj)
+    compare(down(out), brillouin.apply(brillouin.build(v), p, 0.1, adj), "c64", f"D_B fly nv={nv}")
+
+
 def test_fly_equals_stored_w():
     dims = (16, 4, 4, 4)
     say("case brillouin fly vs stored W")
