@@ -830,19 +830,25 @@ hipError_t launch_brillouin_fly(bool adj, int dtype, const Geom& g, const void* 
   return brillouin_rows_t<12, C64, float, true>(adj, g, R, bt, xcd, V, in, out, clover, mass, st);
 }
 
-// Row-staged gradient with respect to W (FP32 storage, N_v = 12, chunks of at
-// least 12 sites); hipErrorNotSupported otherwise (the caller then uses the
-// per-direction kernel).  DSLASH_ROWS=0 disables it.
+// Row-staged gradient with respect to W (FP32 storage, N_v = 4, 8, 12, 16,
+// 24, the chunks of brillouin_rows_sites); hipErrorNotSupported otherwise (the
+// caller then uses the per-direction kernel).  DSLASH_ROWS=0 disables it.
 hipError_t launch_brillouin_wgrad_rows(int dtype, const Geom& g, const void* chi, const void* psi, void* GW,
                                        hipStream_t st) {
   if (knobs().rows.get(1) == 0) return hipErrorNotSupported;
   if (!aligned16(chi) || !aligned16(psi) || !aligned16(GW)) return hipErrorNotSupported;
-  if (dtype != DT_C64 || g.nv != 12) return hipErrorNotSupported;
+  if (dtype != DT_C64) return hipErrorNotSupported;
   const int R = brillouin_rows_sites(dtype, g);
   if (R == 0) return hipErrorNotSupported;
   int bt = 2;
   bt = knobs().tband.get(bt);
   const bool xcd = knobs().xcd.get(1) != 0;
+  switch (g.nv) {
+    case 4: return brillouin_wgrad_rows_t<4, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
+    case 8: return brillouin_wgrad_rows_t<8, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
+    case 16: return brillouin_wgrad_rows_t<16, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
+    case 24: return brillouin_wgrad_rows_t<24, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
+  }
   return brillouin_wgrad_rows_t<12, C64, float>(g, R, bt, xcd, chi, psi, GW, st);
 }
 

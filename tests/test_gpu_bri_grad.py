@@ -52,6 +52,22 @@ def test_wgrad_rows_matches_oracle(dims, monkeypatch):
     compare(down(gW), ref, dt, "G_W rows")
 
 
+# one chunk of 16 at N_v = 4, 8, 16; chunks of 8 at N_v = 24; 24-site rows
+# in chunks of 12 (N_v = 8) or 8 (N_v = 24)
+@pytest.mark.parametrize("nv,dims", [(4, (16, 3, 2, 3)), (8, (16, 2, 3, 3)), (16, (16, 3, 2, 2)),
+                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2))])
+def test_wgrad_rows_other_block_sizes(nv, dims, monkeypatch):
+    dt = "c64"
+    assert brillouin_rows_cover(dims[0], nv, dt)
+    say(f"case brillouin W gradient rows {dims} nv={nv}")
+    v, chi, psi = _fields(dims, nv, 116 + nv)
+    W = up(brillouin.build(v), dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    gW, _ = D.backward("brillouin", W, up(chi, dt), up(psi, dt), 0.1, need_grad_in=False)
+    ref = grad.link_grad_brillouin_W(rounded(chi, dt), rounded(psi, dt))
+    compare(down(gW), ref, dt, f"G_W rows nv={nv}")
+
+
 @pytest.mark.parametrize("method", ["walk", "subsets", "levels"])
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("dims", [(3, 3, 2, 3), (4, 3, 3, 5), (5, 4, 3, 4)])
