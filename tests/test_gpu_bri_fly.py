@@ -28,10 +28,12 @@ def test_fly_matches_oracle(adj, dims):
 
 
 # (N_v, rows): one chunk of 16 at N_v = 4, 8, 16; chunks of 8 at N_v = 24;
-# 24-site rows in chunks of 12 or 8
+# 24-site rows in chunks of 12 or 8; one chunk of 20 at N_v = 4 (80 threads,
+# the second wave partly filled)
 @pytest.mark.parametrize("adj", [False, True])
 @pytest.mark.parametrize("nv,dims", [(4, (16, 3, 2, 3)), (8, (16, 2, 3, 3)), (16, (16, 3, 2, 2)),
-                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2))])
+                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2)),
+                                     (4, (20, 2, 2, 3))])
 def test_fly_other_block_sizes(nv, dims, adj):
     say(f"case brillouin fly {dims} nv={nv} adj={adj}")
     v = rounded(synthetic.gauge_links(dims, "haar", 170 + nv), "c64")

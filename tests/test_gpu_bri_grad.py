@@ -53,9 +53,11 @@ def test_wgrad_rows_matches_oracle(dims, monkeypatch):
 
 
 # one chunk of 16 at N_v = 4, 8, 16; chunks of 8 at N_v = 24; 24-site rows
-# in chunks of 12 (N_v = 8) or 8 (N_v = 24)
+# in chunks of 12 (N_v = 8) or 8 (N_v = 24); one chunk of 20 at N_v = 4 (80
+# threads)
 @pytest.mark.parametrize("nv,dims", [(4, (16, 3, 2, 3)), (8, (16, 2, 3, 3)), (16, (16, 3, 2, 2)),
-                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2))])
+                                     (24, (16, 2, 2, 3)), (8, (24, 2, 2, 3)), (24, (24, 2, 3, 2)),
+                                     (4, (20, 2, 2, 3))])
 def test_wgrad_rows_other_block_sizes(nv, dims, monkeypatch):
     dt = "c64"
     assert brillouin_rows_cover(dims[0], nv, dt)
