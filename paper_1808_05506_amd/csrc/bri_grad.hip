@@ -18,7 +18,13 @@
 // P^dag G Q^dag with P, Q the products before and after it, or the adjoint of
 // that when the hop runs against the link.  One thread per link (y, mu) gathers
 // every (d, ordering, hop) that uses it, in a fixed order: the sum is
-// deterministic and needs no atomics.
+// deterministic and needs no atomics.  bri_links_backward_w_kernel sums the
+// orderings that share the hops around the link through the path averages of
+// W instead.
+//
+// bri_wlevel_*: the same adjoint through the recursion of the path averages
+// by their first hop, level by level (the default when W is given), and
+// bri_links_level_kernel: the construction of W itself by that recursion.
 #include "launch.hpp"
 #include "stencils.hpp"
 
