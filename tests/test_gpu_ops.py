@@ -354,6 +354,21 @@ def test_brillouin_row_staged_path(kernel, adj, dims, monkeypatch):
     compare(down(out), brillouin.apply(w, p, 0.1, adj), dt, f"D_B {kernel}")
 
 
+# FP64, N_v = 12, the direct-to-LDS row-staged kernel: one chunk of 16,
+# N_y = 2 (the -y and +y rows coincide), chunks of 16 + 4, a chunk of 12, odd
+# N_y
+@pytest.mark.parametrize("adj", [False, True])
+@pytest.mark.parametrize("dims", [(16, 4, 2, 3), (20, 2, 3, 3), (12, 6, 2, 2), (16, 3, 2, 3)])
+def test_brillouin_fp64_row_staged(dims, adj):
+    nv, dt = 12, "c128"
+    say(f"case brillouin fp64 rows {dims} adj={adj}")
+    v = synthetic.gauge_links(dims, "haar", 35)
+    w = brillouin.build(v)
+    p = synthetic.wilson_spinor(dims, nv, 36)
+    out = D.apply("brillouin", up(w, dt), up(p, dt), 0.1, adjoint=adj)
+    compare(down(out), brillouin.apply(w, p, 0.1, adj), dt, "D_B fp64 rows")
+
+
 @pytest.mark.parametrize("dt", ["c64", "c128", "bf16", "f16"])
 @pytest.mark.parametrize("op", ["wilson", "staggered"])
 @pytest.mark.parametrize("compressed", [False, True])
