@@ -174,6 +174,19 @@ def test_binding_rejects_cpu_tensors():
         D.apply("wilson", u, p, 0.1)
     with pytest.raises(ValueError):
         D.op_code("clover")
+    # the adjoint of the W construction: an unknown method, W with the walk
+    # through V, and the W-based methods without W are refused before any call
+    v = torch.zeros(2, 2, 2, 2, 4, 3, 3, dtype=torch.complex64)
+    gw = torch.zeros(2, 2, 2, 2, 40, 3, 3, dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        D.brillouin_links_backward(v, gw, gw, method="tree")
+    with pytest.raises(ValueError):
+        D.brillouin_links_backward(v, gw, gw, method="walk")
+    for method in ("subsets", "levels"):
+        with pytest.raises(ValueError):
+            D.brillouin_links_backward(v, gw, None, method=method)
+    with pytest.raises(ValueError):
+        D.brillouin_links_backward(v, gw)  # CPU tensors
 
 
 def test_even_odd_validation(lib):
