@@ -318,7 +318,9 @@ def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Ten
     ordering through V (the only one without W); "subsets" sums the orderings
     of each path through the path averages of W; "levels" (the default with W)
     runs the first-hop recursion of the path averages backwards through a
-    grad_W-sized workspace."""
+    workspace of 756 words a site (when that allocation fails and no method
+    was named, the sums through W run instead; they need none)."""
+    auto = method is None
     if method is None:
         method = "walk" if W is None else "levels"
     if method not in ("walk", "subsets", "levels"):
@@ -342,7 +344,13 @@ def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Ten
         nbytes = _lib.dslash_brillouin_links_backward_workspace_bytes(dims, 3, code)
         if nbytes == 0:
             raise DslashError(f"dslash_brillouin_links_backward_workspace_bytes rejected dims {vs[:4]}")
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=V.device)
+        try:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=V.device)
+        except torch.cuda.OutOfMemoryError:
+            if not auto:
+                raise
+            ws = None
+    if method == "levels" and ws is not None:
         _check(_lib.dslash_brillouin_links_backward_ws(_ptr(V), _ptr(W), _ptr(grad_W), _ptr(gV), _ptr(ws), nbytes,
                                                        dims, 3, code, _stream(V)),
                "dslash_brillouin_links_backward_ws")

@@ -87,6 +87,31 @@ def test_links_backward_matches_oracle(dt, dims, method):
     compare(down(gV), ref, dt, "G_V from G_W")
 
 
+def test_links_backward_without_room_for_the_workspace(monkeypatch):
+    # when the level method's workspace cannot be allocated and no method was
+    # named, the sums over orderings through W run instead (same device path,
+    # no workspace); a named method raises
+    dims = (4, 3, 3, 5)
+    say("case brillouin links backward, workspace allocation refused")
+    v = synthetic.gauge_links(dims, "haar", 124)
+    gw = synthetic.gaussian(v.shape[:4] + (40, 3, 3), 125)
+    V, GW = up(v, "c64"), up(gw, "c64")
+    W = D.brillouin_links(V)
+    ref = D.brillouin_links_backward(V, GW, W, method="subsets")
+    real_empty = torch.empty
+
+    def no_workspace(*a, **k):
+        if k.get("dtype") is torch.uint8:
+            raise torch.cuda.OutOfMemoryError("workspace refused by the test")
+        return real_empty(*a, **k)
+    monkeypatch.setattr(D.torch, "empty", no_workspace)
+    got = D.brillouin_links_backward(V, GW, W)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    with pytest.raises(torch.cuda.OutOfMemoryError):
+        D.brillouin_links_backward(V, GW, W, method="levels")
+
+
 def test_links_backward_levels_off_16_byte_alignment():
     # fields 8 bytes off a 16-byte boundary take the per-word transposition
     # into the workspace: the same arithmetic, so the same bits
