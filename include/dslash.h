@@ -175,7 +175,7 @@ size_t dslash_brillouin_links_backward_workspace_bytes(const int dims[4], int Nc
  * result as dslash_brillouin_links_backward up to rounding order, with about a
  * fifth of the matrix products; deterministic (gathers in a fixed order, no
  * atomics).  V, grad_W, grad_V as there; W: dslash_brillouin_links(V),
- * required; workspace: device memory of ws_bytes >=
+ * required; workspace: 16-byte aligned device memory of ws_bytes >=
  * dslash_brillouin_links_backward_workspace_bytes (else E_ARG), overwritten,
  * owned by the caller, must not overlap any other argument (E_ALIAS).  C64
  * and C128 only.  Asynchronous on `stream`.

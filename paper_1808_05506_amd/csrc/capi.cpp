@@ -251,6 +251,7 @@ int dslash_brillouin_links_backward_ws(const void* V, const void* W, const void*
     return fail(DSLASH_E_UNSUPPORTED, "W construction is built for C64 and C128 only (got dtype %d)", dtype);
   if (!V || !W || !grad_W || !grad_V) return fail(DSLASH_E_ARG, "NULL field pointer");
   if (!workspace) return fail(DSLASH_E_ARG, "NULL workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0) return fail(DSLASH_E_ARG, "workspace not 16-byte aligned");
   const uint64_t vol = volume(dims);
   const size_t eb = dsl::dtype_bytes(dtype);
   const size_t nv = size_t(vol) * 36 * eb, nw = size_t(vol) * 360 * eb;

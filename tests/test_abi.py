@@ -260,11 +260,12 @@ def test_brillouin_links_backward_ws_validation(lib):
     assert ws(A, None, B, C, E, nw, dims, 3, 0, None) == 1          # W is required
     assert ws(A, D, B, C, None, nw, dims, 3, 0, None) == 1          # NULL workspace
     assert ws(A, D, B, C, E, nw - 1, dims, 3, 0, None) == 1         # workspace too small
+    assert ws(A, D, B, C, E + 8, nw, dims, 3, 0, None) == 1         # workspace 8 bytes off 16
     assert ws(A, D, B, A, E, nw, dims, 3, 0, None) == 3             # grad_V == V
     assert ws(A, D, B, D, E, nw, dims, 3, 0, None) == 3             # grad_V == W
     assert ws(A, D, B, C, B, nw, dims, 3, 0, None) == 3             # workspace == grad_W
-    assert ws(A, D, B, C, D + 8, nw, dims, 3, 0, None) == 3         # workspace overlaps W
-    assert ws(A, D, B, C, C - 8, nw, dims, 3, 0, None) == 3         # workspace runs into grad_V
+    assert ws(A, D, B, C, D + 16, nw, dims, 3, 0, None) == 3        # workspace overlaps W
+    assert ws(A, D, B, C, C - 16, nw, dims, 3, 0, None) == 3        # workspace runs into grad_V
     assert ws(A, D, B, C, E, nw, dims, 3, 2, None) == 2             # BF16
     assert ws(A, D, B, C, E, nw, dims, 2, 0, None) == 2             # Nc != 3
 
