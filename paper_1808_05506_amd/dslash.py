@@ -146,13 +146,15 @@ def _stream(t: torch.Tensor):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _require(t: torch.Tensor, name: str):
+def _require(t: torch.Tensor, name: str, like: torch.Tensor | None = None):
     if not isinstance(t, torch.Tensor):
         raise ValueError(f"{name} must be a torch.Tensor")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if like is not None and t.device != like.device:
+        raise ValueError(f"{name} must be on {like.device}, not {t.device}")
 
 
 def _spinor_shape(op: int, lat, nv: int) -> tuple:
@@ -195,11 +197,11 @@ def _apply(op, U: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, adjoint: b
     if out is None:
         out = torch.empty_like(psi)
     else:
-        _require(out, "out")
+        _require(out, "out", psi)
         if out.shape != psi.shape or out.dtype != psi.dtype:
             raise ValueError("out must match psi in shape and dtype")
     if clover is not None:
-        _require(clover, "clover")
+        _require(clover, "clover", psi)
         if _core_shape(clover) != tuple(lat) + (2, 18) or _dtype_code(clover) != _dtype_code(psi):
             raise ValueError(f"clover must be [Nt,Nz,Ny,Nx,2,18] in the dtype of psi, got {tuple(clover.shape)}")
         _check(_lib.dslash_apply_clover(op, _ptr(U), _ptr(clover), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv,
@@ -219,7 +221,7 @@ def apply_brillouin_fly(V: torch.Tensor, psi: torch.Tensor, mass: float = 0.0, a
     if out is None:
         out = torch.empty_like(psi)
     else:
-        _require(out, "out")
+        _require(out, "out", psi)
         if out.shape != psi.shape or out.dtype != psi.dtype:
             raise ValueError("out must match psi in shape and dtype")
     _check(_lib.dslash_apply_brillouin_fly(_ptr(V), _ptr(psi), _ptr(out), _dims_c(lat), 3, nv, float(mass),
@@ -246,7 +248,7 @@ def apply_compressed(op, Vc: torch.Tensor, psi: torch.Tensor, mass: float = 0.0,
     """out = D psi (or D^dag psi) for D_S or D_W with compressed links from ``compress_links``."""
     op = op_code(op)
     _require(Vc, "Vc")
-    _require(psi, "psi")
+    _require(psi, "psi", Vc)
     if _dtype_code(Vc) != _dtype_code(psi):
         raise ValueError("Vc and psi must have the same storage dtype")
     vs, ps = _core_shape(Vc), _core_shape(psi)
@@ -258,7 +260,7 @@ def apply_compressed(op, Vc: torch.Tensor, psi: torch.Tensor, mass: float = 0.0,
     if out is None:
         out = torch.empty_like(psi)
     else:
-        _require(out, "out")
+        _require(out, "out", psi)
         if out.shape != psi.shape or out.dtype != psi.dtype:
             raise ValueError("out must match psi in shape and dtype")
     _check(_lib.dslash_apply_compressed(op, _ptr(Vc), _ptr(psi), _ptr(out), _dims_c(vs), 3, nv, float(mass),
@@ -288,7 +290,7 @@ def backward(op, U: torch.Tensor, grad_out: torch.Tensor, psi: torch.Tensor, mas
     """(grad_U, grad_in) of out = D[U] psi for upstream gradient grad_out."""
     op = op_code(op)
     lat, nv = _validate(op, U, psi)
-    _require(grad_out, "grad_out")
+    _require(grad_out, "grad_out", psi)
     if grad_out.shape != psi.shape or grad_out.dtype != psi.dtype:
         raise ValueError("grad_out must match psi in shape and dtype")
     gU = torch.empty_like(U) if need_grad_U else None
@@ -328,14 +330,14 @@ def brillouin_links_backward(V: torch.Tensor, grad_W: torch.Tensor, W: torch.Ten
     if (W is None) != (method == "walk"):
         raise ValueError(f"method {method!r} {'takes no' if method == 'walk' else 'needs'} W")
     _require(V, "V")
-    _require(grad_W, "grad_W")
+    _require(grad_W, "grad_W", V)
     vs = _core_shape(V)
     if len(vs) != 7 or vs[4:] != (4, 3, 3):
         raise ValueError(f"V must have shape [Nt,Nz,Ny,Nx,4,3,3], got {vs}")
-    if tuple(grad_W.shape) != vs[:4] + (40, 3, 3) or grad_W.dtype != V.dtype:
-        raise ValueError("grad_W must be [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
+    if tuple(grad_W.shape) != vs[:4] + (40, 3, 3) or grad_W.dtype != V.dtype or grad_W.device != V.device:
+        raise ValueError("grad_W must be [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V, on its device")
     if W is not None:
-        _require(W, "W")
+        _require(W, "W", V)
         if W.shape != grad_W.shape or W.dtype != V.dtype or W.device != V.device:
             raise ValueError("W must be brillouin_links(V): [Nt,Nz,Ny,Nx,40,3,3] in the dtype of V")
     gV = torch.empty_like(V)
@@ -490,7 +492,7 @@ def eo_pack(field: torch.Tensor):
 def eo_unpack(even: torch.Tensor, odd: torch.Tensor) -> torch.Tensor:
     """Full-lattice field from its packed even and odd halves."""
     _require(even, "even")
-    _require(odd, "odd")
+    _require(odd, "odd", even)
     if even.shape != odd.shape or even.dtype != odd.dtype:
         raise ValueError("even and odd halves must match in shape and dtype")
     nt, nz, ny, nh = even.shape[:4]
@@ -504,7 +506,7 @@ def eo_hop(U_even: torch.Tensor, U_odd: torch.Tensor, psi: torch.Tensor, parity_
            adjoint: bool = False) -> torch.Tensor:
     """H psi on the packed sites of parity parity_out; psi packed on the other parity."""
     for t, n in ((U_even, "U_even"), (U_odd, "U_odd"), (psi, "psi")):
-        _require(t, n)
+        _require(t, n, U_even)
     cs = _core_shape(psi)
     if len(cs) != 7 or cs[4:6] != (4, 3):
         raise ValueError(f"psi must be packed [Nt,Nz,Ny,Nx/2,4,3,Nv], got {cs}")
