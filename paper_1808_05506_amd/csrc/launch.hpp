@@ -23,6 +23,7 @@ struct Knob {
 };
 struct Knobs {
   Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra, cg_fuse;
+  Knob grad_tile_y, grad_tile_z;
 };
 inline Knob read_knob(const char* name) {
   Knob k;
@@ -44,6 +45,8 @@ inline Knobs read_knobs() {
   r.rows = read_knob("DSLASH_ROWS");
   r.row_lds_extra = read_knob("DSLASH_ROW_LDS_EXTRA");
   r.cg_fuse = read_knob("DSLASH_CG_FUSE");
+  r.grad_tile_y = read_knob("DSLASH_GRAD_TILE_Y");
+  r.grad_tile_z = read_knob("DSLASH_GRAD_TILE_Z");
   return r;
 }
 inline Knobs& knob_store() {

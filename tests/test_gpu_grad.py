@@ -132,3 +132,22 @@ def test_link_grad_rows_determinism_across_chunk_sizes(op, monkeypatch):
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), grad.link_grad(op, chi, psi), dt, f"grad_U rows R sweep {op}")
+
+
+def test_link_grad_wilson_tile_orders(monkeypatch):
+    # the D_W gradient's chunk order in (y, z) tiles (the default: 6 x 2 here)
+    # against other tiles and the t-band order ("0"): the same arithmetic per
+    # chunk, so the same bits, over several tiles and 10 + 10 site chunks
+    dims, nv, dt = (20, 6, 4, 5), 12, "c64"
+    u, chi, psi = _fields("wilson", dims, nv, 420, dt)
+    U, C, P = up(u, dt), up(chi, dt), up(psi, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    outs = []
+    for by, bz in ((None, None), ("3", "2"), ("2", "4"), ("6", "1"), ("1", "1"), ("0", "0")):
+        set_knob(monkeypatch, "DSLASH_GRAD_TILE_Y", by)
+        set_knob(monkeypatch, "DSLASH_GRAD_TILE_Z", bz)
+        say(f"case link grad wilson tile {by} x {bz}")
+        outs.append(D.backward("wilson", U, C, P, 0.0, need_grad_in=False)[0].cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), grad.link_grad("wilson", chi, psi), dt, "grad_U tile orders")
