@@ -23,7 +23,7 @@ struct Knob {
 };
 struct Knobs {
   Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra, cg_fuse;
-  Knob grad_tile_y, grad_tile_z;
+  Knob grad_tile_y, grad_tile_z, march_tile_y, march_tile_z;
 };
 inline Knob read_knob(const char* name) {
   Knob k;
@@ -47,6 +47,8 @@ inline Knobs read_knobs() {
   r.cg_fuse = read_knob("DSLASH_CG_FUSE");
   r.grad_tile_y = read_knob("DSLASH_GRAD_TILE_Y");
   r.grad_tile_z = read_knob("DSLASH_GRAD_TILE_Z");
+  r.march_tile_y = read_knob("DSLASH_MARCH_TILE_Y");
+  r.march_tile_z = read_knob("DSLASH_MARCH_TILE_Z");
   return r;
 }
 inline Knobs& knob_store() {

@@ -420,3 +420,25 @@ def test_fields_off_16_byte_alignment(op):
         ref = (wilson if op == "wilson" else staggered).apply(u, p, 0.1)
         compare(down(Om), ref, dt, f"{op} misaligned nv={nv}")
         compare(down(aligned), ref, dt, f"{op} aligned nv={nv}")
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_staggered_march_tile_orders(dt, monkeypatch):
+    # the D_S march's workgroups in (y, z) tiles (default: eight tiles, here
+    # 1 x 3), other tiles and the plain order ("0"): the same arithmetic per
+    # workgroup, so the same bits; 20-site rows in two chunks, t segments of 4
+    # with a short last one
+    dims, nv = (20, 4, 6, 10), 12
+    u, p = _stag_fields(dims, nv, 95, 96, dt)
+    U, P = up(u, dt), up(p, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "4")
+    outs = []
+    for by, bz in ((None, None), ("1", "1"), ("4", "2"), ("2", "6"), ("0", "0")):
+        set_knob(monkeypatch, "DSLASH_MARCH_TILE_Y", by)
+        set_knob(monkeypatch, "DSLASH_MARCH_TILE_Z", bz)
+        say(f"case staggered march tile {by} x {bz} {dt}")
+        outs.append(D.apply("staggered", U, P, 0.05).cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), staggered.apply(u, p, 0.05), dt, "D_S march tile orders")
