@@ -14,6 +14,7 @@
 
 #include "launch.hpp"
 #include "rows.hpp"
+#include "tiles.hpp"
 
 namespace dsl {
 
@@ -292,7 +293,7 @@ template <int NV> struct BriWaves { static constexpr int value = NV < 8 ? 2 : 3;
 // off-axis links are built on the fly for every row.
 template <bool ADJ, bool CLOV, bool FLY, int NV, class S, class T>
 __global__ void __launch_bounds__(256, BriWaves<NV>::value)
-    brillouin_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ Wl,
+    brillouin_rows_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd, const typename S::word* __restrict__ Wl,
                           const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                           const typename S::word* __restrict__ C, T diag) {
   using W = typename S::word;
@@ -305,7 +306,7 @@ __global__ void __launch_bounds__(256, BriWaves<NV>::value)
   W* lcl = wbuf + ((27 * R + 3) & ~3);  // [R][36] (CLOV), 16-byte aligned
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
@@ -354,18 +355,46 @@ __global__ void __launch_bounds__(256, BriWaves<NV>::value)
   }
 }
 
+// Chunk tiles of the D_B row kernels: the largest by x bz rows (by | Ny,
+// bz | Nz) whose spinor rows at one t take at most 1.25 MB, the squarer of
+// equal sizes, by >= bz on a tie; DSLASH_BRI_TILE_Y, _Z override (0: t-band
+// order).  Each output row stages the 27 rows around it, and in the t-band
+// order its +-z rows were a band of planes away, gone from the XCD's L2.  On
+// 32^4, N_v = 12: FP64 4 x 4, 16.72 against 17.77 ms (2 x 2: 18.00, 8 x 8:
+// 17.03); FP32 8 x 4, 7.09 against 7.39 ms (4 x 4: 7.18, 8 x 8: 7.21); W on
+// the fly 23.8 against 24.5 ms.  The W-gradient kernel gained nothing (6.96
+// ms either way) and keeps the t-band order (tiled = false).
+static ChunkTiles bri_tiles(const Geom& g, int R, long site_bytes, bool tiled = true) {
+  const long row_bytes = long((g.n[0] + R - 1) / R) * R * site_bytes;
+  const long max_rows = tiled ? 1280L * 1024 / row_bytes : 0;
+  int by = 0, bz = 0;
+  for (int y = 1; y <= g.n[1]; ++y) {
+    if (g.n[1] % y) continue;
+    for (int z = 1; z <= g.n[2]; ++z) {
+      if (g.n[2] % z || long(y) * z > max_rows) continue;
+      const int a = y * z, b = by * bz, d = y > z ? y - z : z - y, e = by > bz ? by - bz : bz - by;
+      if (a > b || (a == b && (d < e || (d == e && y > by)))) {
+        by = y;
+        bz = z;
+      }
+    }
+  }
+  return make_chunk_tiles(g, R, knobs().bri_tile_y.get(by), knobs().bri_tile_z.get(bz));
+}
+
 // CLOVER_OK = false builds the form without the clover term only (C must be null).
 template <int NV, class S, class T, bool FLY, bool CLOVER_OK = true>
 static hipError_t brillouin_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, const void* Wl, const void* in,
                                    void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const ChunkTiles o = bri_tiles(g, R, 12L * NV * long(sizeof(W)));
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
   const size_t lds =
       (size_t(R + 2) * SiteStride<NV, S>::WORDS + size_t(3 * R) * 9 + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   const T diag = T(mass) + T(15.0 / 8.0);
 #define DSL_BK(A, CL)                                                                                        \
-  hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, FLY, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)Wl, \
+  hipLaunchKernelGGL((brillouin_rows_kernel<A, CL, FLY, NV, S, T>), grid, block, lds, st, g, tr, o, int(xcd), (const W*)Wl, \
                      (const W*)in, (W*)out, (const W*)C, diag)
   if constexpr (CLOVER_OK) {
     if (C) {
@@ -462,7 +491,7 @@ __device__ __forceinline__ void bri_lds_spinor(const typename S::word* site, int
 
 template <int NV, class S, class T>
 __global__ void __launch_bounds__(256, 3)
-    bri_wgrad_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ chi,
+    bri_wgrad_rows_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd, const typename S::word* __restrict__ chi,
                           const typename S::word* __restrict__ psi, typename S::word* __restrict__ GW) {
   using W = typename S::word;
   constexpr int SSW = SiteStride<NV, S>::WORDS;
@@ -472,7 +501,7 @@ __global__ void __launch_bounds__(256, 3)
   T* red = reinterpret_cast<T*>(bs + (R + 2) * SSW);  // [3][R][18][NV]
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
@@ -558,9 +587,10 @@ static hipError_t brillouin_wgrad_rows_t(const Geom& g, int R, int bt, bool xcd,
                                          void* GW, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const ChunkTiles o = bri_tiles(g, R, 12L * NV * long(sizeof(W)), false);
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
   const size_t lds = size_t(R + 2) * SiteStride<NV, S>::WORDS * sizeof(W) + size_t(3 * R) * 18 * NV * sizeof(T);
-  hipLaunchKernelGGL((bri_wgrad_rows_kernel<NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)chi,
+  hipLaunchKernelGGL((bri_wgrad_rows_kernel<NV, S, T>), grid, block, lds, st, g, tr, o, int(xcd), (const W*)chi,
                      (const W*)psi, (W*)GW);
   return hipGetLastError();
 }
@@ -694,7 +724,7 @@ constexpr size_t kDmaRowBytes = (size_t(kDmaSites + 2) * 12 * 12 + size_t(27) * 
 // while the others do the same out of step.
 template <bool ADJ, int NV>
 __global__ void __launch_bounds__(kDmaSites * NV, 3)
-    brillouin_rows_dma_kernel(Geom g, RowTraversal tr, int xcd, const C128::word* __restrict__ Wl,
+    brillouin_rows_dma_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd, const C128::word* __restrict__ Wl,
                               const C128::word* __restrict__ in, C128::word* __restrict__ out, double diag) {
   using T = double;
   constexpr int SW = 12 * NV;
@@ -703,7 +733,7 @@ __global__ void __launch_bounds__(kDmaSites * NV, 3)
   char* const wbuf = buf + size_t(kDmaSites + 2) * SW * 16;   // [3][16][9] pieces: its link columns
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v;
   const int wave = tid >> 6, lane = tid & 63, waves = kDmaSites * NV / 64;
@@ -784,11 +814,12 @@ hipError_t launch_brillouin_rows(bool adj, int dtype, const Geom& g, const void*
   if (dtype == DT_C128 && g.nv == 12 && !clover) {
     // FP64: the direct-to-LDS staged kernel, chunks of 16 sites
     const RowTraversal tr = make_row_traversal(g, uint32_t(kDmaSites), uint32_t(knobs().tband.get(2)));
+    const ChunkTiles o = bri_tiles(g, kDmaSites, 12L * 12 * long(sizeof(C128::word)));
     const dim3 block(12, kDmaSites), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
     const bool xcd = knobs().xcd.get(1) != 0;
     const double diag = mass + 15.0 / 8.0;
 #define DSL_BD(A)                                                                                         \
-  hipLaunchKernelGGL((brillouin_rows_dma_kernel<A, 12>), grid, block, kDmaRowBytes, st, g, tr, int(xcd), \
+  hipLaunchKernelGGL((brillouin_rows_dma_kernel<A, 12>), grid, block, kDmaRowBytes, st, g, tr, o, int(xcd), \
                      (const C128::word*)Wl, (const C128::word*)in, (C128::word*)out, diag)
     if (adj) DSL_BD(true); else DSL_BD(false);
 #undef DSL_BD

@@ -15,6 +15,7 @@
 
 #include "launch.hpp"
 #include "rows.hpp"
+#include "tiles.hpp"
 
 namespace dsl {
 
@@ -70,43 +71,10 @@ __device__ __forceinline__ void grad_term(const typename S::word* nb, const cpx<
   }
 }
 
-// Chunk order in tiles of by x bz (y, z) rows: the chunks of one tile's rows
-// at one t, then at the next t, and tile after tile.  When each XCD takes a
-// contiguous range of this order, the +y, +z and +t rows a chunk stages are
-// the own rows of chunks that run shortly before or after it on the same XCD,
-// so they are still in that XCD's L2; the t-band order instead reaches the
-// +z row a whole band of planes later.
-struct GradTiles {
-  uint32_t on, chunks, by, bz, tiles_y;
-};
-
-DSL_HD RowChunk tile_chunk(const Geom& g, const GradTiles& o, uint32_t sb, uint32_t L) {
-  const uint32_t per_row = o.chunks * o.by;
-  const uint32_t per_t = per_row * o.bz;
-  const uint32_t per_tile = per_t * uint32_t(g.n[3]);
-  const uint32_t tile = L / per_tile;
-  uint32_t r = L - tile * per_tile;
-  const uint32_t t = r / per_t;
-  r -= t * per_t;
-  const uint32_t zz = r / per_row;
-  r -= zz * per_row;
-  const uint32_t yy = r / o.chunks;
-  const uint32_t chunk = r - yy * o.chunks;
-  const uint32_t tz = tile / o.tiles_y, ty = tile - tz * o.tiles_y;
-  RowChunk c;
-  c.x0 = int(chunk * sb);
-  c.n = g.n[0] - c.x0 < int(sb) ? g.n[0] - c.x0 : int(sb);
-  c.y = int(ty * o.by + yy);
-  c.z = int(tz * o.bz + zz);
-  c.t = int(t);
-  c.row_base = uint32_t(g.n[0]) * (uint32_t(c.y) + uint32_t(g.n[1]) * (uint32_t(c.z) + uint32_t(g.n[2]) * t));
-  return c;
-}
-
 }  // namespace
 
 template <int OP, int NV, class S, class T>
-__global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal tr, GradTiles o, int xcd,
+__global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd,
                                                           const typename S::word* __restrict__ chi,
                                                           const typename S::word* __restrict__ psi,
                                                           typename S::word* __restrict__ G) {
@@ -121,7 +89,7 @@ __global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal 
   W* gout = reinterpret_cast<W*>(red + R * 9 * NV);                  // [R][36]
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = o.on ? tile_chunk(g, o, tr.sb, L) : row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const uint32_t own_base = c.row_base + uint32_t(c.x0);
@@ -234,7 +202,7 @@ __global__ void __launch_bounds__(256, 3) grad_rows_kernel(Geom g, RowTraversal 
 }
 
 template <int OP, int NV, class S, class T>
-static hipError_t grad_rows_t(const Geom& g, int R, int bt, const GradTiles& o, bool xcd, const void* chi,
+static hipError_t grad_rows_t(const Geom& g, int R, int bt, const ChunkTiles& o, bool xcd, const void* chi,
                               const void* psi, void* G, hipStream_t st) {
   using W = typename S::word;
   constexpr int COMPS = OP == OP_WILSON ? 12 : 3;
@@ -248,7 +216,7 @@ static hipError_t grad_rows_t(const Geom& g, int R, int bt, const GradTiles& o, 
 }
 
 template <int NV>
-static hipError_t grad_rows_nv(int op, int dtype, const Geom& g, int R, int bt, const GradTiles& o, bool xcd,
+static hipError_t grad_rows_nv(int op, int dtype, const Geom& g, int R, int bt, const ChunkTiles& o, bool xcd,
                                const void* chi, const void* psi, void* G, hipStream_t st) {
   if (op == OP_WILSON) return grad_rows_t<OP_WILSON, NV, C64, float>(g, R, bt, o, xcd, chi, psi, G, st);
   if (dtype == DT_C64) return grad_rows_t<OP_STAGGERED, NV, C64, float>(g, R, bt, o, xcd, chi, psi, G, st);
@@ -301,16 +269,9 @@ hipError_t launch_grad_rows(int op, int dtype, const Geom& g, const void* chi, c
   bt = knobs().tband.get(bt);
   bool xcd = true;
   xcd = knobs().xcd.get(xcd) != 0;
-  GradTiles o{};
   int by = 0, bz = 0;
   if (op == OP_WILSON) grad_tile_default(g, R, nv, by, bz);
-  o.by = uint32_t(knobs().grad_tile_y.get(by));
-  o.bz = uint32_t(knobs().grad_tile_z.get(bz));
-  if (o.by > 0 && o.bz > 0 && g.n[1] % int(o.by) == 0 && g.n[2] % int(o.bz) == 0) {
-    o.on = 1;
-    o.chunks = uint32_t((g.n[0] + R - 1) / R);
-    o.tiles_y = uint32_t(g.n[1]) / o.by;
-  }
+  const ChunkTiles o = make_chunk_tiles(g, R, knobs().grad_tile_y.get(by), knobs().grad_tile_z.get(bz));
   switch (nv) {
     case 4: return grad_rows_nv<4>(op, dtype, g, R, bt, o, xcd, chi, psi, G, st);
     case 8: return grad_rows_nv<8>(op, dtype, g, R, bt, o, xcd, chi, psi, G, st);

@@ -23,7 +23,7 @@ struct Knob {
 };
 struct Knobs {
   Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra, cg_fuse;
-  Knob grad_tile_y, grad_tile_z, march_tile_y, march_tile_z;
+  Knob grad_tile_y, grad_tile_z, march_tile_y, march_tile_z, bri_tile_y, bri_tile_z;
 };
 inline Knob read_knob(const char* name) {
   Knob k;
@@ -49,6 +49,8 @@ inline Knobs read_knobs() {
   r.grad_tile_z = read_knob("DSLASH_GRAD_TILE_Z");
   r.march_tile_y = read_knob("DSLASH_MARCH_TILE_Y");
   r.march_tile_z = read_knob("DSLASH_MARCH_TILE_Z");
+  r.bri_tile_y = read_knob("DSLASH_BRI_TILE_Y");
+  r.bri_tile_z = read_knob("DSLASH_BRI_TILE_Z");
   return r;
 }
 inline Knobs& knob_store() {

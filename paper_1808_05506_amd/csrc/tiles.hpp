@@ -1,0 +1,59 @@
+// Chunk order of the one-row kernels in tiles of by x bz (y, z) rows: the
+// chunks of a tile's rows at one t, then at the next t, tile after tile.  The
+// XCD mapping (xcd_block) gives each XCD a contiguous range of this order, so
+// the neighbour rows a chunk stages (+-y, +-z, +-t) are mostly the own rows of
+// chunks that run shortly before or after it on the same XCD and are still in
+// its L2; the t-band order of RowTraversal reaches the z neighbours a whole
+// band of planes later.  The grid is the same (chunks x Ny x Nz x Nt).
+#pragma once
+
+#include "rows.hpp"
+
+namespace dsl {
+
+struct ChunkTiles {
+  uint32_t on, chunks, by, bz, tiles_y;
+};
+
+// by | Ny and bz | Nz, both > 0, else the tiles are off (t-band order).
+inline ChunkTiles make_chunk_tiles(const Geom& g, int R, int by, int bz) {
+  ChunkTiles o{};
+  if (by > 0 && bz > 0 && g.n[1] % by == 0 && g.n[2] % bz == 0) {
+    o.on = 1;
+    o.chunks = uint32_t((g.n[0] + R - 1) / R);
+    o.by = uint32_t(by);
+    o.bz = uint32_t(bz);
+    o.tiles_y = uint32_t(g.n[1] / by);
+  }
+  return o;
+}
+
+DSL_HD RowChunk tile_chunk(const Geom& g, const ChunkTiles& o, uint32_t sb, uint32_t L) {
+  const uint32_t per_row = o.chunks * o.by;
+  const uint32_t per_t = per_row * o.bz;
+  const uint32_t per_tile = per_t * uint32_t(g.n[3]);
+  const uint32_t tile = L / per_tile;
+  uint32_t r = L - tile * per_tile;
+  const uint32_t t = r / per_t;
+  r -= t * per_t;
+  const uint32_t zz = r / per_row;
+  r -= zz * per_row;
+  const uint32_t yy = r / o.chunks;
+  const uint32_t chunk = r - yy * o.chunks;
+  const uint32_t tz = tile / o.tiles_y, ty = tile - tz * o.tiles_y;
+  RowChunk c;
+  c.x0 = int(chunk * sb);
+  c.n = g.n[0] - c.x0 < int(sb) ? g.n[0] - c.x0 : int(sb);
+  c.y = int(ty * o.by + yy);
+  c.z = int(tz * o.bz + zz);
+  c.t = int(t);
+  c.row_base = uint32_t(g.n[0]) * (uint32_t(c.y) + uint32_t(g.n[1]) * (uint32_t(c.z) + uint32_t(g.n[2]) * t));
+  return c;
+}
+
+// The chunk of logical block L: tiled order when o.on, else the t-band order.
+DSL_HD RowChunk order_chunk(const Geom& g, const RowTraversal& tr, const ChunkTiles& o, uint32_t L) {
+  return o.on ? tile_chunk(g, o, tr.sb, L) : row_chunk(g, tr, L);
+}
+
+}  // namespace dsl

@@ -442,3 +442,27 @@ def test_staggered_march_tile_orders(dt, monkeypatch):
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), staggered.apply(u, p, 0.05), dt, "D_S march tile orders")
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_brillouin_tile_orders(dt, monkeypatch):
+    # the D_B row kernels' chunks in (y, z) tiles (default here: the whole
+    # 6 x 4 plane in FP32, 3 x 4 in FP64), other tiles and the t-band order
+    # ("0"): the
+    # same arithmetic per chunk, so the same bits; FP32 in chunks of 12 + 12,
+    # FP64 (direct-to-LDS kernel) in 16 + 8
+    dims, nv = (24, 6, 4, 3), 12
+    v = synthetic.gauge_links(dims, "haar", 37)
+    w = rounded(brillouin.build(v), dt)
+    p = rounded(synthetic.wilson_spinor(dims, nv, 38), dt)
+    W, P = up(w, dt), up(p, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    outs = []
+    for by, bz in ((None, None), ("2", "2"), ("3", "1"), ("1", "4"), ("0", "0")):
+        set_knob(monkeypatch, "DSLASH_BRI_TILE_Y", by)
+        set_knob(monkeypatch, "DSLASH_BRI_TILE_Z", bz)
+        say(f"case brillouin tile {by} x {bz} {dt}")
+        outs.append(D.apply("brillouin", W, P, 0.1).cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(outs[0].numpy().astype(np.complex128), brillouin.apply(w, p, 0.1), dt, "D_B tile orders")
