@@ -76,7 +76,7 @@ def site_bytes(op: str, nv: int, eb: int, compressed: bool = False) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("dslash_common.hpp", "stencils.hpp", "rows.hpp", "apply.hip", "apply_rows.hip"):
+    for f in ("dslash_common.hpp", "stencils.hpp", "rows.hpp", "tiles.hpp", "apply.hip", "apply_rows.hip"):
         with open(os.path.join(ROOT, "paper_1808_05506_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -10,6 +10,7 @@
 
 #include "launch.hpp"
 #include "rows.hpp"
+#include "tiles.hpp"
 
 namespace dsl {
 
@@ -443,7 +444,7 @@ template <int DEPTH> struct RowsWaves { static constexpr int value = DEPTH <= 2 
 // site, staged in LDS after lnb).
 template <int DEPTH, bool ADJ, bool CLOV, int NV, class S, class T>
 __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
-    wilson_rows_kernel(Geom g, RowTraversal tr, int xcd, const typename S::word* __restrict__ U,
+    wilson_rows_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd, const typename S::word* __restrict__ U,
                        const typename S::word* __restrict__ in, typename S::word* __restrict__ out,
                        const typename S::word* __restrict__ C, T diag) {
   using W = typename S::word;
@@ -457,7 +458,7 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   W* lcl = lnb + ((R * 9 + 3) & ~3);  // [R][36] clover words of the chunk's sites (CLOV), 16-byte aligned
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
@@ -1176,7 +1177,7 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
 // Forward links come from Uo (parity p), backward ones from Ui (parity 1 - p).
 template <int DEPTH, bool ADJ, int NV, class S, class T, int EPI = EPI_STORE>
 __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
-    wilson_eo_rows_kernel(Geom g, RowTraversal tr, int xcd, int p, const typename S::word* __restrict__ Uo,
+    wilson_eo_rows_kernel(Geom g, RowTraversal tr, ChunkTiles o, int xcd, int p, const typename S::word* __restrict__ Uo,
                           const typename S::word* __restrict__ Ui, const typename S::word* __restrict__ in,
                           typename S::word* __restrict__ out, const typename S::word* __restrict__ add, T c_add,
                           T c_hop, EpiArgs ea) {
@@ -1191,7 +1192,7 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   W* lxb = lnb + R * 9;           // [R][9]: V_x(x - 1) from Ui
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const RowChunk c = row_chunk(g, tr, L);
+  const RowChunk c = order_chunk(g, tr, o, L);
   const int v = threadIdx.x, xl = threadIdx.y;
   const int tid = xl * NV + v, nth = R * NV;
   const int xm = wrap_x(g, c.x0 - 1), xp = wrap_x(g, c.x0 + c.n);
@@ -1297,18 +1298,44 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
   }
 }
 
+// Chunk tiles of the one-row D_W kernels: the largest by x bz rows (by | Ny,
+// bz | Nz) whose spinor rows at one t take at most 1.25 MB, the squarer of
+// equal sizes, by >= bz on a tie; DSLASH_ROWS_TILE_Y, _Z override (0: t-band
+// order).  The even-odd hop on 32^3 x 64 (N_v = 12, 8 x 8 tiles) took 890
+// against 948 us in FP32 and 547 against 557 us in BF16; the kernel with the
+// clover term on 16^3 x 32 took 102 against 99 us and keeps the t-band order
+// (tiled = false).
+static ChunkTiles rows_tiles(const Geom& g, int R, long site_bytes, bool tiled) {
+  const long row_bytes = long((g.n[0] + R - 1) / R) * R * site_bytes;
+  const long max_rows = tiled ? 1280L * 1024 / row_bytes : 0;
+  int by = 0, bz = 0;
+  for (int y = 1; y <= g.n[1]; ++y) {
+    if (g.n[1] % y) continue;
+    for (int z = 1; z <= g.n[2]; ++z) {
+      if (g.n[2] % z || long(y) * z > max_rows) continue;
+      const int a = y * z, b = by * bz, d = y > z ? y - z : z - y, e = by > bz ? by - bz : bz - by;
+      if (a > b || (a == b && (d < e || (d == e && y > by)))) {
+        by = y;
+        bz = z;
+      }
+    }
+  }
+  return make_chunk_tiles(g, R, knobs().rows_tile_y.get(by), knobs().rows_tile_z.get(bz));
+}
+
 template <int NV, class S, class T>
 static hipError_t wilson_eo_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd, int parity, const void* Uo,
                                    const void* Ui, const void* in, void* out, const void* add, double c_add,
                                    double c_hop, hipStream_t st, int epi, EpiArgs& ea) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const ChunkTiles o = rows_tiles(g, R, 12L * NV * long(sizeof(W)), true);
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
   if (epi != EPI_STORE && grid.x > ea.capacity) return hipErrorNotSupported;
   ea.blocks = grid.x;
   const size_t lds = (rows_lds_words<NV, S>(R) + size_t(R) * 9) * sizeof(W);
 #define DSL_EK(A, E)                                                                                          \
-  hipLaunchKernelGGL((wilson_eo_rows_kernel<3, A, NV, S, T, E>), grid, block, lds, st, g, tr, int(xcd), parity, \
+  hipLaunchKernelGGL((wilson_eo_rows_kernel<3, A, NV, S, T, E>), grid, block, lds, st, g, tr, o, int(xcd), parity, \
                      (const W*)Uo, (const W*)Ui, (const W*)in, (W*)out, (const W*)add, T(c_add), T(c_hop), ea)
   // fused epilogues: the Schur operator M with EPI_NORM, M^dag with EPI_AXPY
   if (epi == EPI_STORE) {
@@ -1383,13 +1410,14 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
                                 void* out, const void* C, double mass, hipStream_t st) {
   using W = typename S::word;
   const RowTraversal tr = make_row_traversal(g, uint32_t(R), uint32_t(bt));
+  const ChunkTiles o = rows_tiles(g, R, 12L * NV * long(sizeof(W)), false);
   const dim3 block(NV, R), grid(tr.rows_plane * uint32_t(g.n[2]) * uint32_t(g.n[3]));
   size_t lds = (rows_lds_words<NV, S>(R) + (C ? 3 + size_t(R) * 36 : 0)) * sizeof(W);
   // DSLASH_ROW_LDS_EXTRA (bytes) lowers the workgroups per CU (tuning).
   lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
 #define DSL_RK(A, CL)                                                                                      \
-  hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, A, CL, NV, S, T>), grid, block, lds, st, g, tr, int(xcd), (const W*)U, \
+  hipLaunchKernelGGL((wilson_rows_kernel<DEPTH, A, CL, NV, S, T>), grid, block, lds, st, g, tr, o, int(xcd), (const W*)U, \
                      (const W*)in, (W*)out, (const W*)C, diag)
   if (C) {
     if (adj) DSL_RK(true, true); else DSL_RK(false, true);

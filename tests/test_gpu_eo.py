@@ -127,3 +127,25 @@ def test_solve_eo(inner, itol, dims, nv):
     _, full = D.solve("wilson", up(u, "c128"), up(b, "c128"), m0, inner=inner, tol=1e-10, inner_tol=itol)
     say(f"inner iterations: eo {info['inner_iters']}, full {full['inner_iters']}")
     assert info["inner_iters"] < full["inner_iters"]
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16"])
+def test_eo_hop_tile_orders(dt, monkeypatch):
+    # the row-staged hop's chunks in (y, z) tiles (the default), other tiles
+    # and the t-band order ("0"): the same arithmetic per chunk, so the same
+    # bits; packed rows of 27 sites in chunks of 14 + 13, several tiles
+    dims = (54, 4, 6, 2)
+    say(f"case eo hop tile orders {dims} {dt}")
+    u = rounded(synthetic.gauge_links(dims, "haar", 74), dt)
+    p = rounded(synthetic.wilson_spinor(dims, 12, 75), dt)
+    pin = evenodd.pack(p, 0)
+    Ue, Uo, Pin = up(evenodd.pack(u, 0), dt), up(evenodd.pack(u, 1), dt), up(pin, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    outs = []
+    for by, bz in ((None, None), ("1", "1"), ("2", "3"), ("4", "2"), ("0", "0")):
+        set_knob(monkeypatch, "DSLASH_ROWS_TILE_Y", by)
+        set_knob(monkeypatch, "DSLASH_ROWS_TILE_Z", bz)
+        outs.append(D.eo_hop(Ue, Uo, Pin, 1).cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(down(outs[0]), evenodd.hop_eo(u, pin, 1, False), dt, "eo hop tile orders")
