@@ -566,7 +566,7 @@ hipError_t launch_cg_update_r(int dtype, void* r, const void* s_, const double* 
 // e += alpha[v] p;  p = r + beta[v] p  (the old p in both), FP32 arithmetic.
 // Vectorised: thread (cx, y) of a (nv / VW, ry) block keeps the columns
 // cx VW .. cx VW + VW - 1 (as in the reductions).
-template <class S>
+template <class S, bool NT = false>
 __global__ void __launch_bounds__(256) cg_update_ep_vec_kernel(u32x4* __restrict__ e, u32x4* __restrict__ p,
                                                                const u32x4* __restrict__ r,
                                                                const double* __restrict__ alpha,
@@ -583,17 +583,28 @@ __global__ void __launch_bounds__(256) cg_update_ep_vec_kernel(u32x4* __restrict
   }
   for (size_t c = g0; c < chunks; c += G) {
     W we[VW], wp[VW], wr[VW];
-    Vec<S>::unpack(e[c], we);
-    Vec<S>::unpack(p[c], wp);
-    Vec<S>::unpack(r[c], wr);
+    if constexpr (NT) {
+      Vec<S>::unpack(__builtin_nontemporal_load(&e[c]), we);
+      Vec<S>::unpack(__builtin_nontemporal_load(&p[c]), wp);
+      Vec<S>::unpack(__builtin_nontemporal_load(&r[c]), wr);
+    } else {
+      Vec<S>::unpack(e[c], we);
+      Vec<S>::unpack(p[c], wp);
+      Vec<S>::unpack(r[c], wr);
+    }
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
       const cpx<float> pv = S::template load<float>(&wp[k]);
       S::template store<float>(&we[k], rmadd(S::template load<float>(&we[k]), a[k], pv));
       S::template store<float>(&wp[k], rmadd(S::template load<float>(&wr[k]), b[k], pv));
     }
-    e[c] = Vec<S>::pack(we);
-    p[c] = Vec<S>::pack(wp);
+    if constexpr (NT) {
+      __builtin_nontemporal_store(Vec<S>::pack(we), &e[c]);
+      __builtin_nontemporal_store(Vec<S>::pack(wp), &p[c]);
+    } else {
+      e[c] = Vec<S>::pack(we);
+      p[c] = Vec<S>::pack(wp);
+    }
   }
 }
 
@@ -623,8 +634,15 @@ static hipError_t update_ep_t(void* e, void* p, const void* r, const double* alp
     size_t blocks = (chunks + size_t(cols) * ry - 1) / (size_t(cols) * ry);
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(cg_update_ep_vec_kernel<S>, dim3(unsigned(blocks)), dim3(cols, ry), 0, st, (u32x4*)e,
-                       (u32x4*)p, (const u32x4*)r, alpha, beta, chunks);
+    // non-temporal loads and stores for FP32 words (DSLASH_BLAS_NT overrides):
+    // on 32^3 x 64, N_v = 12 the full-lattice update took 2508 against 2674 us
+    // with them in C64, but 1412 against 1249 us in BF16 and FP16
+    if (knobs().blas_nt.get(sizeof(W) == 8 ? 1 : 0))
+      hipLaunchKernelGGL((cg_update_ep_vec_kernel<S, true>), dim3(unsigned(blocks)), dim3(cols, ry), 0, st,
+                         (u32x4*)e, (u32x4*)p, (const u32x4*)r, alpha, beta, chunks);
+    else
+      hipLaunchKernelGGL((cg_update_ep_vec_kernel<S, false>), dim3(unsigned(blocks)), dim3(cols, ry), 0, st,
+                         (u32x4*)e, (u32x4*)p, (const u32x4*)r, alpha, beta, chunks);
   } else {
     hipLaunchKernelGGL(cg_update_ep_kernel<S>, stream_grid(n), dim3(256), 0, st, (W*)e, (W*)p, (const W*)r, alpha,
                        beta, n, nv);
