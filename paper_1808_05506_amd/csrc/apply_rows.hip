@@ -1306,20 +1306,8 @@ __global__ void __launch_bounds__(256, RowsWaves<DEPTH>::value)
 // clover term on 16^3 x 32 took 102 against 99 us and keeps the t-band order
 // (tiled = false).
 static ChunkTiles rows_tiles(const Geom& g, int R, long site_bytes, bool tiled) {
-  const long row_bytes = long((g.n[0] + R - 1) / R) * R * site_bytes;
-  const long max_rows = tiled ? 1280L * 1024 / row_bytes : 0;
-  int by = 0, bz = 0;
-  for (int y = 1; y <= g.n[1]; ++y) {
-    if (g.n[1] % y) continue;
-    for (int z = 1; z <= g.n[2]; ++z) {
-      if (g.n[2] % z || long(y) * z > max_rows) continue;
-      const int a = y * z, b = by * bz, d = y > z ? y - z : z - y, e = by > bz ? by - bz : bz - by;
-      if (a > b || (a == b && (d < e || (d == e && y > by)))) {
-        by = y;
-        bz = z;
-      }
-    }
-  }
+  int by, bz;
+  pick_tile(g, long((g.n[0] + R - 1) / R) * R * site_bytes, tiled ? 1280L * 1024 : 0, by, bz);
   return make_chunk_tiles(g, R, knobs().rows_tile_y.get(by), knobs().rows_tile_z.get(bz));
 }
 

@@ -365,20 +365,8 @@ __global__ void __launch_bounds__(256, BriWaves<NV>::value)
 // the fly 23.8 against 24.5 ms.  The W-gradient kernel gained nothing (6.96
 // ms either way) and keeps the t-band order (tiled = false).
 static ChunkTiles bri_tiles(const Geom& g, int R, long site_bytes, bool tiled = true) {
-  const long row_bytes = long((g.n[0] + R - 1) / R) * R * site_bytes;
-  const long max_rows = tiled ? 1280L * 1024 / row_bytes : 0;
-  int by = 0, bz = 0;
-  for (int y = 1; y <= g.n[1]; ++y) {
-    if (g.n[1] % y) continue;
-    for (int z = 1; z <= g.n[2]; ++z) {
-      if (g.n[2] % z || long(y) * z > max_rows) continue;
-      const int a = y * z, b = by * bz, d = y > z ? y - z : z - y, e = by > bz ? by - bz : bz - by;
-      if (a > b || (a == b && (d < e || (d == e && y > by)))) {
-        by = y;
-        bz = z;
-      }
-    }
-  }
+  int by, bz;
+  pick_tile(g, long((g.n[0] + R - 1) / R) * R * site_bytes, tiled ? 1280L * 1024 : 0, by, bz);
   return make_chunk_tiles(g, R, knobs().bri_tile_y.get(by), knobs().bri_tile_z.get(bz));
 }
 

@@ -230,20 +230,7 @@ static hipError_t grad_rows_nv(int op, int dtype, const Geom& g, int R, int bt, 
 // 569 us; 12 x 2: 2.5 GB, 590 us).  D_S, whose rows are a quarter of the
 // size, gained nothing (212 against 206 us) and keeps the t-band order.
 static void grad_tile_default(const Geom& g, int R, int nv, int& by, int& bz) {
-  const long row_bytes = long((g.n[0] + R - 1) / R) * R * 2L * 12 * nv * 8;
-  const long max_rows = 2048L * 1024 / row_bytes;
-  by = bz = 0;
-  for (int y = 1; y <= g.n[1]; ++y) {
-    if (g.n[1] % y) continue;
-    for (int z = 1; z <= g.n[2]; ++z) {
-      if (g.n[2] % z || long(y) * z > max_rows) continue;
-      const int a = y * z, b = by * bz;
-      if (a > b || (a == b && (y > z ? y - z : z - y) < (by > bz ? by - bz : bz - by))) {
-        by = y;
-        bz = z;
-      }
-    }
-  }
+  pick_tile(g, long((g.n[0] + R - 1) / R) * R * 2L * 12 * nv * 8, 2048L * 1024, by, bz);
 }
 
 // Row-staged link gradient for N_v = 4, 8, 12, 16, 24: D_W in C64, D_S in C64

@@ -15,6 +15,25 @@ struct ChunkTiles {
   uint32_t on, chunks, by, bz, tiles_y;
 };
 
+// The largest by x bz rows (by | Ny, bz | Nz) whose rows at one t take at
+// most `budget` bytes (row_bytes each), the squarer of equal sizes and the
+// larger by of equally square ones; by = bz = 0 when no row fits.
+inline void pick_tile(const Geom& g, long row_bytes, long budget, int& by, int& bz) {
+  const long max_rows = row_bytes > 0 ? budget / row_bytes : 0;
+  by = bz = 0;
+  for (int y = 1; y <= g.n[1]; ++y) {
+    if (g.n[1] % y) continue;
+    for (int z = 1; z <= g.n[2]; ++z) {
+      if (g.n[2] % z || long(y) * z > max_rows) continue;
+      const int a = y * z, b = by * bz, d = y > z ? y - z : z - y, e = by > bz ? by - bz : bz - by;
+      if (a > b || (a == b && (d < e || (d == e && y > by)))) {
+        by = y;
+        bz = z;
+      }
+    }
+  }
+}
+
 // by | Ny and bz | Nz, both > 0, else the tiles are off (t-band order).
 inline ChunkTiles make_chunk_tiles(const Geom& g, int R, int by, int bz) {
   ChunkTiles o{};
