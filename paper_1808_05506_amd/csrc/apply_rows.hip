@@ -1486,7 +1486,10 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
   // Default: FP32 storage takes 3 (full or compressed links), BF16 storage 2,
   // FP16 storage and other compressed links one buffer; with FP32 storage, a
   // lattice whose 16-step grid fits at two workgroups per CU (all its
-  // workgroups resident at once) marches 16 steps, otherwise 8.
+  // workgroups resident at once) and still gives every SIMD 1.5 waves marches
+  // 16 steps, otherwise 8.  On 16^3 x 32: N_v = 12 and 16 take 16 steps
+  // (1536 and 2048 waves); N_v = 4 and 8 (512 and 1024 waves at 16 steps)
+  // took 44.4 and 65.6 us at 8 steps against 64.8 and 74.6 us at 16.
   int tsteps = 8;
   int pp = 0;
   if (knobs().tsteps.set) {
@@ -1497,7 +1500,8 @@ hipError_t launch_wilson_rows(bool adj, int dtype, const Geom& g, const void* U,
     if (dtype == DT_C64 && g.n[3] >= 16) {
       const MarchTraversal m16 = make_march_traversal(g, uint32_t(R), 16u);
       const uint32_t wgs = m16.rows * ((uint32_t(g.n[3]) + 15u) / 16u);
-      if (wgs <= 2u * uint32_t(device_cus())) tsteps = 16;
+      const uint32_t waves = wgs * uint32_t((R * nv + 63) / 64);
+      if (wgs <= 2u * uint32_t(device_cus()) && 2u * waves >= 3u * 4u * uint32_t(device_cus())) tsteps = 16;
     }
   }
   if (nv != 12) {
