@@ -1035,7 +1035,7 @@ template <int PP, int DEPTH> struct MarchOcc { static constexpr int value = PP ?
 
 template <int DEPTH, bool ADJ, int NV, class S, class T, int LW, int PP = 0, int EPI = EPI_STORE>
 __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
-    wilson_march_kernel(Geom g, MarchTraversal m, int xcd, const typename S::word* __restrict__ U,
+    wilson_march_kernel(Geom g, MarchTraversal m, MarchTiles o, int xcd, const typename S::word* __restrict__ U,
                         const typename S::word* __restrict__ in, typename S::word* __restrict__ out, T diag,
                         EpiArgs ea) {
   using W = typename S::word;
@@ -1052,8 +1052,8 @@ __global__ void __launch_bounds__(256, (MarchOcc<PP, DEPTH>::value))
   W* lnb1 = lnb + R * LW;  // PP only
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  const uint32_t seg = m.d_rows.div(L);
-  const uint32_t id = L - seg * m.rows;
+  uint32_t seg;
+  const uint32_t id = march_order_id(g, m, o, L, seg);
   const int t0 = int(seg * m.T);
   const int steps = g.n[3] - t0 < int(m.T) ? g.n[3] - t0 : int(m.T);
   RowChunk c = march_chunk(g, m, id, t0);
@@ -1115,11 +1115,11 @@ struct MarchEpiBuilt {
 
 template <int DEPTH, int NV, class S, class T, int LW, int PP>
 static hipError_t march_launch(bool adj, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Geom& g,
-                               const MarchTraversal& m, bool xcd, const void* U, const void* in, void* out, T diag,
-                               const EpiArgs& ea) {
+                               const MarchTraversal& m, const MarchTiles& o, bool xcd, const void* U, const void* in,
+                               void* out, T diag, const EpiArgs& ea) {
   using W = typename S::word;
-#define DSL_MK(A, E)                                                                                           \
-  hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, PP, E>), grid, block, lds, st, g, m, int(xcd), \
+#define DSL_MK(A, E)                                                                                              \
+  hipLaunchKernelGGL((wilson_march_kernel<DEPTH, A, NV, S, T, LW, PP, E>), grid, block, lds, st, g, m, o, int(xcd), \
                      (const W*)U, (const W*)in, (W*)out, diag, ea)
   if (epi == EPI_STORE) {
     if (adj) DSL_MK(true, EPI_STORE); else DSL_MK(false, EPI_STORE);
@@ -1132,6 +1132,19 @@ static hipError_t march_launch(bool adj, int epi, dim3 grid, dim3 block, size_t 
   }
 #undef DSL_MK
   return hipGetLastError();
+}
+
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
 }
 
 // ONLY_PP >= 0 builds that buffer scheme only (pp must equal it).
@@ -1151,19 +1164,26 @@ static hipError_t wilson_march_t(bool adj, const Geom& g, int R, int tsteps, int
   if (pp == 3) lds += (size_t(2 * R) * HalfStride<NV, S>::WORDS + size_t(R) * LW) * sizeof(W);
   lds += size_t(knobs().row_lds_extra.get(0));
   const T diag = T(4) + T(mass);
+  // Tiles of (y, z) rows, one per XCD, when the grid runs in more than one
+  // round (more than two workgroups per CU); a grid resident at once keeps
+  // the plane order.  DSLASH_WMARCH_TILE_Y, _Z override (0: plane order).
+  int by = 0, bz = 0;
+  if (grid.x > 2u * uint32_t(device_cus())) march_tile_default(g, by, bz);
+  const MarchTiles o =
+      make_march_tiles(g, m.chunks, nseg, knobs().wmarch_tile_y.get(by), knobs().wmarch_tile_z.get(bz));
   if constexpr (ONLY_PP >= 0) {
     if constexpr (ONLY_PP == 3 && !(sizeof(W) == 8 && NV % 2 == 0)) return hipErrorInvalidValue;
-    else return march_launch<DEPTH, NV, S, T, LW, ONLY_PP>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+    else return march_launch<DEPTH, NV, S, T, LW, ONLY_PP>(adj, epi, grid, block, lds, st, g, m, o, xcd, U, in, out, diag, ea);
   } else {
     switch (pp) {
       case 3:
         if constexpr (sizeof(W) == 8 && NV % 2 == 0)
-          return march_launch<DEPTH, NV, S, T, LW, 3>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+          return march_launch<DEPTH, NV, S, T, LW, 3>(adj, epi, grid, block, lds, st, g, m, o, xcd, U, in, out, diag, ea);
         else
           return hipErrorInvalidValue;
-      case 2: return march_launch<DEPTH, NV, S, T, LW, 2>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
-      case 1: return march_launch<DEPTH, NV, S, T, LW, 1>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
-      default: return march_launch<DEPTH, NV, S, T, LW, 0>(adj, epi, grid, block, lds, st, g, m, xcd, U, in, out, diag, ea);
+      case 2: return march_launch<DEPTH, NV, S, T, LW, 2>(adj, epi, grid, block, lds, st, g, m, o, xcd, U, in, out, diag, ea);
+      case 1: return march_launch<DEPTH, NV, S, T, LW, 1>(adj, epi, grid, block, lds, st, g, m, o, xcd, U, in, out, diag, ea);
+      default: return march_launch<DEPTH, NV, S, T, LW, 0>(adj, epi, grid, block, lds, st, g, m, o, xcd, U, in, out, diag, ea);
     }
   }
 }
@@ -1416,18 +1436,6 @@ static hipError_t wilson_rows_t(bool adj, const Geom& g, int R, int bt, bool xcd
   return hipGetLastError();
 }
 
-// Compute units of the current device (cached per device).
-static int device_cus() {
-  static int cus[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cus[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cus[dev] = n;
-  }
-  return cus[dev];
-}
 
 // Row-staged D_W with FP32 arithmetic (C64, BF16, F16 storage) for N_v = 4, 8,
 // 12, 16, 24.  Returns hipErrorNotSupported when the configuration is not

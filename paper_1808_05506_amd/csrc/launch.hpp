@@ -24,7 +24,7 @@ struct Knob {
 struct Knobs {
   Knob sites_per_block, tband, xcd, row_sites, row_depth, tsteps, march_pp, rows, row_lds_extra, cg_fuse;
   Knob grad_tile_y, grad_tile_z, march_tile_y, march_tile_z, bri_tile_y, bri_tile_z, rows_tile_y,
-      rows_tile_z, blas_nt;
+      rows_tile_z, blas_nt, wmarch_tile_y, wmarch_tile_z;
 };
 inline Knob read_knob(const char* name) {
   Knob k;
@@ -55,6 +55,8 @@ inline Knobs read_knobs() {
   r.rows_tile_y = read_knob("DSLASH_ROWS_TILE_Y");
   r.rows_tile_z = read_knob("DSLASH_ROWS_TILE_Z");
   r.blas_nt = read_knob("DSLASH_BLAS_NT");
+  r.wmarch_tile_y = read_knob("DSLASH_WMARCH_TILE_Y");
+  r.wmarch_tile_z = read_knob("DSLASH_WMARCH_TILE_Z");
   return r;
 }
 inline Knobs& knob_store() {

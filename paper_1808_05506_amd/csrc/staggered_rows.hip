@@ -14,6 +14,7 @@
 
 #include "launch.hpp"
 #include "rows.hpp"
+#include "tiles.hpp"
 
 namespace dsl {
 
@@ -480,31 +481,6 @@ size_t smarch_lds_words(int R) {
 // Waves per SIMD: FP32 four (about 100 VGPRs), FP64 two.
 template <class S> struct SMarchWaves { static constexpr int value = sizeof(typename S::word) == 16 ? 2 : 4; };
 
-// Workgroup order in tiles of by x bz (y, z) rows, every t segment of a tile
-// before the next tile.  With eight tiles each XCD takes one whole tile (the
-// XCD mapping deals contiguous eighths of the order), and its workgroups walk
-// the tile's rows segment by segment, so the +-y and +-z rows a workgroup
-// stages were mostly just staged by its neighbours on the same XCD.  On 32^4
-// (N_v = 12, FP32) 8 x 16 tiles read 1.11 GB per launch instead of 1.55 GB,
-// and ran 286.6 against 296.6 us (N_v = 4: 138.6 / 142.9, N_v = 8: 203.6 /
-// 210.7, N_v = 24: 521.8 / 528.4, FP64 N_v = 12: 511.1 / 526.2 us).
-struct MarchTiles {
-  uint32_t on, chunks, by, bz, tiles_y, nseg;
-};
-
-DSL_HD uint32_t march_tile_id(const Geom& g, const MarchTiles& o, uint32_t L, uint32_t& seg) {
-  const uint32_t per_row = o.chunks * o.by, per_seg = per_row * o.bz, per_tile = per_seg * o.nseg;
-  const uint32_t tile = L / per_tile;
-  uint32_t r = L - tile * per_tile;
-  seg = r / per_seg;
-  r -= seg * per_seg;
-  const uint32_t zz = r / per_row;
-  r -= zz * per_row;
-  const uint32_t yy = r / o.chunks, chunk = r - yy * o.chunks;
-  const uint32_t tz = tile / o.tiles_y, ty = tile - tz * o.tiles_y;
-  return ((tz * o.bz + zz) * uint32_t(g.n[1]) + ty * o.by + yy) * o.chunks + chunk;
-}
-
 template <int DEPTH, bool ADJ, int NV, class S, class T, int LW>
 __global__ void __launch_bounds__(256, SMarchWaves<S>::value)
     staggered_march_kernel(Geom g, MarchTraversal m, MarchTiles o, int xcd, const typename S::word* __restrict__ U,
@@ -522,13 +498,8 @@ __global__ void __launch_bounds__(256, SMarchWaves<S>::value)
   W* lnbb = lnba + R * LW;
 
   const uint32_t L = xcd_block(blockIdx.x, gridDim.x, xcd != 0);
-  uint32_t seg, id;
-  if (o.on) {
-    id = march_tile_id(g, o, L, seg);
-  } else {
-    seg = m.d_rows.div(L);
-    id = L - seg * m.rows;
-  }
+  uint32_t seg;
+  const uint32_t id = march_order_id(g, m, o, L, seg);
   const int t0 = int(seg * m.T);
   const int steps = g.n[3] - t0 < int(m.T) ? g.n[3] - t0 : int(m.T);
   RowChunk c = march_chunk(g, m, id, t0);
@@ -563,22 +534,6 @@ __global__ void __launch_bounds__(256, SMarchWaves<S>::value)
   }
 }
 
-// Eight tiles, the squarest with by <= bz (8 x 16 on 32^4); by = bz = 0 when
-// Ny x Nz has no such split.
-static void march_tile_default(const Geom& g, int& by, int& bz) {
-  by = bz = 0;
-  for (int y = 1; y <= g.n[1]; ++y) {
-    if (g.n[1] % y) continue;
-    for (int z = y; z <= g.n[2]; ++z) {
-      if (g.n[2] % z || (g.n[1] / y) * (g.n[2] / z) != 8) continue;
-      if (by == 0 || z - y < bz - by) {
-        by = y;
-        bz = z;
-      }
-    }
-  }
-}
-
 template <int DEPTH, int NV, class S, class T, int LW>
 static hipError_t staggered_march_t(bool adj, const Geom& g, int R, int tsteps, bool xcd, const void* U,
                                     const void* in, void* out, double mass, hipStream_t st) {
@@ -588,17 +543,9 @@ static hipError_t staggered_march_t(bool adj, const Geom& g, int R, int tsteps, 
   const dim3 block(NV, R), grid(m.rows * nseg);
   size_t lds = smarch_lds_words<NV, S, LW>(R) * sizeof(W);
   lds += size_t(knobs().row_lds_extra.get(0));
-  MarchTiles o{};
   int by, bz;
   march_tile_default(g, by, bz);
-  o.by = uint32_t(knobs().march_tile_y.get(by));
-  o.bz = uint32_t(knobs().march_tile_z.get(bz));
-  if (o.by > 0 && o.bz > 0 && g.n[1] % int(o.by) == 0 && g.n[2] % int(o.bz) == 0) {
-    o.on = 1;
-    o.chunks = m.chunks;
-    o.tiles_y = uint32_t(g.n[1]) / o.by;
-    o.nseg = nseg;
-  }
+  const MarchTiles o = make_march_tiles(g, m.chunks, nseg, knobs().march_tile_y.get(by), knobs().march_tile_z.get(bz));
   if (adj)
     hipLaunchKernelGGL((staggered_march_kernel<DEPTH, true, NV, S, T, LW>), grid, block, lds, st, g, m, o, int(xcd),
                        (const W*)U, (const W*)in, (W*)out, T(mass));

@@ -75,4 +75,69 @@ DSL_HD RowChunk order_chunk(const Geom& g, const RowTraversal& tr, const ChunkTi
   return o.on ? tile_chunk(g, o, tr.sb, L) : row_chunk(g, tr, L);
 }
 
+// Workgroup order in tiles of by x bz (y, z) rows, every t segment of a tile
+// before the next tile.  With eight tiles each XCD takes one whole tile (the
+// XCD mapping deals contiguous eighths of the order), and its workgroups walk
+// the tile's rows segment by segment, so the +-y and +-z rows a workgroup
+// stages were mostly just staged by its neighbours on the same XCD.  The D_S
+// march on 32^4 (N_v = 12, FP32) in 8 x 16 tiles read 1.11 GB per launch
+// instead of 1.55 GB, and ran 286.6 against 296.6 us (N_v = 4: 138.6 / 142.9,
+// N_v = 8: 203.6 / 210.7, N_v = 24: 521.8 / 528.4, FP64 N_v = 12: 511.1 /
+// 526.2 us).
+struct MarchTiles {
+  uint32_t on, chunks, by, bz, tiles_y, nseg;
+};
+
+// by | Ny and bz | Nz, both > 0, else the tiles are off (plane order).
+inline MarchTiles make_march_tiles(const Geom& g, uint32_t chunks, uint32_t nseg, int by, int bz) {
+  MarchTiles o{};
+  if (by > 0 && bz > 0 && g.n[1] % by == 0 && g.n[2] % bz == 0) {
+    o.on = 1;
+    o.chunks = chunks;
+    o.by = uint32_t(by);
+    o.bz = uint32_t(bz);
+    o.tiles_y = uint32_t(g.n[1] / by);
+    o.nseg = nseg;
+  }
+  return o;
+}
+
+DSL_HD uint32_t march_tile_id(const Geom& g, const MarchTiles& o, uint32_t L, uint32_t& seg) {
+  const uint32_t per_row = o.chunks * o.by, per_seg = per_row * o.bz, per_tile = per_seg * o.nseg;
+  const uint32_t tile = L / per_tile;
+  uint32_t r = L - tile * per_tile;
+  seg = r / per_seg;
+  r -= seg * per_seg;
+  const uint32_t zz = r / per_row;
+  r -= zz * per_row;
+  const uint32_t yy = r / o.chunks, chunk = r - yy * o.chunks;
+  const uint32_t tz = tile / o.tiles_y, ty = tile - tz * o.tiles_y;
+  return ((tz * o.bz + zz) * uint32_t(g.n[1]) + ty * o.by + yy) * o.chunks + chunk;
+}
+
+// Segment and chunk id of logical block L: tiled order when o.on, else plane
+// order (segment-major).
+DSL_HD uint32_t march_order_id(const Geom& g, const MarchTraversal& m, const MarchTiles& o, uint32_t L,
+                               uint32_t& seg) {
+  if (o.on) return march_tile_id(g, o, L, seg);
+  seg = m.d_rows.div(L);
+  return L - seg * m.rows;
+}
+
+// Eight tiles, the squarest with by <= bz (8 x 16 on 32^4); by = bz = 0 when
+// Ny x Nz has no such split.
+inline void march_tile_default(const Geom& g, int& by, int& bz) {
+  by = bz = 0;
+  for (int y = 1; y <= g.n[1]; ++y) {
+    if (g.n[1] % y) continue;
+    for (int z = y; z <= g.n[2]; ++z) {
+      if (g.n[2] % z || (g.n[1] / y) * (g.n[2] / z) != 8) continue;
+      if (by == 0 || z - y < bz - by) {
+        by = y;
+        bz = z;
+      }
+    }
+  }
+}
+
 }  // namespace dsl

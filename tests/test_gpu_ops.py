@@ -466,3 +466,25 @@ def test_brillouin_tile_orders(dt, monkeypatch):
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
     compare(outs[0].numpy().astype(np.complex128), brillouin.apply(w, p, 0.1), dt, "D_B tile orders")
+
+
+@pytest.mark.parametrize("dt", ["c64", "bf16"])
+def test_wilson_march_tile_orders(dt, monkeypatch):
+    # the D_W march's workgroups in (y, z) tiles (the default when the grid
+    # runs in several rounds; forced here), other tiles and the plane order:
+    # the same arithmetic per workgroup, so the same bits; 4-step segments
+    # with a short last one
+    dims, nv = (16, 4, 6, 10), 12
+    u, p = _wil_fields(dims, nv, 97, 98, dt)
+    U, P = up(u, dt), up(p, dt)
+    set_knob(monkeypatch, "DSLASH_ROWS", "2")
+    set_knob(monkeypatch, "DSLASH_TSTEPS", "4")
+    outs = []
+    for by, bz in (("0", "0"), ("2", "3"), ("4", "2"), ("1", "1"), ("1", "3")):
+        set_knob(monkeypatch, "DSLASH_WMARCH_TILE_Y", by)
+        set_knob(monkeypatch, "DSLASH_WMARCH_TILE_Z", bz)
+        say(f"case wilson march tile {by} x {bz} {dt}")
+        outs.append(D.apply("wilson", U, P, 0.1).cpu())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    compare(down(outs[0]), wilson.apply(u, p, 0.1), dt, "D_W march tile orders")
